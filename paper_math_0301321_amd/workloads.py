@@ -1,0 +1,299 @@
+"""Seeded synthetic workloads for the immersed-boundary time step.
+
+This module is the model generator: it builds marker positions, lattice
+topology, material weights and drive patterns, the way the paper's separate
+model-generation software writes geometry and material files before the
+solver starts (Sec. 3.3, Sec. 4).  It holds none of the time step's
+arithmetic (no force law, no delta function, no fluid solve), so both the
+GPU library and the CPU oracle can consume its output.
+
+Geometry stands in for the measured cochlea (Sec. 4), which is not available:
+a tapered helicoidal strip (the basilar membrane, BM) inside a coiled tube
+wall, in the paper's proportions (1 unit = 1 cm; BM about 3.5 cm long, its
+width growing from 150 um to 560 um).  The window is a patch of the wall
+near the base that carries a sinusoidal force along the outward wall normal
+(Sec. 4, oval-window drive).
+
+Units are CGS: rho = 1, mu = 0.01 for every workload.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+
+@dataclass
+class Lattice:
+    """A rectangular material lattice Q (Sec. 3.2): markers first + i2*n1 + i1.
+
+    i1 runs along direction 1 (0..n1-1, fastest), i2 along direction 2
+    (0..n2-1, periodic when ``periodic2``).  ``Ks``/``Kb`` are the stretch and
+    bend moduli applied to every lattice edge / triple.
+    """
+    first: int
+    n1: int
+    n2: int
+    periodic2: bool
+    Ks: float
+    Kb: float
+
+
+@dataclass
+class Workload:
+    name: str
+    N: int                 # grid points per dimension (periodic cube)
+    L: float               # box edge; h = L / N
+    rho: float
+    mu: float
+    dt: float
+    n_steps: int
+    convect: int           # 1: upwind advection term on; 0: Stokes (linear) step
+    X0: np.ndarray         # (3, M) float64 initial marker positions
+    w: np.ndarray          # (M,) area weight (Delta q) per marker
+    k: np.ndarray          # (M,) stiffness multiplier per marker
+    X_ref: np.ndarray      # (3, M) reference shape: tether targets, rest geometry
+    kappa: np.ndarray      # (M,) tether stiffness density (0 = untethered)
+    lattices: list = field(default_factory=list)
+    spring_ab: np.ndarray = None      # (2, S) int32 marker pairs
+    spring_rest: np.ndarray = None    # (S,) float64 rest lengths
+    K_spring: float = 0.0
+    drive_idx: np.ndarray = None      # (D,) int32 driven markers
+    drive_dir: np.ndarray = None      # (3, D) float64 unit directions
+    drive_A: float = 0.0
+    drive_freq: float = 0.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def M(self) -> int:
+        return int(self.X0.shape[1])
+
+    @property
+    def h(self) -> float:
+        return self.L / self.N
+
+    def with_grid(self, N: int) -> "Workload":
+        """Same markers and time step on another grid size (a replica)."""
+        import copy
+        wl = copy.copy(self)
+        wl.N = int(N)
+        wl.name = f"{self.name}@{N}^3"
+        return wl
+
+
+def _empty_int(shape):
+    return np.zeros(shape, dtype=np.int32)
+
+
+# --------------------------------------------------------------------------
+# closed spherical shell (icosphere)
+# --------------------------------------------------------------------------
+def icosphere(subdiv: int):
+    """Vertices (V,3) on the unit sphere and faces (F,3) of a subdivided icosahedron."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    verts = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0),
+             (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+             (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    verts = [np.array(v, dtype=np.float64) / np.linalg.norm(v) for v in verts]
+    faces = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11),
+             (1, 5, 9), (5, 11, 4), (11, 10, 2), (10, 7, 6), (7, 1, 8),
+             (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9),
+             (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(subdiv):
+        cache = {}
+
+        def mid(a, b):
+            key = (a, b) if a < b else (b, a)
+            if key not in cache:
+                m = verts[a] + verts[b]
+                verts.append(m / np.linalg.norm(m))
+                cache[key] = len(verts) - 1
+            return cache[key]
+
+        nf = []
+        for a, b, c in faces:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = nf
+    return np.array(verts), np.array(faces, dtype=np.int64)
+
+
+def _edges_from_faces(faces):
+    e = np.concatenate([faces[:, [0, 1]], faces[:, [1, 2]], faces[:, [2, 0]]])
+    e.sort(axis=1)
+    return np.unique(e, axis=0)
+
+
+def config1(N: int = 32) -> Workload:
+    """Closed spherical shell of Hookean springs, stretched 10% along x, fluid at rest.
+
+    Periodic 32^3 grid on the unit cube, rho = 1, mu = 0.01, dt = 1e-3,
+    10 steps; icosphere subdivision 4 (2,562 markers, 7,680 edges), radius
+    0.25 about the cube centre; spring stiffness 1e3, rest length equal to the
+    unstretched edge length.
+    """
+    v, f = icosphere(4)
+    R, c = 0.25, 0.5
+    rest_pos = (c + R * v).T.copy()                     # (3, M) unstretched
+    X0 = rest_pos.copy()
+    X0[0] = c + 1.1 * (X0[0] - c)                      # 10% stretch along x
+    edges = _edges_from_faces(f)
+    rest = np.linalg.norm(rest_pos[:, edges[:, 1]] - rest_pos[:, edges[:, 0]], axis=0)
+    M = X0.shape[1]
+    area = 4.0 * math.pi * R * R / M
+    return Workload(
+        name="shell32", N=N, L=1.0, rho=1.0, mu=0.01, dt=1e-3, n_steps=10, convect=1,
+        X0=X0, w=np.full(M, area), k=np.ones(M), X_ref=rest_pos, kappa=np.zeros(M),
+        lattices=[], spring_ab=np.ascontiguousarray(edges.T.astype(np.int32)),
+        spring_rest=rest, K_spring=1e3,
+        drive_idx=_empty_int(0), drive_dir=np.zeros((3, 0)), drive_A=0.0, drive_freq=0.0,
+        meta={"faces": f})
+
+
+# --------------------------------------------------------------------------
+# helicoidal membrane in a coiled tube
+# --------------------------------------------------------------------------
+_TURNS = 2.5
+
+
+def _centre(s):
+    th = 2.0 * math.pi * _TURNS * s
+    R = 0.30 - 0.18 * s
+    C = np.stack([0.5 + R * np.cos(th), 0.5 + R * np.sin(th), 0.20 + 0.60 * s])
+    dth = 2.0 * math.pi * _TURNS
+    dC = np.stack([-0.18 * np.cos(th) - R * dth * np.sin(th),
+                   -0.18 * np.sin(th) + R * dth * np.cos(th),
+                   np.full_like(s, 0.60)])
+    er = np.stack([np.cos(th), np.sin(th), np.zeros_like(s)])
+    return C, dC, er
+
+
+def helicoid_in_tube(nb1, nb2, nw1, nw2, win1, win2, *, N, dt, n_steps, freq,
+                     Ks=50.0, Kb=3e-4, kappa=1e5, drive_A=1e2, jitter_seed=None,
+                     convect=1, name="helix") -> Workload:
+    """Tapered helicoidal strip ('BM', nb1 x nb2) inside a coiled tube wall (nw1 x nw2).
+
+    BM centre line C(s) = (1/2 + R cos th, 1/2 + R sin th, 0.2 + 0.6 s), th = 5 pi s
+    (2.5 turns), R = 0.30 - 0.18 s; the strip spans +-b(s)/2 along the radial
+    direction, b = 0.015 + 0.041 s.  BM stretch/bend stiffness multiplier
+    k = exp(-3 s) (times 1 + 0.05 U(-1,1) when ``jitter_seed`` is given); its two
+    long edges are tethered.  The wall is a tube of radius a = 0.10 - 0.04 s
+    around C(s), every marker tethered to its initial position.  The window
+    patch (wall i1 < win1, i2 < win2) is driven along the outward normal.
+    """
+    # ---- basilar membrane lattice: index = i2 * nb1 + i1 ----
+    s = np.linspace(0.0, 1.0, nb1)
+    C, dC, er = _centre(s)
+    b = 0.015 + 0.041 * s
+    eta = np.linspace(-0.5, 0.5, nb2)
+    BM = C[:, None, :] + eta[None, :, None] * (b * er)[:, None, :]      # (3, nb2, nb1)
+    ds_len = np.linalg.norm(dC, axis=0) / (nb1 - 1)
+    w_bm = np.broadcast_to(ds_len * b / (nb2 - 1), (nb2, nb1))
+    k_bm = np.broadcast_to(np.exp(-3.0 * s), (nb2, nb1)).copy()
+    if jitter_seed is not None:
+        rng = np.random.default_rng(jitter_seed)
+        k_bm *= 1.0 + 0.05 * rng.uniform(-1.0, 1.0, size=k_bm.shape)
+    kap_bm = np.zeros((nb2, nb1))
+    kap_bm[0, :] = kappa
+    kap_bm[-1, :] = kappa
+    s_bm = np.broadcast_to(s, (nb2, nb1))
+
+    # ---- tube wall lattice (periodic around): index = M_bm + i2 * nw1 + i1 ----
+    sw = np.linspace(0.0, 1.0, nw1)
+    Cw, dCw, erw = _centre(sw)
+    t = dCw / np.linalg.norm(dCw, axis=0)
+    n1 = erw - (erw * t).sum(0) * t
+    n1 /= np.linalg.norm(n1, axis=0)
+    n2 = np.cross(t.T, n1.T).T
+    a = 0.10 - 0.04 * sw
+    ph = 2.0 * math.pi * np.arange(nw2) / nw2
+    nrm = (np.cos(ph)[:, None, None] * n1.T[None, :, :]
+           + np.sin(ph)[:, None, None] * n2.T[None, :, :])                 # (nw2, nw1, 3)
+    WALL = (Cw.T[None, :, :] + a[None, :, None] * nrm).transpose(2, 0, 1)   # (3, nw2, nw1)
+    dsw_len = np.linalg.norm(dCw, axis=0) / (nw1 - 1)
+    w_w = np.broadcast_to(dsw_len * 2.0 * math.pi * a / nw2, (nw2, nw1))
+
+    M_bm, M_w = nb1 * nb2, nw1 * nw2
+    X0 = np.concatenate([BM.reshape(3, M_bm), WALL.reshape(3, M_w)], axis=1)
+    X0 = np.ascontiguousarray(X0)
+    w = np.concatenate([w_bm.reshape(-1), w_w.reshape(-1)])
+    k = np.concatenate([k_bm.reshape(-1), np.ones(M_w)])
+    kap = np.concatenate([kap_bm.reshape(-1), np.full(M_w, kappa)])
+
+    i2w, i1w = np.meshgrid(np.arange(win2), np.arange(win1), indexing="ij")
+    didx = (M_bm + i2w * nw1 + i1w).reshape(-1).astype(np.int32)
+    ddir = nrm[i2w.reshape(-1), i1w.reshape(-1), :].T.copy()
+
+    lattices = [Lattice(0, nb1, nb2, False, Ks, Kb), Lattice(M_bm, nw1, nw2, True, 0.0, 0.0)]
+    meta = {"bm_first": 0, "bm_n1": nb1, "bm_n2": nb2, "wall_first": M_bm,
+            "wall_n1": nw1, "wall_n2": nw2, "s_bm": s_bm.reshape(-1).copy()}
+    return Workload(
+        name=name, N=N, L=1.0, rho=1.0, mu=0.01, dt=dt, n_steps=n_steps, convect=convect,
+        X0=X0, w=np.ascontiguousarray(w), k=np.ascontiguousarray(k), X_ref=X0.copy(),
+        kappa=np.ascontiguousarray(kap), lattices=lattices,
+        spring_ab=np.zeros((2, 0), np.int32), spring_rest=np.zeros(0), K_spring=0.0,
+        drive_idx=didx, drive_dir=np.ascontiguousarray(ddir), drive_A=drive_A,
+        drive_freq=float(freq), meta=meta)
+
+
+def config2(N: int = 128) -> Workload:
+    """128^3 grid; BM 800 x 250 (200k) + wall 1000 x 300 (300k); window 20 x 100; 1 kHz; dt 5e-5 x 200."""
+    return helicoid_in_tube(800, 250, 1000, 300, 20, 100, N=N, dt=5e-5, n_steps=200,
+                            freq=1000.0, name="helix128")
+
+
+C3_FREQS = (200.0, 500.0, 1000.0, 1500.0)
+
+
+def config3(N: int = 256, freq: float = C3_FREQS[2]) -> Workload:
+    """256^3 grid; BM 1200 x 500 (600k) + wall 1800 x 500 (900k) = 1.5M markers; +-5% k jitter (seed 0)."""
+    return helicoid_in_tube(1200, 500, 1800, 500, 36, 167, N=N, dt=2.5e-5, n_steps=500,
+                            freq=freq, jitter_seed=0, name="helix256")
+
+
+def loss_window(wl: Workload, lo: int = 238, hi: int = 241) -> np.ndarray:
+    """BM markers at stations i1 in [lo, hi] across the full width (1,000 markers at 800 x 250)."""
+    n1, n2 = wl.meta["bm_n1"], wl.meta["bm_n2"]
+    i2, i1 = np.meshgrid(np.arange(n2), np.arange(lo, hi + 1), indexing="ij")
+    return (wl.meta["bm_first"] + i2 * n1 + i1).reshape(-1).astype(np.int64)
+
+
+def config4(N: int = 128) -> Workload:
+    """Adjoint workload: helix128 geometry, Stokes step (convect = 0), 50 steps, checkpoint every 10."""
+    wl = config2(N)
+    wl.name, wl.n_steps, wl.convect = "adjoint128", 50, 0
+    wl.meta["ckpt"] = 10
+    wl.meta["loss_idx"] = loss_window(wl)
+    return wl
+
+
+def config5(N: int = 256) -> Workload:
+    """Adjoint at scale: helix256 geometry, 100 steps, checkpoint every 20 (64^3 replica: config5(64))."""
+    wl = config3(N)
+    wl.name, wl.n_steps, wl.convect = f"adjoint{N}", 100, 0
+    wl.meta["ckpt"] = 20
+    wl.meta["loss_idx"] = loss_window(wl, 357, 359)
+    return wl
+
+
+def tiny_helix(N: int = 32, nb=(60, 12), nw=(80, 24), dt=2e-4, n_steps=10) -> Workload:
+    """A scaled-down helix for fast parity tests (same structure, few markers)."""
+    return helicoid_in_tube(nb[0], nb[1], nw[0], nw[1], 4, 6, N=N, dt=dt, n_steps=n_steps,
+                            freq=1000.0, jitter_seed=0, name=f"helix_tiny{N}")
+
+
+def random_markers(M: int, seed: int = 2, lo: float = 0.0, hi: float = 1.0):
+    """Uniform random marker positions and forces (seed 2 is used for test fields)."""
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(lo, hi, size=(3, M))
+    F = rng.standard_normal((3, M))
+    return X, F
+
+
+def random_field(N: int, seed: int = 2, comps: int = 3):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((comps, N, N, N))
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}

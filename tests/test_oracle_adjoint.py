@@ -1,0 +1,98 @@
+"""Pins of the oracle's adjoint step against the (pinned) forward step, on the CPU.
+
+The adjoint of one Stokes step (convect = 0) must be the transpose of its
+linearisation: for any tangent (dX, du, dk) and cotangent (Xbar', ubar'),
+<J (dX, du, dk), (Xbar', ubar')> = <(dX, du, dk), J^T (Xbar', ubar')>.
+J is taken by central differences of the forward oracle.  A multi-step
+gradient of a membrane-displacement loss is checked against finite
+differences of the same loss.
+"""
+import numpy as np
+
+from paper_math_0301321_amd import workloads as W
+
+
+def _setup(N=16):
+    wl = W.tiny_helix(N=N)
+    wl.convect = 0
+    rng = np.random.default_rng(31)
+    X = wl.X0 + 2e-3 * rng.standard_normal(wl.X0.shape)
+    u = 0.05 * W.random_field(N, seed=32)
+    return wl, X, u, rng
+
+
+def test_adjoint_step_is_transpose_of_linearised_step(oracle_mod):
+    wl, X, u, rng = _setup()
+    t = 3e-4
+    dX = rng.standard_normal(X.shape)
+    du = rng.standard_normal(u.shape)
+    dk = rng.standard_normal(wl.M)
+    Xb1 = rng.standard_normal(X.shape)
+    ub1 = rng.standard_normal(u.shape)
+
+    def fwd(e):
+        m = oracle_mod.Model(wl, wl.k + e * dk)
+        return oracle_mod.step(m, wl, X + e * dX, u + e * du, t, convect=0)
+
+    eps = 1e-6
+    Xp, up = fwd(eps)
+    Xm, um = fwd(-eps)
+    jX, ju = (Xp - Xm) / (2 * eps), (up - um) / (2 * eps)
+    lhs = (jX * Xb1).sum() + (ju * ub1).sum()
+
+    m = oracle_mod.Model(wl)
+    _, u1 = oracle_mod.step(m, wl, X, u, t, convect=0)
+    Xb, ub, kb = oracle_mod.adjoint_step(m, wl, X, u1, t, Xb1, ub1, np.zeros(wl.M))
+    rhs = (dX * Xb).sum() + (du * ub).sum() + (dk * kb).sum()
+    assert abs(lhs - rhs) <= 1e-6 * abs(rhs), (lhs, rhs)
+
+    # each part separately (dX only, du only, dk only) so no error can cancel
+    for part in ("X", "u", "k"):
+        sX = dX if part == "X" else 0 * dX
+        su = du if part == "u" else 0 * du
+        sk = dk if part == "k" else 0 * dk
+
+        def f2(e):
+            mm = oracle_mod.Model(wl, wl.k + e * sk)
+            return oracle_mod.step(mm, wl, X + e * sX, u + e * su, t, convect=0)
+
+        a, b = f2(eps), f2(-eps)
+        l2 = (((a[0] - b[0]) * Xb1).sum() + ((a[1] - b[1]) * ub1).sum()) / (2 * eps)
+        r2 = (sX * Xb).sum() + (su * ub).sum() + (sk * kb).sum()
+        assert abs(l2 - r2) <= 2e-6 * max(abs(r2), 1e-30) + 1e-9 * abs(rhs), (part, l2, r2)
+
+
+def test_multistep_gradient_vs_finite_differences(oracle_mod):
+    wl, X0, _, rng = _setup()
+    n = 4
+    W_idx = np.arange(wl.meta["bm_n1"] * 3, wl.meta["bm_n1"] * 3 + 20)
+
+    def loss(k):
+        X, u = oracle_mod.run(wl, n, X=X0, k=k, convect=0)
+        d = X[:, W_idx] - X0[:, W_idx]
+        return (d ** 2).sum() / len(W_idx)
+
+    # forward with stored states, then reverse
+    m = oracle_mod.Model(wl)
+    Xs, us = [X0.copy()], [np.zeros((3, wl.N, wl.N, wl.N))]
+    for s in range(n):
+        Xn, un = oracle_mod.step(m, wl, Xs[-1], us[-1], s * wl.dt, convect=0)
+        Xs.append(Xn)
+        us.append(un)
+    Xb = np.zeros_like(X0)
+    Xb[:, W_idx] = 2.0 * (Xs[-1][:, W_idx] - X0[:, W_idx]) / len(W_idx)
+    ub = np.zeros_like(us[0])
+    kb = np.zeros(wl.M)
+    for s in reversed(range(n)):
+        Xb, ub, kb = oracle_mod.adjoint_step(m, wl, Xs[s], us[s + 1], s * wl.dt, Xb, ub, kb)
+
+    bm = np.arange(wl.meta["bm_n1"] * wl.meta["bm_n2"])
+    near = bm[np.abs(bm % wl.meta["bm_n1"] - 10) <= 3]          # stations around the loss window
+    pick = np.concatenate([rng.choice(near, size=6, replace=False), rng.choice(bm, size=4, replace=False)])
+    for i in pick:
+        e = 1e-5 * wl.k[i]
+        kp, km = wl.k.copy(), wl.k.copy()
+        kp[i] += e
+        km[i] -= e
+        g_fd = (loss(kp) - loss(km)) / (2 * e)
+        assert abs(kb[i] - g_fd) <= 1e-4 * max(abs(g_fd), 1e-3 * np.abs(kb).max()), (i, kb[i], g_fd)

@@ -1,0 +1,375 @@
+"""Pins of the oracle against what the paper and the mathematics fix (CPU only).
+
+Each test checks the oracle against something other than itself: closed-form
+values, identities the 4-point function satisfies, brute force on tiny
+inputs, a library routine for a special case, or an invariant of the
+discrete equations of Sec. 3.2.  A plausible slip in the oracle (a dropped
+term, a wrong sign or index, a transposed operand) fails at least one.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_math_0301321_amd import workloads as W
+
+
+# --------------------------------------------------------------------------
+# phi (Sec. 3.2, definition of delta_h)
+# --------------------------------------------------------------------------
+def test_phi_closed_form_values(oracle_mod):
+    s2 = math.sqrt(2.0)
+    r = np.array([0.0, 0.5, 1.0, 1.5, 2.0, 2.5, -0.5, -1.5, 3.0])
+    want = np.array([0.5, (2 + s2) / 8, 0.25, (2 - s2) / 8, 0.0, 0.0, (2 + s2) / 8, (2 - s2) / 8, 0.0])
+    np.testing.assert_allclose(oracle_mod.phi(r), want, rtol=0, atol=1e-16)
+
+
+def test_phi_is_c1(oracle_mod):
+    # phi'(0) = 0, phi'(+-1) = -+1/2, phi'(+-2) = 0 (one-sided differences on both sides agree)
+    e = 1e-6
+    for r0, slope in [(0.0, 0.0), (1.0, -0.5), (-1.0, 0.5), (2.0, 0.0), (-2.0, 0.0)]:
+        left = (oracle_mod.phi(r0) - oracle_mod.phi(r0 - e)) / e
+        right = (oracle_mod.phi(r0 + e) - oracle_mod.phi(r0)) / e
+        assert abs(left - slope) < 1e-5 and abs(right - slope) < 1e-5, (r0, left, right)
+
+
+def test_phi_moment_identities(oracle_mod):
+    r = np.linspace(0.0, 1.0, 100001)
+    j = np.arange(-3, 5)
+    P = oracle_mod.phi(r[:, None] - j[None, :])
+    even = (j % 2 == 0)
+    assert np.abs(P.sum(1) - 1.0).max() < 1e-15 * 8
+    assert np.abs(P[:, even].sum(1) - 0.5).max() < 1e-15 * 8
+    assert np.abs(P[:, ~even].sum(1) - 0.5).max() < 1e-15 * 8
+    assert np.abs((P * (r[:, None] - j[None, :])).sum(1)).max() < 1e-15 * 16
+    assert np.abs((P ** 2).sum(1) - 3.0 / 8.0).max() < 1e-15 * 8
+    # support |r| < 2
+    assert np.all(oracle_mod.phi(np.linspace(2.0, 5.0, 101)) == 0.0)
+
+
+# --------------------------------------------------------------------------
+# binning (the partition of Sec. 3.3): cell containment, order, stability
+# --------------------------------------------------------------------------
+def _brute_bin(N, L, X):
+    h = L / N
+    M = X.shape[1]
+    out = []
+    for q in range(M):
+        c = [int(math.floor(X[d, q] / h)) % N for d in range(3)]
+        out.append(((c[2] * N + c[1]) * N + c[0], q))
+    out.sort()
+    return np.array([o[0] for o in out], np.uint32), np.array([o[1] for o in out], np.int32)
+
+
+@pytest.mark.parametrize("N", [8, 32])
+def test_bin_brute_force_and_containment(oracle_mod, N):
+    rng = np.random.default_rng(5)
+    M = 3000
+    # many ties (markers sharing cells), positions outside [0, L) that must wrap
+    X = rng.integers(-N, 2 * N, size=(3, M)) / N + rng.choice([0.0, 0.25 / N, 0.5 / N], size=(3, M))
+    keys, perm = oracle_mod.bin_markers(N, 1.0, X)
+    bk, bp = _brute_bin(N, 1.0, X)
+    assert np.array_equal(keys, bk) and np.array_equal(perm, bp)
+    assert np.array_equal(np.sort(perm), np.arange(M))
+    h = 1.0 / N
+    c1, c2, c3 = keys % N, (keys // N) % N, keys // (N * N)
+    for d, c in enumerate((c1, c2, c3)):
+        xw = np.mod(X[d, perm], 1.0)
+        assert np.all(c * h <= xw + 1e-15) and np.all(xw < (c + 1) * h + 1e-15)
+    # stable: equal keys keep marker order
+    same = keys[1:] == keys[:-1]
+    assert np.all(perm[1:][same] > perm[:-1][same])
+
+
+# --------------------------------------------------------------------------
+# FFT: brute-force DFT on tiny inputs, numpy.fft on moderate ones
+# --------------------------------------------------------------------------
+def _brute_dft3(x, sign):
+    N = x.shape[0]
+    n = np.arange(N)
+    out = np.zeros_like(x, dtype=complex)
+    for a in range(N):
+        for b in range(N):
+            for c in range(N):
+                ph = np.exp(sign * 2j * np.pi * (a * n[:, None, None] + b * n[None, :, None] + c * n[None, None, :]) / N)
+                out[a, b, c] = (x * ph).sum()
+    return out
+
+
+@pytest.mark.parametrize("N", [4, 8])
+def test_fft_vs_brute_force(oracle_mod, N):
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((N, N, N)) + 1j * rng.standard_normal((N, N, N))
+    for sign in (-1, 1):
+        got = oracle_mod.fft3(x, sign)
+        want = _brute_dft3(x, sign)
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("N", [16, 64])
+def test_fft_vs_numpy(oracle_mod, N):
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((N, N, N)) + 1j * rng.standard_normal((N, N, N))
+    got = oracle_mod.fft3(x, -1)
+    want = np.fft.fftn(x)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+    back = oracle_mod.fft3(got, +1) / N ** 3
+    assert np.abs(back - x).max() <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# spreading and interpolation (eqs. discreteF, discreteX)
+# --------------------------------------------------------------------------
+def test_spread_total_force_and_first_moment(oracle_mod):
+    N, L = 16, 1.0
+    h = L / N
+    rng = np.random.default_rng(2)
+    M = 200
+    X = rng.uniform(0.3, 0.7, size=(3, M))     # away from the wrap
+    F = rng.standard_normal((3, M))
+    Fg = oracle_mod.spread(N, L, X, F)
+    tot = Fg.reshape(3, -1).sum(1) * h ** 3
+    np.testing.assert_allclose(tot, F.sum(1), rtol=1e-12, atol=1e-12)
+    z, y, x = np.meshgrid(np.arange(N) * h, np.arange(N) * h, np.arange(N) * h, indexing="ij")
+    pos = [x, y, z]
+    for d in range(3):
+        for c in range(3):
+            mom = (pos[d] * Fg[c]).sum() * h ** 3
+            assert abs(mom - (X[d] * F[c]).sum()) < 1e-12 * np.abs(F).sum()
+
+
+def test_spread_wraps_periodically(oracle_mod):
+    N, L = 8, 1.0
+    X = np.array([[0.01, 0.999], [0.5, 0.02], [0.98, 0.3]])
+    F = np.array([[1.0, -2.0], [0.5, 3.0], [2.0, 1.0]])
+    Fg = oracle_mod.spread(N, L, X, F)
+    np.testing.assert_allclose(Fg.reshape(3, -1).sum(1) / N ** 3, F.sum(1), rtol=1e-13)
+
+
+def test_spread_square_sum_and_node_weights(oracle_mod):
+    N, L = 16, 1.0
+    h = L / N
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        X = rng.uniform(0.2, 0.8, size=(3, 1))
+        Fg = oracle_mod.spread(N, L, X, np.array([[1.0], [0.0], [0.0]]))
+        assert abs(((Fg[0] * h ** 3) ** 2).sum() - (3.0 / 8.0) ** 3) < 1e-15
+    # marker on a node: separable weights [1/4, 1/2, 1/4]
+    X = np.array([[5 * h], [7 * h], [9 * h]])
+    Fg = oracle_mod.spread(N, L, X, np.array([[1.0], [1.0], [1.0]]))[0] * h ** 3
+    w = np.array([0.25, 0.5, 0.25])
+    want = np.zeros((N, N, N))
+    want[8:11, 6:9, 4:7] = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    np.testing.assert_allclose(Fg, want, rtol=0, atol=1e-16)
+
+
+def test_spread_interp_adjoint(oracle_mod):
+    N, L = 16, 1.0
+    h = L / N
+    X, F = W.random_markers(300, seed=2)
+    u = W.random_field(N, seed=2)
+    lhs = (oracle_mod.spread(N, L, X, F) * u).sum() * h ** 3
+    rhs = (F * oracle_mod.interp(N, L, X, u)).sum()
+    assert abs(lhs - rhs) < 1e-12 * abs(rhs) + 1e-12
+
+
+def test_interp_exact_for_constant_and_linear(oracle_mod):
+    N, L = 16, 1.0
+    h = L / N
+    rng = np.random.default_rng(4)
+    X = rng.uniform(0.3, 0.7, size=(3, 100))
+    z, y, x = np.meshgrid(np.arange(N) * h, np.arange(N) * h, np.arange(N) * h, indexing="ij")
+    u = np.stack([np.full((N, N, N), 1.5), 2.0 * x - 0.5 * y + 0.25 * z + 1.0, -3.0 * z])
+    U = oracle_mod.interp(N, L, X, u)
+    np.testing.assert_allclose(U[0], 1.5, rtol=1e-14)
+    np.testing.assert_allclose(U[1], 2.0 * X[0] - 0.5 * X[1] + 0.25 * X[2] + 1.0, rtol=1e-13)
+    np.testing.assert_allclose(U[2], -3.0 * X[2], rtol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# advection: upwind direction (eq. discreteNS1 and the upwind rule)
+# --------------------------------------------------------------------------
+def test_advection_upwind_direction(oracle_mod):
+    N, L = 8, 1.0
+    h = L / N
+    u = np.zeros((3, N, N, N))
+    step = (np.arange(N) >= 4).astype(float)          # u_y = 1 for x index >= 4
+    u[1] = step[None, None, :]
+    for c, where in [(0.5, 4), (-0.5, 3)]:
+        u[0] = c
+        A = oracle_mod.advect(N, L, u)
+        # only the x-difference of u_y survives; it is taken on the upwind side
+        nz = np.argwhere(np.abs(A[1, 0, 0, :]) > 0).ravel()
+        assert sorted(nz) == sorted([where, 0 if c > 0 else 7])
+        assert abs(A[1, 0, 0, where] - c / h) < 1e-12     # u_x times a unit jump over h
+        assert np.all(A[0] == 0.0) and np.all(A[2] == 0.0)
+    u[0] = 0.0
+    assert np.all(oracle_mod.advect(N, L, u) == 0.0)           # u_k = 0 -> no term
+
+
+# --------------------------------------------------------------------------
+# NS solve / projection (eqs. discreteNS1-2)
+# --------------------------------------------------------------------------
+def _div0(u, h):
+    return sum((np.roll(u[d], -1, axis=2 - d) - np.roll(u[d], 1, axis=2 - d)) / (2 * h) for d in range(3))
+
+
+def _grad0(p, h):
+    return np.stack([(np.roll(p, -1, axis=2 - d) - np.roll(p, 1, axis=2 - d)) / (2 * h) for d in range(3)])
+
+
+def test_solve_divergence_free_and_real(oracle_mod):
+    N, L = 16, 1.0
+    h = L / N
+    u = W.random_field(N, seed=2)
+    un, im = oracle_mod.fluid(N, L, 1.0, 0.01, 1e-3, 1, u, W.random_field(N, seed=9), return_imag=True)
+    assert np.abs(_div0(un, h)).max() <= 1e-12 * np.abs(un).max() / h
+    assert im < 1e-14
+
+
+def test_projection_properties(oracle_mod):
+    N, L = 16, 1.0
+    h = L / N
+    P = lambda v: oracle_mod.fluid(N, L, 1.0, 0.0, 1e-3, 0, v)
+    u = W.random_field(N, seed=2)
+    Pu = P(u)
+    assert np.abs(P(Pu) - Pu).max() < 1e-13 * np.abs(Pu).max()
+    grad = _grad0(W.random_field(N, seed=11, comps=1)[0], h)
+    assert np.abs(P(grad)).max() < 1e-13 * np.abs(grad).max()
+    # a D0-curl field is D0-divergence free and passes unchanged
+    psi = W.random_field(N, seed=12)
+    g = [_grad0(psi[i], h) for i in range(3)]
+    curl = np.stack([g[2][1] - g[1][2], g[0][2] - g[2][0], g[1][0] - g[0][1]])
+    assert np.abs(P(curl) - curl).max() < 1e-12 * np.abs(curl).max()
+    # symmetric: <P a, b> = <a, P b>
+    b = W.random_field(N, seed=13)
+    assert abs((Pu * b).sum() - (u * P(b)).sum()) < 1e-11 * abs((Pu * b).sum())
+
+
+def test_single_fourier_mode_decay(oracle_mod):
+    # u_x = sin(2 pi m y), no force: advection vanishes exactly, u^n = g^n u^0
+    N, L, rho, mu, dt, m, n = 32, 1.0, 1.0, 0.01, 1e-3, 1, 10
+    h = L / N
+    y = np.arange(N) * h
+    u = np.zeros((3, N, N, N))
+    u[0] = np.sin(2 * np.pi * m * y)[None, :, None]
+    u0 = u.copy()
+    for _ in range(n):
+        u = oracle_mod.fluid(N, L, rho, mu, dt, 1, u)
+    g = 1.0 / (1.0 + (mu * dt / rho) * (4.0 / h ** 2) * np.sin(np.pi * m / N) ** 2)
+    np.testing.assert_allclose(u, g ** n * u0, rtol=0, atol=1e-14)
+    assert abs(g ** n - 0.996073) < 1e-6
+    # continuum exp(-nu k^2 t), k = 2 pi m: agreement to O(h^2) + O(dt)
+    assert abs(g ** n / math.exp(-(mu / rho) * (2 * math.pi * m) ** 2 * n * dt) - 1.0) < 2e-5
+
+
+# --------------------------------------------------------------------------
+# material force (sub-step 1): gradient of the energy, invariances, linearity
+# --------------------------------------------------------------------------
+def _fd_grad(oracle_mod, model, X, idx, eps=1e-7):
+    g = np.zeros((3, len(idx)))
+    for j, q in enumerate(idx):
+        for d in range(3):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[d, q] += eps
+            Xm[d, q] -= eps
+            g[d, j] = (oracle_mod.energy(model, Xp) - oracle_mod.energy(model, Xm)) / (2 * eps)
+    return g
+
+
+def _perturbed_helix():
+    wl = W.tiny_helix()
+    rng = np.random.default_rng(21)
+    X = wl.X0 + 1e-3 * rng.standard_normal(wl.X0.shape)
+    return wl, X
+
+
+def test_force_is_minus_energy_gradient(oracle_mod):
+    wl, X = _perturbed_helix()
+    wl.drive_A = 0.0
+    model = oracle_mod.Model(wl)
+    F = oracle_mod.force(model, X, 0.0)
+    idx = [0, 5, 61, 300, 719, wl.meta["wall_first"] + 3, wl.M - 1]
+    g = _fd_grad(oracle_mod, model, X, idx)
+    np.testing.assert_allclose(F[:, idx], -g, rtol=1e-5, atol=1e-6 * np.abs(F).max())
+    wl1 = W.config1(16)
+    m1 = oracle_mod.Model(wl1)
+    F1 = oracle_mod.force(m1, wl1.X0, 0.0)
+    g1 = _fd_grad(oracle_mod, m1, wl1.X0, [0, 17, 2561])
+    np.testing.assert_allclose(F1[:, [0, 17, 2561]], -g1, rtol=1e-5, atol=1e-6 * np.abs(F1).max())
+
+
+def test_force_translation_rotation_invariance(oracle_mod):
+    # springs / stretch only: total force and torque vanish; bend: total force vanishes
+    wl1 = W.config1(16)
+    F = oracle_mod.force(oracle_mod.Model(wl1), wl1.X0, 0.0)
+    assert np.abs(F.sum(1)).max() < 1e-11 * np.abs(F).max()
+    torque = np.cross(wl1.X0.T, F.T).sum(0)
+    assert np.abs(torque).max() < 1e-11 * np.abs(F).max()
+    wl, X = _perturbed_helix()
+    wl.kappa[:] = 0.0
+    wl.drive_A = 0.0
+    wl.lattices[0].Kb = 0.0
+    F = oracle_mod.force(oracle_mod.Model(wl), X, 0.0)
+    assert np.abs(F.sum(1)).max() < 1e-11 * np.abs(F).sum()
+    assert np.abs(np.cross(X.T, F.T).sum(0)).max() < 1e-11 * np.abs(F).sum()
+    wl.lattices[0].Kb, wl.lattices[0].Ks = 3e-4, 0.0
+    F = oracle_mod.force(oracle_mod.Model(wl), X, 0.0)
+    assert np.abs(F.sum(1)).max() < 1e-11 * np.abs(F).sum()
+
+
+def test_force_tether_drive_closed_form_and_k_linearity(oracle_mod):
+    wl, X = _perturbed_helix()
+    for l in wl.lattices:
+        l.Ks = l.Kb = 0.0
+    t = 3.7e-4
+    F = oracle_mod.force(oracle_mod.Model(wl), X, t)
+    want = -(wl.kappa * wl.w) * (X - wl.X_ref)
+    want[:, wl.drive_idx] += wl.drive_A * wl.w[wl.drive_idx] * math.sin(2 * math.pi * wl.drive_freq * t) * wl.drive_dir
+    np.testing.assert_allclose(F, want, rtol=1e-13, atol=1e-18)
+    # elastic part linear in k
+    wl, X = _perturbed_helix()
+    wl.kappa[:] = 0.0
+    wl.drive_A = 0.0
+    rng = np.random.default_rng(1)
+    k1, k2 = rng.uniform(0.5, 1.5, wl.M), rng.uniform(0.5, 1.5, wl.M)
+    f = lambda k: oracle_mod.force(oracle_mod.Model(wl, k), X, 0.0)
+    np.testing.assert_allclose(f(k1 + 2.0 * k2), f(k1) + 2.0 * f(k2), rtol=1e-10, atol=1e-12 * np.abs(f(k1)).max())
+
+
+# --------------------------------------------------------------------------
+# whole step: momentum balance and linearity
+# --------------------------------------------------------------------------
+def test_step_momentum_balance(oracle_mod):
+    wl = W.tiny_helix(N=16)
+    model = oracle_mod.Model(wl)
+    rng = np.random.default_rng(2)
+    u = 0.01 * W.random_field(wl.N, seed=2)
+    X = wl.X0 + 1e-4 * rng.standard_normal(wl.X0.shape)
+    X1, u1, F = oracle_mod.step(model, wl, X, u, 1e-4, convect=0, return_force=True)
+    h3 = wl.h ** 3
+    got = (u1 - u).reshape(3, -1).sum(1) * h3
+    np.testing.assert_allclose(got, wl.dt / wl.rho * F.sum(1), rtol=1e-10, atol=1e-16)
+
+
+def test_fluid_linear_in_u_and_force(oracle_mod):
+    N, L = 16, 1.0
+    a, b = W.random_field(N, seed=2), W.random_field(N, seed=3)
+    Fa, Fb = W.random_field(N, seed=4), W.random_field(N, seed=5)
+    f = lambda u, F: oracle_mod.fluid(N, L, 1.0, 0.01, 1e-3, 0, u, F)
+    lhs = f(a + 2.0 * b, Fa - 3.0 * Fb)
+    rhs = f(a, Fa) + 2.0 * f(b, np.zeros_like(Fb)) - 3.0 * f(np.zeros_like(a), Fb)
+    assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(lhs).max()
+
+
+def test_response_linear_in_drive(oracle_mod):
+    # Sec. 5: ten times the input force gives almost exactly ten times the displacement
+    wl = W.tiny_helix(N=16, n_steps=8)
+    X1, _ = oracle_mod.run(wl, wl.n_steps)
+    wl10 = W.tiny_helix(N=16, n_steps=8)
+    wl10.drive_A *= 10.0
+    X10, _ = oracle_mod.run(wl10, wl10.n_steps)
+    d1, d10 = X1 - wl.X0, X10 - wl.X0
+    ratio = np.linalg.norm(d10) / np.linalg.norm(d1)
+    assert abs(ratio - 10.0) < 1e-3 * 10.0
+    assert np.linalg.norm(d10 - 10.0 * d1) < 1e-3 * np.linalg.norm(d10)
