@@ -1,0 +1,166 @@
+/*
+ * ib.h -- immersed-boundary (IB) time step on one AMD Instinct MI355X (gfx950).
+ *
+ * Implements the first-order IB scheme of Givelberg & Bunn, "A Comprehensive
+ * Three-Dimensional Model of the Cochlea", Sec. 3.2: per step (1) the material
+ * force f^n, (2) spreading F^n = sum_q f^n(q) delta_h(x - X^n(q)) dq
+ * (eq. discreteF), (3) the Navier-Stokes update of eqs. discreteNS1-2 on a
+ * periodic grid by FFT, (4) the marker move of eq. discreteX.  The adjoint
+ * step is not in the paper; it differentiates the same four sub-steps.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grid: a periodic cube of n^3 nodes at positions (i h, j h, k h), h = L/n
+ *    (one mesh width in all directions; n a power of two in [8, 512]).
+ *  - Grid fields (u, F_grid, ubar) are DEVICE arrays [3][n][n][n], x fastest:
+ *    component c of node (i, j, k) at ((c*n + k)*n + j)*n + i, in the fluid
+ *    precision (double for IB_FLUID_FP64, float for IB_FLUID_FP32).
+ *  - Marker arrays (X, F_lag, U, Xbar) are DEVICE double arrays [3][M]
+ *    (component-major).  X is stored unwrapped; only grid indices wrap.
+ *  - Per-marker forces are f(q) dq, i.e. force densities times the marker's
+ *    area weight (so sum_x F_grid h^3 = sum_q F_lag[q]).
+ *  - The caller owns every array it passes; the context owns only its
+ *    workspace.  Calls are asynchronous on the context's stream: arrays must
+ *    stay valid until that stream's work is done.  With the environment
+ *    variable IB_CHECK=1 every call synchronises and checks for errors.
+ *  - Errors are returned as IB_E* codes (never abort, never throw);
+ *    ib_last_error() gives a text.  A context is not thread-safe.
+ */
+#ifndef IB_H
+#define IB_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ib_ctx ib_ctx;
+
+enum {
+  IB_OK = 0,
+  IB_EINVAL = -1,      /* bad argument (size, pointer, parameter out of range)   */
+  IB_ENOMEM = -2,      /* device allocation failed                                */
+  IB_EDEVICE = -3,     /* HIP runtime / kernel launch error                       */
+  IB_ENOTSUP = -4,     /* valid request outside what this build supports          */
+  IB_ENONFINITE = -5   /* IB_CHECK=1 found a NaN or Inf in an output              */
+};
+
+enum { IB_FLUID_FP64 = 0, IB_FLUID_FP32 = 1 };  /* markers are always FP64 */
+
+/* Problem statement of Sec. 3.1-3.2: density rho, viscosity mu, periodic grid,
+ * time step dt.  convect = 1 keeps the upwind advection term of
+ * eq. discreteNS1, 0 drops it (a Stokes step; required by the adjoint). */
+typedef struct {
+  int32_t n;                 /* nodes per dimension: power of two, 8..512          */
+  double L;                  /* box edge (> 0); h = L / n                           */
+  double rho, mu, dt;        /* rho > 0, mu >= 0, dt > 0                            */
+  int32_t fluid_precision;   /* IB_FLUID_FP64 or IB_FLUID_FP32                      */
+  int32_t convect;           /* 0 or 1                                               */
+  int64_t n_markers;         /* M >= 0, < 2^31                                      */
+  void *stream;              /* hipStream_t (NULL: the null stream)                 */
+} ib_params;
+
+/* A rectangular material lattice Q (Sec. 3.2): markers first + i2*n1 + i1,
+ * i1 in [0,n1) fastest, i2 in [0,n2) (periodic when periodic2 != 0). */
+typedef struct {
+  int64_t first;
+  int32_t n1, n2, periodic2;
+  double Ks, Kb;             /* stretch and bend moduli (0: term off)               */
+} ib_lattice;
+
+/* The material model (sub-step 1).  The paper defers fibre and shell forces
+ * to other works; the laws used here are negative energy gradients:
+ *   lattice stretch, edge (a,b): 1/2 Ks kbar wbar (|Xb-Xa| - |Yb-Ya|)^2 / |Yb-Ya|^2
+ *   lattice bend, triple (a,c,b): 1/2 Kb k_c w_c |(Xa-2Xc+Xb) - (Ya-2Yc+Yb)|^2 / Lc^4,
+ *       Lc = (|Yc-Ya| + |Yb-Yc|)/2
+ *   spring (a,b): 1/2 K_spring kbar (|Xb-Xa| - rest)^2
+ *   tether q:     1/2 kappa_q w_q |Xq - Yq|^2
+ *   drive (window, Sec. 4): + drive_A w_q sin(2 pi drive_freq t) dir_q
+ * with kbar, wbar the means over the edge's two markers and Y = X_ref.
+ * w, k, X_ref, kappa are DEVICE arrays read at every call (the caller may
+ * change their contents between calls; ib_set_material swaps pointers).
+ * Topology (lattices, springs, drive) is HOST memory copied at ib_create. */
+typedef struct {
+  const double *w;           /* [M] area weight dq                                  */
+  const double *k;           /* [M] stiffness multiplier (stretch, bend, springs)   */
+  const double *X_ref;       /* [3][M] reference shape: tether targets, rest shape  */
+  const double *kappa;       /* [M] tether stiffness density, 0 = none; nullable    */
+  int32_t n_lattices;        /* <= 16                                               */
+  const ib_lattice *lattices;
+  int64_t n_springs;
+  const int32_t *spring_ab;  /* [2][S] marker pairs (host)                          */
+  const double *spring_rest; /* [S] rest lengths (host)                             */
+  double K_spring;
+  int64_t n_drive;
+  const int32_t *drive_idx;  /* [D] distinct driven markers (host)                  */
+  const double *drive_dir;   /* [3][D] drive directions (host)                      */
+  double drive_A, drive_freq;
+} ib_elastic;
+
+/* Validate, copy the topology, allocate the workspace.  IB_EINVAL on a bad
+ * parameter or topology index, IB_ENOTSUP for n outside [8, 512] or not a
+ * power of two, IB_ENOMEM on allocation failure.  *out is NULL on error. */
+int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out);
+void ib_destroy(ib_ctx *c);
+
+/* Replace the per-marker material pointers (NULL keeps the current one). */
+int ib_set_material(ib_ctx *c, const double *w, const double *k, const double *X_ref,
+                    const double *kappa);
+/* Run subsequent calls on another hipStream_t. */
+int ib_set_stream(ib_ctx *c, void *stream);
+
+/* One time step (Sec. 3.2, all four sub-steps) at time t = n dt: X^n -> X^{n+1}
+ * and u^n -> u^{n+1} in place.  F_lag_out (nullable, [3][M] double) receives
+ * f^n dq.  Markers move with u^{n+1} interpolated at X^n (eq. discreteX). */
+int ib_step(ib_ctx *c, double *X, void *u, double t, double *F_lag_out);
+
+/* Sub-step 1: F_lag = f(X, t) dq, [3][M] double (overwritten). */
+int ib_force(ib_ctx *c, const double *X, double t, double *F_lag);
+
+/* Sub-step 2, eq. discreteF: F_grid = sum_q F_lag[q] delta_h(x - X_q)
+ * (overwrites the whole [3][n^3] F_grid). */
+int ib_spread(ib_ctx *c, const double *X, const double *F_lag, void *F_grid);
+
+/* Velocity of eq. discreteX: U_q = sum_x u(x) delta_h(x - X_q) h^3, [3][M] double. */
+int ib_interp(ib_ctx *c, const double *X, const void *u, double *U);
+
+/* Sub-step 3, eqs. discreteNS1-2: u^n -> u^{n+1} in place given F_grid
+ * (nullable: no body force). */
+int ib_fluid(ib_ctx *c, void *u, const void *F_grid);
+
+/* The binning that partitions markers among grid cells (Sec. 3.3): the cell
+ * of marker q is floor(X_q / h) per dimension wrapped into [0, n); key =
+ * (c3*n + c2)*n + c1.  perm[i] lists marker ids by key, ties by id (stable);
+ * keys_sorted[i] is the key of perm[i].  Both DEVICE arrays of length M. */
+int ib_bin(ib_ctx *c, const double *X, uint32_t *keys_sorted, int32_t *perm);
+
+/* Adjoint of ib_step for convect = 0 (IB_ENOTSUP otherwise).  Inputs: X_n
+ * (the step's starting positions), u_np1 (the velocity it produced), t.
+ * On entry Xbar [3][M] double and ubar [3][n^3] (fluid precision) hold the
+ * adjoints at step n+1; on return they hold those at step n, and
+ * kbar [M] double has (df/dk)^T fbar added to it. */
+int ib_adjoint_step(ib_ctx *c, const double *X_n, const void *u_np1, double t,
+                    double *Xbar, void *ubar, double *kbar);
+
+/* Text of the last error on this context ("" if none); c may be NULL for the
+ * last ib_create failure. */
+const char *ib_last_error(const ib_ctx *c);
+
+/* Device bytes held by the context's workspace. */
+int64_t ib_workspace_bytes(const ib_ctx *c);
+
+/* Per-phase timing (the instrumentation of Sec. 3.3, here with HIP events on
+ * the context's stream).  While enabled, every phase of every call records a
+ * start/stop event pair; ib_timers_read synchronises the stream and returns,
+ * for phase i < min(max, IB_N_TIMERS), the summed milliseconds ms[i] and the
+ * number of launches calls[i] since the last reset.  Phase names come from
+ * ib_timer_name(i) (NULL past the last phase).  Enabling resets the sums. */
+#define IB_N_TIMERS 16
+int ib_timers_enable(ib_ctx *c, int on);
+int ib_timers_read(ib_ctx *c, double *ms, int64_t *calls, int max);
+const char *ib_timer_name(int i);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,537 @@
+// C-ABI of the IB library: context creation, validation, workspace, tables
+// and the entry points declared in include/ib.h.  Host code; every step of the
+// method runs in the kernels of bin.hip, force.hip, spread.hip, fluid.hip and
+// interp.hip, enqueued on the context's stream.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "dev_common.h"
+#include "ib_internal.h"
+
+namespace ib {
+int sort_hist_words(int64_t M, int digit_bits);
+}
+
+using namespace ib;
+
+static thread_local std::string g_create_error;
+static const double kPi = 3.14159265358979323846;
+
+#define IB_TRY(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      c->err = std::string(#expr) + ": " + hipGetErrorString(e_);                            \
+      return IB_EDEVICE;                                                                     \
+    }                                                                                        \
+  } while (0)
+
+static int fail(ib_ctx *c, int code, const std::string &msg) {
+  c->err = msg;
+  return code;
+}
+
+// ------------------------------------------------------------ helpers ----
+namespace {
+
+__global__ void k_nonfinite_d(const double *__restrict__ a, int64_t n, int32_t *flag) {
+  const int64_t i = gtid();
+  if (i < n && !isfinite(a[i])) flag[0] = 1;
+}
+__global__ void k_nonfinite_f(const float *__restrict__ a, int64_t n, int32_t *flag) {
+  const int64_t i = gtid();
+  if (i < n && !isfinite(a[i])) flag[0] = 1;
+}
+
+template <typename A>
+hipError_t dalloc(ib_ctx *c, A **p, int64_t count) {
+  const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(A);
+  c->ws_bytes += (int64_t)bytes;
+  return hipMalloc((void **)p, bytes);
+}
+
+hipError_t dalloc_bytes(ib_ctx *c, void **p, int64_t bytes) {
+  c->ws_bytes += std::max<int64_t>(bytes, 1);
+  return hipMalloc(p, (size_t)std::max<int64_t>(bytes, 1));
+}
+
+double drive_amp(const ib_ctx *c, double t) {
+  if (c->n_drive == 0 || c->drive_A == 0.0) return 0.0;
+  return c->drive_A * sin(2.0 * kPi * c->drive_freq * t);
+}
+
+template <typename T>
+hipError_t upload_tables(ib_ctx *c) {
+  const int n = c->n;
+  const double h = c->h;
+  std::vector<T> tw(n), lam(n), sg(n);
+  for (int k = 0; k < n / 2; k++) {
+    const double a = 2.0 * kPi * (double)k / (double)n;
+    tw[2 * k] = (T)cos(a);
+    tw[2 * k + 1] = (T)(-sin(a));
+  }
+  for (int m = 0; m < n; m++) {
+    const double sh = sin(kPi * (double)m / (double)n);
+    lam[m] = (T)((4.0 / (h * h)) * sh * sh);
+    sg[m] = (m == 0 || 2 * m == n) ? (T)0 : (T)(sin(2.0 * kPi * (double)m / (double)n) / h);
+  }
+  hipError_t e = hipMemcpy(c->ws.tw, tw.data(), sizeof(T) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->ws.lam, lam.data(), sizeof(T) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->ws.sgrad, sg.data(), sizeof(T) * n, hipMemcpyHostToDevice);
+  return e;
+}
+
+bool is_fin(double v) { return isfinite(v) != 0; }
+
+void free_ws(ib_ctx *c) {
+  Workspace &w = c->ws;
+  void *ptrs[] = {w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.hist, w.row_start, w.frac, w.Fs, w.Flag,
+                  w.fb, w.Fgrid, w.tile_flag, w.r, w.spec, w.nonfinite, w.tw, w.lam, w.sgrad,
+                  w.drive_idx, w.drive_dir, w.sp_rowptr, w.sp_col, w.sp_rest};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  c->ws = Workspace{};
+}
+
+int checked(ib_ctx *c, const void *grid, bool grid_f32, const double *markers) {
+  if (!c->check) return IB_OK;
+  IB_TRY(hipStreamSynchronize(c->stream));
+  IB_TRY(hipGetLastError());
+  IB_TRY(hipMemsetAsync(c->ws.nonfinite, 0, sizeof(int32_t), c->stream));
+  if (markers && c->M > 0)
+    hipLaunchKernelGGL(k_nonfinite_d, dim3((unsigned)((3 * c->M + 255) / 256)), dim3(256), 0, c->stream, markers,
+                       3 * c->M, c->ws.nonfinite);
+  if (grid) {
+    if (grid_f32)
+      hipLaunchKernelGGL(k_nonfinite_f, dim3((unsigned)((3 * c->G + 255) / 256)), dim3(256), 0, c->stream,
+                         (const float *)grid, 3 * c->G, c->ws.nonfinite);
+    else
+      hipLaunchKernelGGL(k_nonfinite_d, dim3((unsigned)((3 * c->G + 255) / 256)), dim3(256), 0, c->stream,
+                         (const double *)grid, 3 * c->G, c->ws.nonfinite);
+  }
+  int32_t bad = 0;
+  IB_TRY(hipMemcpyAsync(&bad, c->ws.nonfinite, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  IB_TRY(hipStreamSynchronize(c->stream));
+  if (bad) return fail(c, IB_ENONFINITE, "non-finite value in an output");
+  return IB_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- create ----
+extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) {
+  if (!out) {
+    g_create_error = "ib_create: out is NULL";
+    return IB_EINVAL;
+  }
+  *out = nullptr;
+  if (!p || !e) {
+    g_create_error = "ib_create: params or elastic is NULL";
+    return IB_EINVAL;
+  }
+  const int n = p->n;
+  if (n < 8 || n > 512 || (n & (n - 1)) != 0) {
+    g_create_error = "ib_create: n must be a power of two in [8, 512]";
+    return IB_ENOTSUP;
+  }
+  if (!(p->L > 0.0) || !is_fin(p->L) || !(p->rho > 0.0) || !is_fin(p->rho) || !(p->mu >= 0.0) || !is_fin(p->mu) ||
+      !(p->dt > 0.0) || !is_fin(p->dt)) {
+    g_create_error = "ib_create: need L > 0, rho > 0, mu >= 0, dt > 0 (finite)";
+    return IB_EINVAL;
+  }
+  if (p->fluid_precision != IB_FLUID_FP64 && p->fluid_precision != IB_FLUID_FP32) {
+    g_create_error = "ib_create: fluid_precision must be IB_FLUID_FP64 or IB_FLUID_FP32";
+    return IB_EINVAL;
+  }
+  if (p->convect != 0 && p->convect != 1) {
+    g_create_error = "ib_create: convect must be 0 or 1";
+    return IB_EINVAL;
+  }
+  const int64_t M = p->n_markers;
+  if (M < 0 || M >= (int64_t)INT32_MAX) {
+    g_create_error = "ib_create: n_markers out of range";
+    return IB_EINVAL;
+  }
+  if (M > 0 && (!e->w || !e->k || !e->X_ref)) {
+    g_create_error = "ib_create: w, k and X_ref are required when n_markers > 0";
+    return IB_EINVAL;
+  }
+  if (e->n_lattices < 0 || e->n_lattices > kMaxLattices || (e->n_lattices > 0 && !e->lattices)) {
+    g_create_error = "ib_create: n_lattices must be in [0, 16] with a lattice array";
+    return IB_EINVAL;
+  }
+  std::vector<std::pair<int64_t, int64_t>> spans;
+  for (int l = 0; l < e->n_lattices; l++) {
+    const ib_lattice &L = e->lattices[l];
+    if (L.first < 0 || L.n1 < 1 || L.n2 < 1 || L.first + (int64_t)L.n1 * L.n2 > M || (L.periodic2 && L.n2 < 3) ||
+        !is_fin(L.Ks) || !is_fin(L.Kb)) {
+      g_create_error = "ib_create: lattice " + std::to_string(l) +
+                       " out of range (need first + n1*n2 <= M, n2 >= 3 when periodic, finite moduli)";
+      return IB_EINVAL;
+    }
+    spans.push_back({L.first, L.first + (int64_t)L.n1 * L.n2});
+  }
+  std::sort(spans.begin(), spans.end());
+  for (size_t i = 1; i < spans.size(); i++)
+    if (spans[i].first < spans[i - 1].second) {
+      g_create_error = "ib_create: lattices overlap";
+      return IB_EINVAL;
+    }
+  if (e->n_springs < 0 || (e->n_springs > 0 && (!e->spring_ab || !e->spring_rest)) || !is_fin(e->K_spring)) {
+    g_create_error = "ib_create: bad springs";
+    return IB_EINVAL;
+  }
+  const int64_t S = e->n_springs;
+  for (int64_t s = 0; s < S; s++) {
+    const int64_t a = e->spring_ab[s], b = e->spring_ab[S + s];
+    if (a < 0 || a >= M || b < 0 || b >= M || a == b || !(e->spring_rest[s] >= 0.0) || !is_fin(e->spring_rest[s])) {
+      g_create_error = "ib_create: spring " + std::to_string(s) + " has a bad index or rest length";
+      return IB_EINVAL;
+    }
+  }
+  if (e->n_drive < 0 || (e->n_drive > 0 && (!e->drive_idx || !e->drive_dir)) || !is_fin(e->drive_A) ||
+      !is_fin(e->drive_freq)) {
+    g_create_error = "ib_create: bad drive";
+    return IB_EINVAL;
+  }
+  const int64_t D = e->n_drive;
+  {
+    std::vector<int32_t> di(e->drive_idx, e->drive_idx + D);
+    for (int32_t v : di)
+      if (v < 0 || v >= M) {
+        g_create_error = "ib_create: drive index out of range";
+        return IB_EINVAL;
+      }
+    std::sort(di.begin(), di.end());
+    if (std::adjacent_find(di.begin(), di.end()) != di.end()) {
+      g_create_error = "ib_create: drive indices must be distinct";
+      return IB_EINVAL;
+    }
+  }
+
+  ib_ctx *c = new ib_ctx();
+  c->p = *p;
+  c->n = n;
+  while ((1 << c->log2n) < n) c->log2n++;
+  c->G = (int64_t)n * n * n;
+  c->M = M;
+  c->h = p->L / n;
+  c->fp32 = p->fluid_precision == IB_FLUID_FP32;
+  c->stream = (hipStream_t)p->stream;
+  const char *chk = getenv("IB_CHECK");
+  c->check = chk && chk[0] == '1';
+  c->n_springs = S;
+  c->n_drive = D;
+  c->drive_A = e->drive_A;
+  c->drive_freq = e->drive_freq;
+  const int key_bits = 3 * c->log2n;
+  c->sort_passes = (key_bits + 7) / 8;
+  c->digit_bits = (key_bits + c->sort_passes - 1) / c->sort_passes;
+
+  Material &mt = c->mat;
+  mt.w = e->w;
+  mt.k = e->k;
+  mt.X_ref = e->X_ref;
+  mt.kappa = e->kappa;
+  mt.M = M;
+  mt.K_spring = e->K_spring;
+  mt.lat.n = e->n_lattices;
+  for (int l = 0; l < e->n_lattices; l++) {
+    const ib_lattice &L = e->lattices[l];
+    mt.lat.l[l] = LatticeDev{L.first, L.n1, L.n2, L.periodic2 ? 1 : 0, L.Ks, L.Kb};
+  }
+
+  const size_t ts = c->fp32 ? 4 : 8;
+  const int64_t nh = n / 2 + 1;
+  Workspace &w = c->ws;
+  hipError_t err = hipSuccess;
+  auto chk_alloc = [&](hipError_t x) {
+    if (err == hipSuccess) err = x;
+  };
+  chk_alloc(dalloc(c, &w.keys[0], M));
+  chk_alloc(dalloc(c, &w.keys[1], M));
+  chk_alloc(dalloc(c, &w.vals[0], M));
+  chk_alloc(dalloc(c, &w.vals[1], M));
+  chk_alloc(dalloc(c, &w.hist, sort_hist_words(M, c->digit_bits)));
+  chk_alloc(dalloc(c, &w.row_start, (int64_t)n * n + 1));
+  chk_alloc(dalloc_bytes(c, &w.frac, 3 * M * (int64_t)ts));
+  chk_alloc(dalloc_bytes(c, &w.Fs, 3 * M * (int64_t)ts));
+  chk_alloc(dalloc(c, &w.Flag, 3 * M));
+  chk_alloc(dalloc(c, &w.fb, 3 * M));
+  chk_alloc(dalloc_bytes(c, &w.Fgrid, 3 * c->G * (int64_t)ts));
+  chk_alloc(dalloc(c, &w.tile_flag, (int64_t)(n / 8) * (n / 8) * (n / 8)));
+  chk_alloc(dalloc_bytes(c, &w.r, 3 * c->G * (int64_t)ts));
+  chk_alloc(dalloc_bytes(c, &w.spec, 3 * nh * (int64_t)n * n * 2 * (int64_t)ts));
+  chk_alloc(dalloc(c, &w.nonfinite, 1));
+  chk_alloc(dalloc_bytes(c, &w.tw, (int64_t)n * (int64_t)ts));
+  chk_alloc(dalloc_bytes(c, &w.lam, (int64_t)n * (int64_t)ts));
+  chk_alloc(dalloc_bytes(c, &w.sgrad, (int64_t)n * (int64_t)ts));
+  chk_alloc(dalloc(c, &w.drive_idx, D));
+  chk_alloc(dalloc(c, &w.drive_dir, 3 * D));
+  if (err != hipSuccess) {
+    g_create_error = std::string("ib_create: device allocation failed: ") + hipGetErrorString(err);
+    free_ws(c);
+    delete c;
+    return err == hipErrorOutOfMemory ? IB_ENOMEM : IB_EDEVICE;
+  }
+  if (D > 0) {
+    chk_alloc(hipMemcpy(w.drive_idx, e->drive_idx, sizeof(int32_t) * D, hipMemcpyHostToDevice));
+    chk_alloc(hipMemcpy(w.drive_dir, e->drive_dir, sizeof(double) * 3 * D, hipMemcpyHostToDevice));
+  }
+  if (S > 0) {
+    // spring adjacency in CSR, neighbours of each marker in spring order
+    std::vector<int32_t> rowptr(M + 1, 0), col(2 * S);
+    std::vector<double> rest(2 * S);
+    for (int64_t s = 0; s < S; s++) {
+      rowptr[e->spring_ab[s] + 1]++;
+      rowptr[e->spring_ab[S + s] + 1]++;
+    }
+    for (int64_t q = 0; q < M; q++) rowptr[q + 1] += rowptr[q];
+    std::vector<int32_t> fill(rowptr.begin(), rowptr.end() - 1);
+    for (int64_t s = 0; s < S; s++) {
+      const int32_t a = e->spring_ab[s], b = e->spring_ab[S + s];
+      col[fill[a]] = b;
+      rest[fill[a]++] = e->spring_rest[s];
+      col[fill[b]] = a;
+      rest[fill[b]++] = e->spring_rest[s];
+    }
+    chk_alloc(dalloc(c, &w.sp_rowptr, M + 1));
+    chk_alloc(dalloc(c, &w.sp_col, 2 * S));
+    chk_alloc(dalloc(c, &w.sp_rest, 2 * S));
+    if (err == hipSuccess) {
+      chk_alloc(hipMemcpy(w.sp_rowptr, rowptr.data(), sizeof(int32_t) * (M + 1), hipMemcpyHostToDevice));
+      chk_alloc(hipMemcpy(w.sp_col, col.data(), sizeof(int32_t) * 2 * S, hipMemcpyHostToDevice));
+      chk_alloc(hipMemcpy(w.sp_rest, rest.data(), sizeof(double) * 2 * S, hipMemcpyHostToDevice));
+    }
+    mt.sp_rowptr = w.sp_rowptr;
+    mt.sp_col = w.sp_col;
+    mt.sp_rest = w.sp_rest;
+  }
+  if (err == hipSuccess) err = c->fp32 ? upload_tables<float>(c) : upload_tables<double>(c);
+  if (err != hipSuccess) {
+    g_create_error = std::string("ib_create: upload failed: ") + hipGetErrorString(err);
+    free_ws(c);
+    delete c;
+    return err == hipErrorOutOfMemory ? IB_ENOMEM : IB_EDEVICE;
+  }
+  *out = c;
+  return IB_OK;
+}
+
+extern "C" void ib_destroy(ib_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto &r : c->trec) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  free_ws(c);
+  delete c;
+}
+
+// ------------------------------------------------------ instrumentation ----
+static const char *kPhaseNames[PH_COUNT] = {"bin", "force", "prep", "spread", "rhs", "fft_x", "fft_y",
+                                            "fft_z_solve", "fft_y_inv", "fft_x_inv", "interp", "adj_interp",
+                                            "adj_spread", "hessvec"};
+
+static void timers_fold(ib_ctx *c) {
+  if (c->tused == 0) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (size_t i = 0; i < c->tused; i++) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, c->trec[i].a, c->trec[i].b) == hipSuccess) {
+      c->tms[c->trec[i].phase] += ms;
+      c->tcalls[c->trec[i].phase] += 1;
+    }
+  }
+  c->tused = 0;
+}
+
+void ib::timer_begin(ib_ctx *c, int phase) {
+  if (!c->timing) return;
+  if (c->tused == c->trec.size()) {
+    TimerRec r{phase, nullptr, nullptr};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) {
+      c->timing = false;
+      return;
+    }
+    c->trec.push_back(r);
+  }
+  c->trec[c->tused].phase = phase;
+  (void)hipEventRecord(c->trec[c->tused].a, c->stream);
+}
+
+void ib::timer_end(ib_ctx *c) {
+  if (!c->timing) return;
+  (void)hipEventRecord(c->trec[c->tused].b, c->stream);
+  if (++c->tused >= 8192) timers_fold(c);
+}
+
+extern "C" int ib_timers_enable(ib_ctx *c, int on) {
+  if (!c) return IB_EINVAL;
+  timers_fold(c);
+  for (int i = 0; i < PH_COUNT; i++) {
+    c->tms[i] = 0.0;
+    c->tcalls[i] = 0;
+  }
+  c->timing = on != 0;
+  return IB_OK;
+}
+
+extern "C" int ib_timers_read(ib_ctx *c, double *ms, int64_t *calls, int max) {
+  if (!c || max < 0 || (max > 0 && (!ms || !calls))) return IB_EINVAL;
+  timers_fold(c);
+  for (int i = 0; i < max && i < IB_N_TIMERS; i++) {
+    ms[i] = i < PH_COUNT ? c->tms[i] : 0.0;
+    calls[i] = i < PH_COUNT ? c->tcalls[i] : 0;
+  }
+  return IB_OK;
+}
+
+extern "C" const char *ib_timer_name(int i) { return (i >= 0 && i < PH_COUNT) ? kPhaseNames[i] : nullptr; }
+
+extern "C" int ib_set_material(ib_ctx *c, const double *w, const double *k, const double *X_ref,
+                               const double *kappa) {
+  if (!c) return IB_EINVAL;
+  if (w) c->mat.w = w;
+  if (k) c->mat.k = k;
+  if (X_ref) c->mat.X_ref = X_ref;
+  if (kappa) c->mat.kappa = kappa;
+  return IB_OK;
+}
+
+extern "C" int ib_set_stream(ib_ctx *c, void *stream) {
+  if (!c) return IB_EINVAL;
+  c->stream = (hipStream_t)stream;
+  return IB_OK;
+}
+
+extern "C" const char *ib_last_error(const ib_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+extern "C" int64_t ib_workspace_bytes(const ib_ctx *c) { return c ? c->ws_bytes : 0; }
+
+// -------------------------------------------------------- entry points ----
+template <typename T>
+static int step_impl(ib_ctx *c, double *X, T *u, double t, double *F_lag_out) {
+  double *F = F_lag_out ? F_lag_out : c->ws.Flag;
+  IB_TRY(launch_bin(c, X));
+  IB_TRY(launch_force(c, X, drive_amp(c, t), F));
+  IB_TRY(launch_prep<T>(c, X, F));
+  IB_TRY(launch_spread<T>(c, (T *)c->ws.Fgrid, false, 1.0 / (c->h * c->h * c->h)));
+  IB_TRY(launch_rhs<T>(c, u, (const T *)c->ws.Fgrid, 1, c->p.convect, c->p.dt / c->p.rho, (T *)c->ws.r));
+  IB_TRY(launch_fluid_solve<T>(c, (const T *)c->ws.r, u));
+  IB_TRY(launch_interp<T>(c, u, X, nullptr, c->p.dt));
+  return checked(c, u, c->fp32, X);
+}
+
+extern "C" int ib_step(ib_ctx *c, double *X, void *u, double t, double *F_lag_out) {
+  if (!c) return IB_EINVAL;
+  if ((!X && c->M > 0) || !u) return fail(c, IB_EINVAL, "ib_step: X and u are required");
+  c->err.clear();
+  return c->fp32 ? step_impl<float>(c, X, (float *)u, t, F_lag_out)
+                 : step_impl<double>(c, X, (double *)u, t, F_lag_out);
+}
+
+extern "C" int ib_force(ib_ctx *c, const double *X, double t, double *F_lag) {
+  if (!c) return IB_EINVAL;
+  if (c->M > 0 && (!X || !F_lag)) return fail(c, IB_EINVAL, "ib_force: X and F_lag are required");
+  c->err.clear();
+  IB_TRY(launch_force(c, X, drive_amp(c, t), F_lag));
+  return checked(c, nullptr, false, F_lag);
+}
+
+template <typename T>
+static int spread_impl(ib_ctx *c, const double *X, const double *F, T *Fg) {
+  IB_TRY(launch_bin(c, X));
+  IB_TRY(launch_prep<T>(c, X, F));
+  IB_TRY(launch_spread<T>(c, Fg, true, 1.0 / (c->h * c->h * c->h)));
+  return checked(c, Fg, c->fp32, nullptr);
+}
+
+extern "C" int ib_spread(ib_ctx *c, const double *X, const double *F_lag, void *F_grid) {
+  if (!c) return IB_EINVAL;
+  if (!F_grid || (c->M > 0 && (!X || !F_lag))) return fail(c, IB_EINVAL, "ib_spread: X, F_lag, F_grid required");
+  c->err.clear();
+  return c->fp32 ? spread_impl<float>(c, X, F_lag, (float *)F_grid)
+                 : spread_impl<double>(c, X, F_lag, (double *)F_grid);
+}
+
+template <typename T>
+static int interp_impl(ib_ctx *c, const double *X, const T *u, double *U) {
+  IB_TRY(launch_bin(c, X));
+  IB_TRY(launch_prep<T>(c, X, nullptr));
+  IB_TRY(launch_interp<T>(c, u, nullptr, U, 0.0));
+  return checked(c, nullptr, false, U);
+}
+
+extern "C" int ib_interp(ib_ctx *c, const double *X, const void *u, double *U) {
+  if (!c) return IB_EINVAL;
+  if (!u || (c->M > 0 && (!X || !U))) return fail(c, IB_EINVAL, "ib_interp: X, u, U required");
+  c->err.clear();
+  return c->fp32 ? interp_impl<float>(c, X, (const float *)u, U) : interp_impl<double>(c, X, (const double *)u, U);
+}
+
+template <typename T>
+static int fluid_impl(ib_ctx *c, T *u, const T *Fg) {
+  IB_TRY(launch_rhs<T>(c, u, Fg, 2, c->p.convect, c->p.dt / c->p.rho, (T *)c->ws.r));
+  IB_TRY(launch_fluid_solve<T>(c, (const T *)c->ws.r, u));
+  return checked(c, u, c->fp32, nullptr);
+}
+
+extern "C" int ib_fluid(ib_ctx *c, void *u, const void *F_grid) {
+  if (!c) return IB_EINVAL;
+  if (!u) return fail(c, IB_EINVAL, "ib_fluid: u required");
+  c->err.clear();
+  return c->fp32 ? fluid_impl<float>(c, (float *)u, (const float *)F_grid)
+                 : fluid_impl<double>(c, (double *)u, (const double *)F_grid);
+}
+
+extern "C" int ib_bin(ib_ctx *c, const double *X, uint32_t *keys_sorted, int32_t *perm) {
+  if (!c) return IB_EINVAL;
+  if (c->M > 0 && (!X || !keys_sorted || !perm)) return fail(c, IB_EINVAL, "ib_bin: X, keys, perm required");
+  c->err.clear();
+  IB_TRY(launch_bin(c, X));
+  if (c->M > 0) {
+    IB_TRY(hipMemcpyAsync(keys_sorted, c->ws.keys[c->sorted_buf], sizeof(uint32_t) * c->M, hipMemcpyDeviceToDevice,
+                          c->stream));
+    IB_TRY(hipMemcpyAsync(perm, c->ws.vals[c->sorted_buf], sizeof(int32_t) * c->M, hipMemcpyDeviceToDevice,
+                          c->stream));
+  }
+  return checked(c, nullptr, false, nullptr);
+}
+
+template <typename T>
+static int adjoint_impl(ib_ctx *c, const double *X_n, const T *u_np1, double t, double *Xbar, T *ubar,
+                        double *kbar) {
+  // forward quantities at X^n: binning, weights, force f^n
+  IB_TRY(launch_bin(c, X_n));
+  IB_TRY(launch_force(c, X_n, drive_amp(c, t), c->ws.Flag));
+  IB_TRY(launch_prep<T>(c, X_n, nullptr));
+  // interpolation / move: phi' term into Xbar, stage Ubar = dt Xbar
+  IB_TRY(launch_adj_interp<T>(c, u_np1, Xbar));
+  // transpose of interpolation: ubar_tot = ubar + S(Ubar) h^3
+  IB_TRY(launch_spread<T>(c, (T *)c->ws.Fgrid, false, 1.0));
+  IB_TRY(launch_rhs<T>(c, ubar, (const T *)c->ws.Fgrid, 1, 0, 1.0, (T *)c->ws.r));
+  // the NS operator is symmetric: ubar^n = Lop ubar_tot
+  IB_TRY(launch_fluid_solve<T>(c, (const T *)c->ws.r, ubar));
+  // transpose of spreading (fbar) and its phi' term, then the force Jacobian
+  IB_TRY(launch_adj_spread<T>(c, ubar, c->ws.Flag, Xbar, c->ws.fb));
+  IB_TRY(launch_hessvec(c, X_n, c->ws.fb, Xbar, kbar));
+  return checked(c, ubar, c->fp32, Xbar);
+}
+
+extern "C" int ib_adjoint_step(ib_ctx *c, const double *X_n, const void *u_np1, double t, double *Xbar,
+                               void *ubar, double *kbar) {
+  if (!c) return IB_EINVAL;
+  if (c->p.convect != 0) return fail(c, IB_ENOTSUP, "ib_adjoint_step: only convect = 0 is differentiated");
+  if (!u_np1 || !ubar || (c->M > 0 && (!X_n || !Xbar || !kbar)))
+    return fail(c, IB_EINVAL, "ib_adjoint_step: X_n, u_np1, Xbar, ubar, kbar required");
+  c->err.clear();
+  return c->fp32 ? adjoint_impl<float>(c, X_n, (const float *)u_np1, t, Xbar, (float *)ubar, kbar)
+                 : adjoint_impl<double>(c, X_n, (const double *)u_np1, t, Xbar, (double *)ubar, kbar);
+}

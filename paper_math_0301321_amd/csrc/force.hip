@@ -1,0 +1,279 @@
+// Material force, sub-step 1 of the time step (Sec. 3.2), in FP64.
+//
+// One thread per marker gathers every term that acts on it (lattice stretch
+// edges, bend triples in which it is an end or the centre, springs through a
+// CSR adjacency, its tether), so no two threads write the same output and the
+// result does not depend on scheduling.  Each edge / triple is evaluated once
+// per marker it touches.  The window drive is added by a second kernel over
+// the (distinct) driven markers.  Force laws: see include/ib.h.
+#include "dev_common.h"
+#include "ib_internal.h"
+
+namespace ib {
+
+struct V3 {
+  double x, y, z;
+};
+
+__device__ __forceinline__ V3 ld3(const double *__restrict__ A, int64_t M, int64_t q) {
+  return V3{A[q], A[M + q], A[2 * M + q]};
+}
+__device__ __forceinline__ double nrm(const V3 &a) { return sqrt(a.x * a.x + a.y * a.y + a.z * a.z); }
+
+// Force on marker q from the stretch edge (q, o).
+__device__ __forceinline__ void stretch_on(const Material &m, const double *__restrict__ X, int64_t q,
+                                           int64_t o, const V3 &xq, double Ks, V3 &f) {
+  const int64_t M = m.M;
+  const V3 xo = ld3(X, M, o);
+  const V3 yq = ld3(m.X_ref, M, q), yo = ld3(m.X_ref, M, o);
+  const V3 d{xo.x - xq.x, xo.y - xq.y, xo.z - xq.z};
+  const V3 dy{yo.x - yq.x, yo.y - yq.y, yo.z - yq.z};
+  const double len = nrm(d), Le = nrm(dy);
+  const double K = Ks * (0.5 * (m.k[q] + m.k[o])) * (0.5 * (m.w[q] + m.w[o]));
+  const double s = K * (len - Le) / (Le * Le) / len;
+  f.x += s * d.x;
+  f.y += s * d.y;
+  f.z += s * d.z;
+}
+
+// Force on marker q from the bend triple (a, c, b); role: 0 = end, 1 = centre.
+__device__ __forceinline__ void bend_on(const Material &m, const double *__restrict__ X, int64_t a,
+                                        int64_t c, int64_t b, int role, double Kb, V3 &f) {
+  const int64_t M = m.M;
+  const V3 xa = ld3(X, M, a), xb = ld3(X, M, b), xc = ld3(X, M, c);
+  const V3 ya = ld3(m.X_ref, M, a), yb = ld3(m.X_ref, M, b), yc = ld3(m.X_ref, M, c);
+  const V3 v{(xa.x - 2.0 * xc.x + xb.x) - (ya.x - 2.0 * yc.x + yb.x),
+             (xa.y - 2.0 * xc.y + xb.y) - (ya.y - 2.0 * yc.y + yb.y),
+             (xa.z - 2.0 * xc.z + xb.z) - (ya.z - 2.0 * yc.z + yb.z)};
+  const V3 e1{yc.x - ya.x, yc.y - ya.y, yc.z - ya.z}, e2{yb.x - yc.x, yb.y - yc.y, yb.z - yc.z};
+  const double Lc = 0.5 * (nrm(e1) + nrm(e2));
+  const double K = Kb * m.k[c] * m.w[c] / (Lc * Lc * Lc * Lc);
+  const double s = role ? 2.0 * K : -K;
+  f.x += s * v.x;
+  f.y += s * v.y;
+  f.z += s * v.z;
+}
+
+__device__ void lattice_force(const Material &m, const LatticeDev &L, const double *__restrict__ X,
+                              int64_t q, const V3 &xq, V3 &f) {
+  const int64_t rel = q - L.first;
+  const int64_t n1 = L.n1, n2 = L.n2;
+  const int64_t i1 = rel % n1, i2 = rel / n1;
+  const bool per = L.periodic2 != 0;
+  auto idx = [&](int64_t a1, int64_t a2) { return L.first + a2 * n1 + a1; };
+  auto w2 = [&](int64_t a2) { return per ? (a2 + n2) % n2 : a2; };
+  const bool has_dn = per || i2 > 0, has_up = per || i2 < n2 - 1;
+  if (L.Ks != 0.0) {
+    if (i1 > 0) stretch_on(m, X, q, idx(i1 - 1, i2), xq, L.Ks, f);
+    if (i1 < n1 - 1) stretch_on(m, X, q, idx(i1 + 1, i2), xq, L.Ks, f);
+    if (has_dn) stretch_on(m, X, q, idx(i1, w2(i2 - 1)), xq, L.Ks, f);
+    if (has_up) stretch_on(m, X, q, idx(i1, w2(i2 + 1)), xq, L.Ks, f);
+  }
+  if (L.Kb != 0.0) {
+    // direction 1: centres 1 .. n1-2
+    if (i1 >= 1 && i1 <= n1 - 2) bend_on(m, X, idx(i1 - 1, i2), q, idx(i1 + 1, i2), 1, L.Kb, f);
+    if (i1 + 1 <= n1 - 2) bend_on(m, X, q, idx(i1 + 1, i2), idx(i1 + 2, i2), 0, L.Kb, f);
+    if (i1 - 1 >= 1) bend_on(m, X, idx(i1 - 2, i2), idx(i1 - 1, i2), q, 0, L.Kb, f);
+    // direction 2: centres 1 .. n2-2, or every row when periodic
+    auto centre_ok = [&](int64_t c2) { return per || (c2 >= 1 && c2 <= n2 - 2); };
+    if (centre_ok(i2)) bend_on(m, X, idx(i1, w2(i2 - 1)), q, idx(i1, w2(i2 + 1)), 1, L.Kb, f);
+    if ((per || i2 + 1 < n2) && centre_ok(i2 + 1))
+      bend_on(m, X, q, idx(i1, w2(i2 + 1)), idx(i1, w2(i2 + 2)), 0, L.Kb, f);
+    if ((per || i2 - 1 >= 0) && centre_ok(i2 - 1))
+      bend_on(m, X, idx(i1, w2(i2 - 2)), idx(i1, w2(i2 - 1)), q, 0, L.Kb, f);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_force(Material m, const double *__restrict__ X,
+                                               double *__restrict__ F) {
+  const int64_t q = gtid();
+  const int64_t M = m.M;
+  if (q >= M) return;
+  const V3 xq = ld3(X, M, q);
+  V3 f{0.0, 0.0, 0.0};
+  for (int l = 0; l < m.lat.n; l++) {
+    const LatticeDev &L = m.lat.l[l];
+    if (q >= L.first && q < L.first + (int64_t)L.n1 * L.n2) {
+      lattice_force(m, L, X, q, xq, f);
+      break;
+    }
+  }
+  if (m.sp_rowptr) {
+    for (int32_t e = m.sp_rowptr[q]; e < m.sp_rowptr[q + 1]; e++) {
+      const int64_t o = m.sp_col[e];
+      const V3 xo = ld3(X, M, o);
+      const V3 d{xo.x - xq.x, xo.y - xq.y, xo.z - xq.z};
+      const double len = nrm(d);
+      const double K = m.K_spring * (0.5 * (m.k[q] + m.k[o]));
+      const double s = K * (len - m.sp_rest[e]) / len;
+      f.x += s * d.x;
+      f.y += s * d.y;
+      f.z += s * d.z;
+    }
+  }
+  if (m.kappa) {
+    const double kw = m.kappa[q] * m.w[q];
+    if (kw != 0.0) {
+      const V3 y = ld3(m.X_ref, M, q);
+      f.x += -kw * (xq.x - y.x);
+      f.y += -kw * (xq.y - y.y);
+      f.z += -kw * (xq.z - y.z);
+    }
+  }
+  F[q] = f.x;
+  F[M + q] = f.y;
+  F[2 * M + q] = f.z;
+}
+
+// Window drive (Sec. 4): amp = A sin(2 pi f t) evaluated on the host in FP64.
+__global__ __launch_bounds__(256) void k_drive(const int32_t *__restrict__ idx, const double *__restrict__ dir,
+                                               int64_t D, const double *__restrict__ w, double amp, int64_t M,
+                                               double *__restrict__ F) {
+  const int64_t j = gtid();
+  if (j >= D) return;
+  const int64_t q = idx[j];
+  const double s = amp * w[q];
+  F[q] += s * dir[j];
+  F[M + q] += s * dir[D + j];
+  F[2 * M + q] += s * dir[2 * D + j];
+}
+
+hipError_t launch_force(ib_ctx *c, const double *X, double amp, double *F) {
+  if (c->M == 0) return hipSuccess;
+  PhaseScope ps(c, PH_FORCE);
+  hipLaunchKernelGGL(k_force, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream, c->mat, X, F);
+  if (c->n_drive > 0 && amp != 0.0)
+    hipLaunchKernelGGL(k_drive, dim3((unsigned)((c->n_drive + 255) / 256)), dim3(256), 0, c->stream,
+                       c->ws.drive_idx, c->ws.drive_dir, c->n_drive, c->mat.w, amp, c->M, F);
+  return hipGetLastError();
+}
+
+}  // namespace ib
+
+// ---------------------------------------------------------------------------
+// Adjoint of the force: with fbar the force cotangent,
+//   Xbar_q -= (H fbar)_q   (H the Hessian of the elastic energy; f = -grad E),
+//   kbar_q += (df/dk_q) . fbar   (f is linear in k).
+// Gather form, one thread per marker, as in the forward kernel.
+// ---------------------------------------------------------------------------
+namespace ib {
+
+// Stretch or spring edge (q, o) with energy 1/2 Ku kf (|d| - L0)^2 / D, D = L0^2
+// (lattice) or 1 (spring), d = Xo - Xq.  Adds the edge's part of (H fbar)_q to hv
+// and returns (unit-kf edge force) . fbar over both endpoints.
+__device__ __forceinline__ double edge_adj(const double *__restrict__ X, const double *__restrict__ fb, int64_t M,
+                                           int64_t q, int64_t o, double Ku, double kf, double L0, bool rest_sq,
+                                           V3 &hv) {
+  const V3 xq = ld3(X, M, q), xo = ld3(X, M, o);
+  const V3 vq = ld3(fb, M, q), vo = ld3(fb, M, o);
+  const V3 d{xo.x - xq.x, xo.y - xq.y, xo.z - xq.z};
+  const V3 dv{vo.x - vq.x, vo.y - vq.y, vo.z - vq.z};
+  const double len = nrm(d);
+  const double Kup = rest_sq ? Ku / (L0 * L0) : Ku;
+  const double Kp = Kup * kf;
+  const double dd = d.x * dv.x + d.y * dv.y + d.z * dv.z;
+  const double a = 1.0 - L0 / len, b = (L0 / (len * len * len)) * dd;
+  hv.x -= Kp * (a * dv.x + b * d.x);
+  hv.y -= Kp * (a * dv.y + b * d.y);
+  hv.z -= Kp * (a * dv.z + b * d.z);
+  return -(Kup * (len - L0) / len) * dd;
+}
+
+// Bend triple (a, c, b): adds the triple's part of (H fbar)_q (role 1: q is the
+// centre) and returns, for the centre, (unit-k_c triple force) . fbar.
+__device__ __forceinline__ double bend_adj(const Material &m, const double *__restrict__ X,
+                                           const double *__restrict__ fb, int64_t a, int64_t c, int64_t b,
+                                           int role, double Kb, V3 &hv) {
+  const int64_t M = m.M;
+  const V3 ya = ld3(m.X_ref, M, a), yb = ld3(m.X_ref, M, b), yc = ld3(m.X_ref, M, c);
+  const V3 e1{yc.x - ya.x, yc.y - ya.y, yc.z - ya.z}, e2{yb.x - yc.x, yb.y - yc.y, yb.z - yc.z};
+  const double Lc = 0.5 * (nrm(e1) + nrm(e2));
+  const double K1 = Kb * m.w[c] / (Lc * Lc * Lc * Lc);
+  const double K = K1 * m.k[c];
+  const V3 va = ld3(fb, M, a), vb = ld3(fb, M, b), vc = ld3(fb, M, c);
+  const V3 z{va.x - 2.0 * vc.x + vb.x, va.y - 2.0 * vc.y + vb.y, va.z - 2.0 * vc.z + vb.z};
+  const double s = role ? -2.0 * K : K;
+  hv.x += s * z.x;
+  hv.y += s * z.y;
+  hv.z += s * z.z;
+  if (!role) return 0.0;
+  const V3 xa = ld3(X, M, a), xb = ld3(X, M, b), xc = ld3(X, M, c);
+  const V3 v{(xa.x - 2.0 * xc.x + xb.x) - (ya.x - 2.0 * yc.x + yb.x),
+             (xa.y - 2.0 * xc.y + xb.y) - (ya.y - 2.0 * yc.y + yb.y),
+             (xa.z - 2.0 * xc.z + xb.z) - (ya.z - 2.0 * yc.z + yb.z)};
+  return -K1 * (v.x * z.x + v.y * z.y + v.z * z.z);
+}
+
+__global__ __launch_bounds__(256) void k_hessvec(Material m, const double *__restrict__ X,
+                                                 const double *__restrict__ fb, double *__restrict__ Xbar,
+                                                 double *__restrict__ kbar) {
+  const int64_t q = gtid();
+  const int64_t M = m.M;
+  if (q >= M) return;
+  V3 hv{0.0, 0.0, 0.0};
+  double kb = 0.0;
+  for (int l = 0; l < m.lat.n; l++) {
+    const LatticeDev &L = m.lat.l[l];
+    if (q < L.first || q >= L.first + (int64_t)L.n1 * L.n2) continue;
+    const int64_t rel = q - L.first, n1 = L.n1, n2 = L.n2;
+    const int64_t i1 = rel % n1, i2 = rel / n1;
+    const bool per = L.periodic2 != 0;
+    auto idx = [&](int64_t a1, int64_t a2) { return L.first + a2 * n1 + a1; };
+    auto w2 = [&](int64_t a2) { return per ? (a2 + n2) % n2 : a2; };
+    if (L.Ks != 0.0) {
+      auto edge = [&](int64_t o) {
+        const V3 yq = ld3(m.X_ref, M, q), yo = ld3(m.X_ref, M, o);
+        const V3 dy{yo.x - yq.x, yo.y - yq.y, yo.z - yq.z};
+        const double kf = 0.5 * (m.k[q] + m.k[o]);
+        const double wbar = 0.5 * (m.w[q] + m.w[o]);
+        kb += 0.5 * edge_adj(X, fb, M, q, o, L.Ks * wbar, kf, nrm(dy), true, hv);
+      };
+      if (i1 > 0) edge(idx(i1 - 1, i2));
+      if (i1 < n1 - 1) edge(idx(i1 + 1, i2));
+      if (per || i2 > 0) edge(idx(i1, w2(i2 - 1)));
+      if (per || i2 < n2 - 1) edge(idx(i1, w2(i2 + 1)));
+    }
+    if (L.Kb != 0.0) {
+      if (i1 >= 1 && i1 <= n1 - 2) kb += bend_adj(m, X, fb, idx(i1 - 1, i2), q, idx(i1 + 1, i2), 1, L.Kb, hv);
+      if (i1 + 1 <= n1 - 2) bend_adj(m, X, fb, q, idx(i1 + 1, i2), idx(i1 + 2, i2), 0, L.Kb, hv);
+      if (i1 - 1 >= 1) bend_adj(m, X, fb, idx(i1 - 2, i2), idx(i1 - 1, i2), q, 0, L.Kb, hv);
+      auto centre_ok = [&](int64_t c2) { return per || (c2 >= 1 && c2 <= n2 - 2); };
+      if (centre_ok(i2)) kb += bend_adj(m, X, fb, idx(i1, w2(i2 - 1)), q, idx(i1, w2(i2 + 1)), 1, L.Kb, hv);
+      if ((per || i2 + 1 < n2) && centre_ok(i2 + 1))
+        bend_adj(m, X, fb, q, idx(i1, w2(i2 + 1)), idx(i1, w2(i2 + 2)), 0, L.Kb, hv);
+      if ((per || i2 - 1 >= 0) && centre_ok(i2 - 1))
+        bend_adj(m, X, fb, idx(i1, w2(i2 - 2)), idx(i1, w2(i2 - 1)), q, 0, L.Kb, hv);
+    }
+    break;
+  }
+  if (m.sp_rowptr) {
+    for (int32_t e = m.sp_rowptr[q]; e < m.sp_rowptr[q + 1]; e++) {
+      const int64_t o = m.sp_col[e];
+      const double kf = 0.5 * (m.k[q] + m.k[o]);
+      kb += 0.5 * edge_adj(X, fb, M, q, o, m.K_spring, kf, m.sp_rest[e], false, hv);
+    }
+  }
+  if (m.kappa) {
+    const double kw = m.kappa[q] * m.w[q];
+    if (kw != 0.0) {
+      const V3 v = ld3(fb, M, q);
+      hv.x += kw * v.x;
+      hv.y += kw * v.y;
+      hv.z += kw * v.z;
+    }
+  }
+  Xbar[q] -= hv.x;
+  Xbar[M + q] -= hv.y;
+  Xbar[2 * M + q] -= hv.z;
+  kbar[q] += kb;
+}
+
+hipError_t launch_hessvec(ib_ctx *c, const double *X, const double *v, double *Xbar, double *kbar) {
+  if (c->M == 0) return hipSuccess;
+  PhaseScope ps(c, PH_HESSVEC);
+  hipLaunchKernelGGL(k_hessvec, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream, c->mat, X, v, Xbar,
+                     kbar);
+  return hipGetLastError();
+}
+
+}  // namespace ib

@@ -1,0 +1,199 @@
+// Interpolation and marker move, sub-step 4 (eq. discreteX), and the two
+// gathers of the adjoint step that share its stencil.
+//
+// One thread per marker in sorted (cell) order, so neighbouring threads read
+// overlapping 4^3 stencils of the grid and the loads coalesce in L1/L2.  The
+// weights come from the same X^n fractional offsets the spread used (eq.
+// discreteX interpolates u^{n+1} at X^n).  Velocities accumulate in the fluid
+// precision; the position update X += dt U is FP64.
+#include "dev_common.h"
+#include "ib_internal.h"
+
+namespace ib {
+
+struct Cell {
+  int x, y, z;
+};
+
+__device__ __forceinline__ Cell key_cell(uint32_t key, int log2n, int mask) {
+  return Cell{(int)(key & (uint32_t)mask), (int)((key >> log2n) & (uint32_t)mask), (int)(key >> (2 * log2n))};
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_interp(const uint32_t *__restrict__ keys, const int32_t *__restrict__ perm,
+                                                const T *__restrict__ frac, const T *__restrict__ u, int n,
+                                                int log2n, int64_t M, double dt, double *__restrict__ X,
+                                                double *__restrict__ U) {
+  const int64_t i = gtid();
+  if (i >= M) return;
+  const int mask = n - 1;
+  const int64_t G = (int64_t)n << (2 * log2n);
+  const Cell cc = key_cell(keys[i], log2n, mask);
+  T wx[4], wy[4], wz[4];
+  phi4<T>(frac[i], wx);
+  phi4<T>(frac[M + i], wy);
+  phi4<T>(frac[2 * M + i], wz);
+  T a0 = 0, a1 = 0, a2 = 0;
+  for (int c3 = 0; c3 < 4; c3++) {
+    const int64_t zo = (int64_t)((cc.z + c3 - 1) & mask) << (2 * log2n);
+    for (int c2 = 0; c2 < 4; c2++) {
+      const int64_t yo = zo + ((int64_t)((cc.y + c2 - 1) & mask) << log2n);
+      const T wyz = wy[c2];
+      for (int c1 = 0; c1 < 4; c1++) {
+        const int64_t p = yo + ((cc.x + c1 - 1) & mask);
+        const T wt = (wx[c1] * wyz) * wz[c3];
+        a0 += u[p] * wt;
+        a1 += u[G + p] * wt;
+        a2 += u[2 * G + p] * wt;
+      }
+    }
+  }
+  const int64_t q = perm[i];
+  if (U) {
+    U[q] = (double)a0;
+    U[M + q] = (double)a1;
+    U[2 * M + q] = (double)a2;
+  }
+  if (X) {
+    X[q] = X[q] + dt * (double)a0;
+    X[M + q] = X[M + q] + dt * (double)a1;
+    X[2 * M + q] = X[2 * M + q] + dt * (double)a2;
+  }
+}
+
+// Adjoint of the interpolation and move.  With Ubar = dt Xbar (Xbar at n+1):
+//   Xbar_q += sum_x (u^{n+1}(x) . Ubar_q) dPhi_q/dX_q      (phi' term)
+// and Ubar is staged (sorted order, fluid precision) for the transpose of
+// interpolation, a spread without the 1/h^3 factor.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__ keys,
+                                                    const int32_t *__restrict__ perm, const T *__restrict__ frac,
+                                                    const T *__restrict__ u, int n, int log2n, int64_t M,
+                                                    double dt, double inv_h, double *__restrict__ Xbar,
+                                                    T *__restrict__ Ub_sorted) {
+  const int64_t i = gtid();
+  if (i >= M) return;
+  const int mask = n - 1;
+  const int64_t G = (int64_t)n << (2 * log2n);
+  const Cell cc = key_cell(keys[i], log2n, mask);
+  const int64_t q = perm[i];
+  const double xb0 = Xbar[q], xb1 = Xbar[M + q], xb2 = Xbar[2 * M + q];
+  const T ub0 = (T)(dt * xb0), ub1 = (T)(dt * xb1), ub2 = (T)(dt * xb2);
+  Ub_sorted[i] = ub0;
+  Ub_sorted[M + i] = ub1;
+  Ub_sorted[2 * M + i] = ub2;
+  T wx[4], wy[4], wz[4], gx[4], gy[4], gz[4];
+  phi4<T>(frac[i], wx);
+  phi4<T>(frac[M + i], wy);
+  phi4<T>(frac[2 * M + i], wz);
+  dphi4<T>(frac[i], gx);
+  dphi4<T>(frac[M + i], gy);
+  dphi4<T>(frac[2 * M + i], gz);
+  T g0 = 0, g1 = 0, g2 = 0;
+  for (int c3 = 0; c3 < 4; c3++) {
+    const int64_t zo = (int64_t)((cc.z + c3 - 1) & mask) << (2 * log2n);
+    for (int c2 = 0; c2 < 4; c2++) {
+      const int64_t yo = zo + ((int64_t)((cc.y + c2 - 1) & mask) << log2n);
+      for (int c1 = 0; c1 < 4; c1++) {
+        const int64_t p = yo + ((cc.x + c1 - 1) & mask);
+        const T uU = u[p] * ub0 + u[G + p] * ub1 + u[2 * G + p] * ub2;
+        g0 += uU * (gx[c1] * wy[c2] * wz[c3]);
+        g1 += uU * (wx[c1] * gy[c2] * wz[c3]);
+        g2 += uU * (wx[c1] * wy[c2] * gz[c3]);
+      }
+    }
+  }
+  Xbar[q] = xb0 + (double)g0 * inv_h;
+  Xbar[M + q] = xb1 + (double)g1 * inv_h;
+  Xbar[2 * M + q] = xb2 + (double)g2 * inv_h;
+}
+
+// Adjoint of the spreading, with Fbar = scale_F * ubar^n (scale_F = dt/rho):
+//   fbar_q = sum_x Fbar(x) Phi_q / h^3,
+//   Xbar_q += sum_x (Fbar(x) . f_q) dPhi_q/dX_q / h^3.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_spread(const uint32_t *__restrict__ keys,
+                                                    const int32_t *__restrict__ perm, const T *__restrict__ frac,
+                                                    const T *__restrict__ ub, const double *__restrict__ F, int n,
+                                                    int log2n, int64_t M, double scale, double inv_h,
+                                                    double *__restrict__ Xbar, double *__restrict__ fbar) {
+  const int64_t i = gtid();
+  if (i >= M) return;
+  const int mask = n - 1;
+  const int64_t G = (int64_t)n << (2 * log2n);
+  const Cell cc = key_cell(keys[i], log2n, mask);
+  const int64_t q = perm[i];
+  const T f0 = (T)F[q], f1 = (T)F[M + q], f2 = (T)F[2 * M + q];
+  T wx[4], wy[4], wz[4], gx[4], gy[4], gz[4];
+  phi4<T>(frac[i], wx);
+  phi4<T>(frac[M + i], wy);
+  phi4<T>(frac[2 * M + i], wz);
+  dphi4<T>(frac[i], gx);
+  dphi4<T>(frac[M + i], gy);
+  dphi4<T>(frac[2 * M + i], gz);
+  T a0 = 0, a1 = 0, a2 = 0, g0 = 0, g1 = 0, g2 = 0;
+  for (int c3 = 0; c3 < 4; c3++) {
+    const int64_t zo = (int64_t)((cc.z + c3 - 1) & mask) << (2 * log2n);
+    for (int c2 = 0; c2 < 4; c2++) {
+      const int64_t yo = zo + ((int64_t)((cc.y + c2 - 1) & mask) << log2n);
+      for (int c1 = 0; c1 < 4; c1++) {
+        const int64_t p = yo + ((cc.x + c1 - 1) & mask);
+        const T b0 = ub[p], b1 = ub[G + p], b2 = ub[2 * G + p];
+        const T wt = (wx[c1] * wy[c2]) * wz[c3];
+        a0 += b0 * wt;
+        a1 += b1 * wt;
+        a2 += b2 * wt;
+        const T Ff = b0 * f0 + b1 * f1 + b2 * f2;
+        g0 += Ff * (gx[c1] * wy[c2] * wz[c3]);
+        g1 += Ff * (wx[c1] * gy[c2] * wz[c3]);
+        g2 += Ff * (wx[c1] * wy[c2] * gz[c3]);
+      }
+    }
+  }
+  fbar[q] = scale * (double)a0;
+  fbar[M + q] = scale * (double)a1;
+  fbar[2 * M + q] = scale * (double)a2;
+  Xbar[q] += scale * (double)g0 * inv_h;
+  Xbar[M + q] += scale * (double)g1 * inv_h;
+  Xbar[2 * M + q] += scale * (double)g2 * inv_h;
+}
+
+template <typename T>
+hipError_t launch_interp(ib_ctx *c, const T *u, double *X_inout, double *U_out, double dt) {
+  if (c->M == 0) return hipSuccess;
+  PhaseScope ps(c, PH_INTERP);
+  hipLaunchKernelGGL(k_interp<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
+                     c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (const T *)c->ws.frac, u, c->n,
+                     c->log2n, c->M, dt, X_inout, U_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_interp(ib_ctx *c, const T *u_np1, double *Xbar) {
+  if (c->M == 0) return hipSuccess;
+  PhaseScope ps(c, PH_ADJ_INTERP);
+  hipLaunchKernelGGL(k_adj_interp<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
+                     c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (const T *)c->ws.frac, u_np1, c->n,
+                     c->log2n, c->M, c->p.dt, 1.0 / c->h, Xbar, (T *)c->ws.Fs);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_spread(ib_ctx *c, const T *ubar_n, const double *F, double *Xbar, double *fbar) {
+  if (c->M == 0) return hipSuccess;
+  PhaseScope ps(c, PH_ADJ_SPREAD);
+  const double scale = (c->p.dt / c->p.rho) / (c->h * c->h * c->h);
+  hipLaunchKernelGGL(k_adj_spread<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
+                     c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (const T *)c->ws.frac, ubar_n, F, c->n,
+                     c->log2n, c->M, scale, 1.0 / c->h, Xbar, fbar);
+  return hipGetLastError();
+}
+
+template hipError_t launch_interp<float>(ib_ctx *, const float *, double *, double *, double);
+template hipError_t launch_interp<double>(ib_ctx *, const double *, double *, double *, double);
+template hipError_t launch_adj_interp<float>(ib_ctx *, const float *, double *);
+template hipError_t launch_adj_interp<double>(ib_ctx *, const double *, double *);
+template hipError_t launch_adj_spread<float>(ib_ctx *, const float *, const double *, double *, double *);
+template hipError_t launch_adj_spread<double>(ib_ctx *, const double *, const double *, double *, double *);
+
+}  // namespace ib

@@ -1,0 +1,121 @@
+"""CPU checks of the boundary: the C-ABI library loads and exports every
+declared entry point, argument validation fails cleanly before any device
+call, and the product and the oracle stay independent."""
+import ast
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ib[o]?_[a-z0-9_]+)\s*\(", text)))
+
+
+def _lib():
+    from paper_math_0301321_amd import ib
+    return ib.load_library()
+
+
+def test_library_exports_every_declared_entry_point():
+    lib = _lib()
+    names = _declared(os.path.join(ROOT, "include", "ib.h"))
+    assert "ib_step" in names and "ib_adjoint_step" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_oracle_exports_every_declared_function(oracle_mod):
+    lib = oracle_mod.lib()
+    for name in _declared(os.path.join(ROOT, "oracle", "ibo.h")):
+        assert hasattr(lib, name), name
+
+
+def _params(ib, **kw):
+    p = dict(n=16, L=1.0, rho=1.0, mu=0.01, dt=1e-3, fluid_precision=ib.IB_FLUID_FP32, convect=1,
+             n_markers=0, stream=None)
+    p.update(kw)
+    return ib.ib_params(**p)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=12), "IB_ENOTSUP"), (dict(n=4), "IB_ENOTSUP"), (dict(n=1024), "IB_ENOTSUP"),
+    (dict(L=0.0), "IB_EINVAL"), (dict(rho=-1.0), "IB_EINVAL"), (dict(mu=-0.1), "IB_EINVAL"),
+    (dict(dt=0.0), "IB_EINVAL"), (dict(dt=float("nan")), "IB_EINVAL"),
+    (dict(fluid_precision=7), "IB_EINVAL"), (dict(convect=2), "IB_EINVAL"),
+    (dict(n_markers=-5), "IB_EINVAL"), (dict(n_markers=10), "IB_EINVAL"),   # no material arrays
+])
+def test_create_rejects_bad_parameters(kw, code):
+    from paper_math_0301321_amd import ib
+    lib = _lib()
+    p = _params(ib, **kw)
+    e = ib.ib_elastic()
+    h = C.c_void_p()
+    rc = lib.ib_create(C.byref(p), C.byref(e), C.byref(h))
+    assert rc == getattr(ib, code)
+    assert h.value is None
+    assert lib.ib_last_error(None).decode().startswith("ib_create")
+
+
+def test_create_rejects_bad_topology():
+    from paper_math_0301321_amd import ib
+    lib = _lib()
+    fake = C.c_void_p(16)     # never dereferenced: validation fails first
+    p = _params(ib, n_markers=10)
+    lat = (ib.ib_lattice * 1)(ib.ib_lattice(0, 4, 3, 0, 1.0, 0.0))          # 12 > 10 markers
+    e = ib.ib_elastic(w=fake, k=fake, X_ref=fake, n_lattices=1, lattices=lat)
+    assert lib.ib_create(C.byref(p), C.byref(e), C.byref(C.c_void_p())) == ib.IB_EINVAL
+    lat = (ib.ib_lattice * 1)(ib.ib_lattice(0, 5, 2, 1, 1.0, 0.0))          # periodic with n2 < 3
+    e = ib.ib_elastic(w=fake, k=fake, X_ref=fake, n_lattices=1, lattices=lat)
+    assert lib.ib_create(C.byref(p), C.byref(e), C.byref(C.c_void_p())) == ib.IB_EINVAL
+    ab = np.array([[0, 3], [3, 3]], np.int32)                               # spring (3, 3)
+    rest = np.array([0.1, 0.1])
+    e = ib.ib_elastic(w=fake, k=fake, X_ref=fake, n_springs=2, spring_ab=ab.ctypes.data_as(C.c_void_p),
+                      spring_rest=rest.ctypes.data_as(C.c_void_p))
+    assert lib.ib_create(C.byref(p), C.byref(e), C.byref(C.c_void_p())) == ib.IB_EINVAL
+    di = np.array([1, 1], np.int32)                                         # repeated drive index
+    dd = np.zeros((3, 2))
+    e = ib.ib_elastic(w=fake, k=fake, X_ref=fake, n_drive=2, drive_idx=di.ctypes.data_as(C.c_void_p),
+                      drive_dir=dd.ctypes.data_as(C.c_void_p))
+    assert lib.ib_create(C.byref(p), C.byref(e), C.byref(C.c_void_p())) == ib.IB_EINVAL
+
+
+def test_null_context_calls_fail_cleanly():
+    from paper_math_0301321_amd import ib
+    lib = _lib()
+    assert lib.ib_step(None, None, None, 0.0, None) == ib.IB_EINVAL
+    assert lib.ib_adjoint_step(None, None, None, 0.0, None, None, None) == ib.IB_EINVAL
+    assert lib.ib_workspace_bytes(None) == 0
+
+
+def _imports(path):
+    tree = ast.parse(open(path).read())
+    out = set()
+    for node in ast.walk(tree):
+        if isinstance(node, ast.Import):
+            out |= {a.name.split(".")[0] for a in node.names}
+        elif isinstance(node, ast.ImportFrom) and node.module:
+            out.add(node.module.split(".")[0])
+    return out
+
+
+def test_product_and_oracle_are_independent():
+    pkg = os.path.join(ROOT, "paper_math_0301321_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith(".py"):
+                assert "oracle" not in _imports(os.path.join(dirpath, f)), f
+            if f.endswith((".hip", ".h", ".cpp")):
+                assert "ibo" not in open(os.path.join(dirpath, f)).read(), f
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith(".py"):
+            assert "paper_math_0301321_amd" not in _imports(os.path.join(ROOT, "oracle", f)), f
+        if f.endswith((".c", ".h")):
+            txt = open(os.path.join(ROOT, "oracle", f)).read()
+            assert "ib_internal" not in txt and "include/ib.h" not in txt, f
