@@ -69,8 +69,8 @@ template <typename T>
 hipError_t upload_tables(ib_ctx *c) {
   const int n = c->n;
   const double h = c->h;
-  std::vector<T> tw(n), lam(n), sg(n);
-  for (int k = 0; k < n / 2; k++) {
+  std::vector<T> tw(2 * n), lam(n), sg(n);
+  for (int k = 0; k < n; k++) {
     const double a = 2.0 * kPi * (double)k / (double)n;
     tw[2 * k] = (T)cos(a);
     tw[2 * k + 1] = (T)(-sin(a));
@@ -80,7 +80,7 @@ hipError_t upload_tables(ib_ctx *c) {
     lam[m] = (T)((4.0 / (h * h)) * sh * sh);
     sg[m] = (m == 0 || 2 * m == n) ? (T)0 : (T)(sin(2.0 * kPi * (double)m / (double)n) / h);
   }
-  hipError_t e = hipMemcpy(c->ws.tw, tw.data(), sizeof(T) * n, hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(c->ws.tw, tw.data(), sizeof(T) * 2 * n, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->ws.lam, lam.data(), sizeof(T) * n, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->ws.sgrad, sg.data(), sizeof(T) * n, hipMemcpyHostToDevice);
   return e;
@@ -90,9 +90,10 @@ bool is_fin(double v) { return isfinite(v) != 0; }
 
 void free_ws(ib_ctx *c) {
   Workspace &w = c->ws;
-  void *ptrs[] = {w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.hist, w.row_start, w.frac, w.Fs, w.Flag,
-                  w.fb, w.Fgrid, w.tile_flag, w.r, w.spec, w.nonfinite, w.tw, w.lam, w.sgrad,
-                  w.drive_idx, w.drive_dir, w.sp_rowptr, w.sp_col, w.sp_rest};
+  void *ptrs[] = {w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.hist, w.row_start, w.recs, w.Flag, w.fb,
+                  w.Fgrid, w.rowtab, w.tile_count, w.tile_flag, w.tile_part, w.tile_item0, w.item_tile,
+                  w.nitems, w.split_list, w.scan_tmp, w.partials, w.r, w.spec, w.nonfinite, w.tw, w.lam, w.sgrad, w.drive_idx,
+                  w.drive_dir, w.sp_rowptr, w.sp_col, w.sp_rest};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->ws = Workspace{};
@@ -259,16 +260,33 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
   chk_alloc(dalloc(c, &w.vals[1], M));
   chk_alloc(dalloc(c, &w.hist, sort_hist_words(M, c->digit_bits)));
   chk_alloc(dalloc(c, &w.row_start, (int64_t)n * n + 1));
-  chk_alloc(dalloc_bytes(c, &w.frac, 3 * M * (int64_t)ts));
-  chk_alloc(dalloc_bytes(c, &w.Fs, 3 * M * (int64_t)ts));
+  chk_alloc(dalloc_bytes(c, &w.recs, M * (int64_t)(c->fp32 ? sizeof(Rec<float>) : sizeof(Rec<double>))));
   chk_alloc(dalloc(c, &w.Flag, 3 * M));
   chk_alloc(dalloc(c, &w.fb, 3 * M));
   chk_alloc(dalloc_bytes(c, &w.Fgrid, 3 * c->G * (int64_t)ts));
-  chk_alloc(dalloc(c, &w.tile_flag, (int64_t)(n / 8) * (n / 8) * (n / 8)));
+  {
+    // spreading work list: every marker is listed by at most 2^3 tiles, so the
+    // items number at most ntiles + 8M/kSpreadItem and split tiles at most twice that
+    const int64_t ntiles = (int64_t)(n / 8) * (n / 8) * (n / 8);
+    const int64_t spill = (8 * M + kSpreadItem - 1) / kSpreadItem;
+    c->item_cap = ntiles + spill + 1;
+    c->part_cap = 2 * spill + 1;
+    c->spread_grid = (int)std::min<int64_t>(c->item_cap, 1024);
+    chk_alloc(dalloc(c, &w.rowtab, (int64_t)n * n * 2 * (n / 8 + 1)));
+    chk_alloc(dalloc(c, &w.tile_count, ntiles));
+    chk_alloc(dalloc(c, &w.tile_flag, ntiles));
+    chk_alloc(dalloc(c, &w.tile_part, ntiles));
+    chk_alloc(dalloc(c, &w.tile_item0, ntiles));
+    chk_alloc(dalloc(c, &w.item_tile, c->item_cap));
+    chk_alloc(dalloc(c, &w.nitems, 2));
+    chk_alloc(dalloc(c, &w.split_list, ntiles));
+    chk_alloc(dalloc(c, &w.scan_tmp, 3 * ((ntiles + 1023) / 1024)));
+    chk_alloc(dalloc_bytes(c, &w.partials, c->part_cap * 3 * 512 * (int64_t)ts));
+  }
   chk_alloc(dalloc_bytes(c, &w.r, 3 * c->G * (int64_t)ts));
   chk_alloc(dalloc_bytes(c, &w.spec, 3 * nh * (int64_t)n * n * 2 * (int64_t)ts));
   chk_alloc(dalloc(c, &w.nonfinite, 1));
-  chk_alloc(dalloc_bytes(c, &w.tw, (int64_t)n * (int64_t)ts));
+  chk_alloc(dalloc_bytes(c, &w.tw, 2 * (int64_t)n * (int64_t)ts));
   chk_alloc(dalloc_bytes(c, &w.lam, (int64_t)n * (int64_t)ts));
   chk_alloc(dalloc_bytes(c, &w.sgrad, (int64_t)n * (int64_t)ts));
   chk_alloc(dalloc(c, &w.drive_idx, D));
@@ -423,8 +441,7 @@ static int step_impl(ib_ctx *c, double *X, T *u, double t, double *F_lag_out) {
   IB_TRY(launch_force(c, X, drive_amp(c, t), F));
   IB_TRY(launch_prep<T>(c, X, F));
   IB_TRY(launch_spread<T>(c, (T *)c->ws.Fgrid, false, 1.0 / (c->h * c->h * c->h)));
-  IB_TRY(launch_rhs<T>(c, u, (const T *)c->ws.Fgrid, 1, c->p.convect, c->p.dt / c->p.rho, (T *)c->ws.r));
-  IB_TRY(launch_fluid_solve<T>(c, (const T *)c->ws.r, u));
+  IB_TRY(launch_fluid<T>(c, u, (const T *)c->ws.Fgrid, 1, c->p.convect, c->p.dt / c->p.rho, u));
   IB_TRY(launch_interp<T>(c, u, X, nullptr, c->p.dt));
   return checked(c, u, c->fp32, X);
 }
@@ -478,8 +495,7 @@ extern "C" int ib_interp(ib_ctx *c, const double *X, const void *u, double *U) {
 
 template <typename T>
 static int fluid_impl(ib_ctx *c, T *u, const T *Fg) {
-  IB_TRY(launch_rhs<T>(c, u, Fg, 2, c->p.convect, c->p.dt / c->p.rho, (T *)c->ws.r));
-  IB_TRY(launch_fluid_solve<T>(c, (const T *)c->ws.r, u));
+  IB_TRY(launch_fluid<T>(c, u, Fg, 2, c->p.convect, c->p.dt / c->p.rho, u));
   return checked(c, u, c->fp32, nullptr);
 }
 
@@ -516,9 +532,8 @@ static int adjoint_impl(ib_ctx *c, const double *X_n, const T *u_np1, double t, 
   IB_TRY(launch_adj_interp<T>(c, u_np1, Xbar));
   // transpose of interpolation: ubar_tot = ubar + S(Ubar) h^3
   IB_TRY(launch_spread<T>(c, (T *)c->ws.Fgrid, false, 1.0));
-  IB_TRY(launch_rhs<T>(c, ubar, (const T *)c->ws.Fgrid, 1, 0, 1.0, (T *)c->ws.r));
   // the NS operator is symmetric: ubar^n = Lop ubar_tot
-  IB_TRY(launch_fluid_solve<T>(c, (const T *)c->ws.r, ubar));
+  IB_TRY(launch_fluid<T>(c, ubar, (const T *)c->ws.Fgrid, 1, 0, 1.0, ubar));
   // transpose of spreading (fbar) and its phi' term, then the force Jacobian
   IB_TRY(launch_adj_spread<T>(c, ubar, c->ws.Flag, Xbar, c->ws.fb));
   IB_TRY(launch_hessvec(c, X_n, c->ws.fb, Xbar, kbar));

@@ -1,0 +1,534 @@
+// Register-resident FFT passes of the Navier-Stokes update (eqs. discreteNS1-2)
+// for n = 32, 64, 128, 256.
+//
+// A length-n transform is split as n = R1 * R2 (four-step): each of the
+// P = min(R1, R2) threads that own a pencil holds n / P values in registers,
+// does length-R1 DFTs in registers, multiplies by exp(-2 pi i s k1 / n),
+// exchanges once through LDS, and does length-R2 DFTs in registers.  The
+// inverse of a transform done with (R1, R2) uses (R2, R1), which leaves every
+// value in the register slot it started from.
+//
+// Five passes over HBM, each reading and writing its array once:
+//   k_xf_rhs   builds r = u - dt (upwind advection) + (dt/rho) F for a block of
+//              rows (all three components) from u staged in LDS and the force
+//              the spread left, and transforms the rows (two real rows packed
+//              as one complex pencil), writing modes kx = 0 .. n/2 to
+//              spec[c][kx][z][y] (runs of 128 bytes along y);
+//   k_y        forward or inverse along y (contiguous pencils);
+//   k_z_solve  forward along z for all three components of a (kx, y-block),
+//              the diagonal viscous solve and the projection per mode in
+//              registers, inverse along z;
+//   k_xi       inverse along x, real rows, scaled by 1/n^3.
+#include "dev_common.h"
+#include "ib_internal.h"
+
+namespace ib {
+namespace {
+
+// cos(2 pi k / 32) for k = 0 .. 8 (FP64, correctly rounded); the rest by symmetry.
+__host__ __device__ constexpr double cos32(int k) {
+  k &= 31;
+  if (k > 16) k = 32 - k;
+  const bool neg = k > 8;
+  if (neg) k = 16 - k;
+  double v = 0.0;
+  switch (k) {
+    case 0: v = 1.0; break;
+    case 1: v = 0.9807852804032304; break;
+    case 2: v = 0.9238795325112867; break;
+    case 3: v = 0.8314696123025452; break;
+    case 4: v = 0.7071067811865476; break;
+    case 5: v = 0.5555702330196022; break;
+    case 6: v = 0.3826834323650898; break;
+    case 7: v = 0.19509032201612828; break;
+    default: v = 0.0; break;
+  }
+  return neg ? -v : v;
+}
+__host__ __device__ constexpr double sin32(int k) { return cos32(k - 8); }
+
+template <int R>
+__host__ __device__ constexpr int brev_c(int i) {
+  int r = 0;
+  for (int b = 1, rb = R >> 1; b < R; b <<= 1, rb >>= 1)
+    if (i & b) r |= rb;
+  return r;
+}
+
+// 16-byte vector of the fluid precision, and its complex values
+template <typename T>
+struct V16;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <>
+struct V16<float> {
+  using type = f32x4;
+  __device__ static __forceinline__ cplx<float> c(const f32x4 &a, int m) {
+    return m == 0 ? cplx<float>{a.x, a.y} : cplx<float>{a.z, a.w};
+  }
+};
+template <>
+struct V16<double> {
+  using type = f64x2;
+  __device__ static __forceinline__ cplx<double> c(const f64x2 &a, int) { return cplx<double>{a.x, a.y}; }
+};
+template <typename T>
+using Vec16 = typename V16<T>::type;
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return cplx<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// In-register DFT of length R (2 .. 32) on v[0 .. R), natural order in and out.
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_reg(cplx<T> *v) {
+#pragma unroll
+  for (int i = 0; i < R; i++) {
+    const int j = brev_c<R>(i);
+    if (i < j) {
+      const cplx<T> t = v[i];
+      v[i] = v[j];
+      v[j] = t;
+    }
+  }
+#pragma unroll
+  for (int len = 2; len <= R; len <<= 1) {
+#pragma unroll
+    for (int i0 = 0; i0 < R; i0 += len) {
+#pragma unroll
+      for (int k = 0; k < len / 2; k++) {
+        const int m = k * (32 / len);   // angle 2 pi k / len = 2 pi m / 32
+        const cplx<T> b = v[i0 + k + len / 2];
+        cplx<T> tb;
+        if (m == 0) {
+          tb = b;
+        } else if (m == 8) {             // times -i (forward) or +i (inverse)
+          tb = INV ? cplx<T>{-b.y, b.x} : cplx<T>{b.y, -b.x};
+        } else {
+          const T wr = (T)cos32(m), wi = INV ? (T)sin32(m) : (T)(-sin32(m));
+          tb = cplx<T>{b.x * wr - b.y * wi, b.x * wi + b.y * wr};
+        }
+        const cplx<T> a = v[i0 + k];
+        v[i0 + k] = cplx<T>{a.x + tb.x, a.y + tb.y};
+        v[i0 + k + len / 2] = cplx<T>{a.x - tb.x, a.y - tb.y};
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Four-step transform of one pencil of length N = R1 R2 by P = min(R1, R2) threads.
+//   in : v[i R1 + j]  = x[(t + P i) + R2 j],   i < R2/P, j < R1
+//   out: v[i R2 + k2] = X[(t + P i) + R1 k2],  i < R1/P, k2 < R2
+// xch: R1 (R2 + 1) LDS values private to the pencil.  BLOCK: the pencil's
+// threads span several waves (block barrier) instead of one (wave barrier).
+template <typename T, int R1, int R2, bool INV, bool BLOCK>
+struct Fft4 {
+  static constexpr int N = R1 * R2;
+  static constexpr int P = R1 < R2 ? R1 : R2;
+  static constexpr int E = N / P;
+  static constexpr int XS = R2 + 1;
+  __device__ static __forceinline__ void sync() {
+    if (BLOCK) __syncthreads();
+    else wave_sync();
+  }
+  __device__ static __forceinline__ void run(cplx<T> *v, int t, cplx<T> *xch, const cplx<T> *__restrict__ tw) {
+#pragma unroll
+    for (int i = 0; i < R2 / P; i++) dft_reg<T, R1, INV>(v + i * R1);
+#pragma unroll
+    for (int i = 0; i < R2 / P; i++) {
+      const int s = t + P * i;
+#pragma unroll
+      for (int k1 = 1; k1 < R1; k1++) {
+        cplx<T> w = tw[s * k1];
+        if (INV) w.y = -w.y;
+        v[i * R1 + k1] = cmul(v[i * R1 + k1], w);
+      }
+    }
+    sync();   // xch is free (earlier users of it have finished)
+#pragma unroll
+    for (int i = 0; i < R2 / P; i++)
+#pragma unroll
+      for (int k1 = 0; k1 < R1; k1++) xch[k1 * XS + t + P * i] = v[i * R1 + k1];
+    sync();
+#pragma unroll
+    for (int i = 0; i < R1 / P; i++)
+#pragma unroll
+      for (int s = 0; s < R2; s++) v[i * R2 + s] = xch[(t + P * i) * XS + s];
+#pragma unroll
+    for (int i = 0; i < R1 / P; i++) dft_reg<T, R2, INV>(v + i * R2);
+  }
+};
+
+// Block index remapped so consecutive work lands on one XCD (8 per device,
+// blocks dealt round-robin): neighbouring z-planes then share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nblk) {
+  if (nblk % 8) return b;
+  return (b % 8) * (nblk / 8) + b / 8;
+}
+
+// ------------------------------------------------ pass x, forward + RHS ----
+template <typename T>
+struct XfCfg {
+  static constexpr int YB = sizeof(T) == 4 ? 16 : 8;   // rows per block: 128-byte runs of complex
+};
+
+template <typename T, int R1, int R2>
+struct XfSmem {
+  static constexpr int N = R1 * R2, YB = XfCfg<T>::YB, NP = 3 * YB / 2;
+  static constexpr int US = N + 8;     // staged row stride: rows of one wave's pencils fall in different banks
+  static constexpr int OS = YB + 1;    // output staging stride (complex values)
+  static constexpr size_t U = sizeof(T) * 3 * (YB + 2) * US;
+  static constexpr size_t X = sizeof(cplx<T>) * NP * R1 * (R2 + 1);
+  static constexpr size_t O = sizeof(cplx<T>) * 3 * (N / 2 + 1) * OS;
+  static constexpr size_t BYTES = U > X ? (U > O ? U : O) : (X > O ? X : O);
+};
+
+template <typename T, int R1, int R2>
+__global__ __launch_bounds__(3 * XfCfg<T>::YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf_rhs(
+    const T *__restrict__ u, const T *__restrict__ Fg, const int32_t *__restrict__ tile_flag, int fmode,
+    int convect, T dt, T f_scale, T inv_h, const cplx<T> *__restrict__ tw, cplx<T> *__restrict__ spec) {
+  using F4 = Fft4<T, R1, R2, false, false>;
+  using SM = XfSmem<T, R1, R2>;
+  constexpr int N = R1 * R2, P = F4::P, E = F4::E, YB = XfCfg<T>::YB, NP = 3 * YB / 2;
+  constexpr int NH = N / 2 + 1, mask = N - 1, NT = NP * P, US = SM::US, OS = SM::OS;
+  constexpr int NTX = N / 8, TY = (YB + 7) / 8;
+  constexpr int64_t G = (int64_t)N * N * N;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[SM::BYTES];
+  __shared__ int sflag[TY * NTX];
+  T *us = (T *)smem;                                   // [3][YB + 2][US]: rows y0-1 .. y0+YB
+  const int nyb = N / YB;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int y0 = (b % nyb) * YB, z = b / nyb;
+  const int tid = threadIdx.x;
+  // 1. stage u rows and the force flags of the block's tiles: all 16-byte
+  //    loads are issued before the first LDS store
+  {
+    using V = Vec16<T>;
+    constexpr int EPC = 16 / sizeof(T), CPR = N / EPC, TOT = 3 * (YB + 2) * CPR, IT = (TOT + NT - 1) / NT;
+    V tmp[IT];
+    auto src = [&](int e) {
+      const int row = e / CPR, x4 = e % CPR, c = row / (YB + 2), rr = row % (YB + 2);
+      const int y = (y0 - 1 + rr) & mask;
+      return (const V *)(u + c * G + ((int64_t)z * N + y) * N + x4 * EPC);
+    };
+    auto dst = [&](int e) { return (V *)(us + (e / CPR) * US + (e % CPR) * EPC); };
+    if constexpr (TOT % NT == 0) {
+#pragma unroll
+      for (int k = 0; k < IT; k++) tmp[k] = *src(tid + k * NT);
+#pragma unroll
+      for (int k = 0; k < IT; k++) *dst(tid + k * NT) = tmp[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < IT; k++)
+        if (tid + k * NT < TOT) tmp[k] = *src(tid + k * NT);
+#pragma unroll
+      for (int k = 0; k < IT; k++)
+        if (tid + k * NT < TOT) *dst(tid + k * NT) = tmp[k];
+    }
+  }
+  if (fmode == 1)
+    for (int e = tid; e < TY * NTX; e += NT)
+      sflag[e] = tile_flag[((z >> 3) * NTX + (y0 >> 3) + e / NTX) * NTX + e % NTX];
+  __syncthreads();
+  // 2. right-hand side for this thread's values, packed two rows per pencil
+  const int p = tid / P, t = tid % P;
+  const int c = p / (YB / 2), rp = p % (YB / 2);
+  const int zm = (z - 1) & mask, zp = (z + 1) & mask;
+  cplx<T> v[E];
+#pragma unroll
+  for (int i = 0; i < R2 / P; i++) {
+#pragma unroll
+    for (int j = 0; j < R1; j++) {
+      const int x = (t + P * i) + R2 * j;
+      T rv[2];
+#pragma unroll
+      for (int ab = 0; ab < 2; ab++) {
+        const int row = 2 * rp + ab;               // local row; staged row row + 1
+        const int y = y0 + row;
+        const T *uc = us + (c * (YB + 2) + row + 1) * US;
+        const T uk0 = us[(0 * (YB + 2) + row + 1) * US + x];
+        const T uk1 = us[(1 * (YB + 2) + row + 1) * US + x];
+        const T uk2 = us[(2 * (YB + 2) + row + 1) * US + x];
+        const T ucc = uc[x];
+        T r = ucc;
+        if (convect) {
+          // upwind side per direction: one load of the neighbour on that side
+          const T nx = uc[uk0 > T(0) ? ((x - 1) & mask) : ((x + 1) & mask)];
+          const T ny = uc[uk1 > T(0) ? x - US : x + US];
+          const T nz = u[c * G + ((int64_t)(uk2 > T(0) ? zm : zp) * N + y) * N + x];
+          T acc = T(0);
+          if (uk0 > T(0)) acc += uk0 * ((ucc - nx) * inv_h);
+          else if (uk0 < T(0)) acc += uk0 * ((nx - ucc) * inv_h);
+          if (uk1 > T(0)) acc += uk1 * ((ucc - ny) * inv_h);
+          else if (uk1 < T(0)) acc += uk1 * ((ny - ucc) * inv_h);
+          if (uk2 > T(0)) acc += uk2 * ((ucc - nz) * inv_h);
+          else if (uk2 < T(0)) acc += uk2 * ((nz - ucc) * inv_h);
+          r = r - dt * acc;
+        }
+        if (fmode != 0) {
+          const bool has = fmode == 2 || sflag[((y >> 3) - (y0 >> 3)) * NTX + (x >> 3)] != 0;
+          const T fv = has ? Fg[c * G + ((int64_t)z * N + y) * N + x] : T(0);
+          if (has) r = r + f_scale * fv;
+        }
+        rv[ab] = r;
+      }
+      v[i * R1 + j] = cplx<T>{rv[0], rv[1]};
+    }
+  }
+  __syncthreads();   // the staged rows are dead; the buffer becomes pencil exchange space
+  cplx<T> *xch = (cplx<T> *)smem + p * R1 * (R2 + 1);
+  F4::run(v, t, xch, tw);
+  // 3. spectra of the two real rows: A = (Z[k] + conj Z[-k]) / 2, B = (Z[k] - conj Z[-k]) / 2i
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < R1 / P; i++)
+#pragma unroll
+    for (int k2 = 0; k2 < R2; k2++) xch[(t + P * i) + R1 * k2] = v[i * R2 + k2];
+  wave_sync();
+  constexpr int KM = (NH + P - 1) / P;
+  cplx<T> A[KM], B[KM];
+#pragma unroll
+  for (int m = 0; m < KM; m++) {
+    const int k = t + P * m;
+    if (k < NH) {
+      const cplx<T> zk = xch[k], zn = xch[(N - k) & mask];
+      A[m] = cplx<T>{T(0.5) * (zk.x + zn.x), T(0.5) * (zk.y - zn.y)};
+      B[m] = cplx<T>{T(0.5) * (zk.y + zn.y), T(0.5) * (zn.x - zk.x)};
+    }
+  }
+  __syncthreads();
+  cplx<T> *out = (cplx<T> *)smem;                      // [3][NH][OS]
+#pragma unroll
+  for (int m = 0; m < KM; m++) {
+    const int k = t + P * m;
+    if (k < NH) {
+      out[(c * NH + k) * OS + 2 * rp] = A[m];
+      out[(c * NH + k) * OS + 2 * rp + 1] = B[m];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < 3 * NH * YB; e += NT) {
+    const int yy = e % YB, ck = e / YB, k = ck % NH, cc = ck / NH;
+    spec[(((int64_t)cc * NH + k) * N + z) * N + y0 + yy] = out[ck * OS + yy];
+  }
+}
+
+// ---------------------------------------------------------------- pass y ----
+template <typename T, int R1, int R2, bool INV>
+__global__ __launch_bounds__(256) void k_y(cplx<T> *__restrict__ spec, int64_t npencils,
+                                           const cplx<T> *__restrict__ tw) {
+  using F4 = Fft4<T, R1, R2, INV, false>;
+  constexpr int N = R1 * R2, P = F4::P, E = F4::E, PPB = 256 / P;
+  __shared__ cplx<T> xch[PPB * R1 * (R2 + 1)];
+  const int lp = threadIdx.x / P, t = threadIdx.x % P;
+  const int64_t pen = (int64_t)blockIdx.x * PPB + lp;
+  if (pen >= npencils) return;       // whole pencils only: the exchange is wave-local
+  cplx<T> *g = spec + pen * N;
+  cplx<T> v[E];
+#pragma unroll
+  for (int i = 0; i < R2 / P; i++)
+#pragma unroll
+    for (int j = 0; j < R1; j++) v[i * R1 + j] = g[(t + P * i) + R2 * j];
+  F4::run(v, t, xch + lp * R1 * (R2 + 1), tw);
+#pragma unroll
+  for (int i = 0; i < R1 / P; i++)
+#pragma unroll
+    for (int k2 = 0; k2 < R2; k2++) g[(t + P * i) + R1 * k2] = v[i * R2 + k2];
+}
+
+// ------------------------------------------------- pass z with the solve ----
+template <typename T, int R1, int R2>
+__global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2)) void k_z_solve(
+    cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ tw, const T *__restrict__ lam,
+    const T *__restrict__ sg, T nu_dt) {
+  using Ff = Fft4<T, R1, R2, false, true>;
+  using Fi = Fft4<T, R2, R1, true, true>;
+  constexpr int N = R1 * R2, P = Ff::P, E = Ff::E, YB = XfCfg<T>::YB, NH = N / 2 + 1;
+  // per-y exchange space, padded to 2 (mod 32) values so that the 16 y's and
+  // neighbouring t's of a wave fall in distinct LDS banks
+  constexpr int XS0 = (R1 * (R2 + 1) > R2 * (R1 + 1)) ? R1 * (R2 + 1) : R2 * (R1 + 1);
+  constexpr int XSZ = XS0 + ((2 - XS0 % 32) + 32) % 32;
+  __shared__ cplx<T> xch[YB * XSZ];
+  const int nyb = N / YB;
+  const int kx = blockIdx.x / nyb, y0 = (blockIdx.x % nyb) * YB;
+  const int yy = threadIdx.x % YB, t = threadIdx.x / YB;
+  const int64_t cs = (int64_t)NH * N * N;
+  cplx<T> *g = spec + ((int64_t)kx * N) * N + y0 + yy;   // + c cs + z N
+  cplx<T> v[3][E];
+#pragma unroll
+  for (int c = 0; c < 3; c++)
+#pragma unroll
+    for (int i = 0; i < R2 / P; i++)
+#pragma unroll
+      for (int j = 0; j < R1; j++) v[c][i * R1 + j] = g[c * cs + (int64_t)((t + P * i) + R2 * j) * N];
+#pragma unroll
+  for (int c = 0; c < 3; c++) Ff::run(v[c], t, xch + yy * XSZ, tw);
+  // per mode (kx, ky, kz): w = r^/(1 + nu dt lambda), then remove the s-component
+  const int ky = y0 + yy;
+  const T lxy = lam[kx] + lam[ky];
+  const T s0 = sg[kx], s1 = sg[ky];
+#pragma unroll
+  for (int i = 0; i < R1 / P; i++) {
+#pragma unroll
+    for (int k2 = 0; k2 < R2; k2++) {
+      const int e = i * R2 + k2;
+      const int kz = (t + P * i) + R1 * k2;
+      const T den = T(1) + nu_dt * (lxy + lam[kz]);
+      const T s2 = sg[kz];
+      cplx<T> w0{v[0][e].x / den, v[0][e].y / den};
+      cplx<T> w1{v[1][e].x / den, v[1][e].y / den};
+      cplx<T> w2{v[2][e].x / den, v[2][e].y / den};
+      const T ss = s0 * s0 + s1 * s1 + s2 * s2;
+      if (ss > T(0)) {
+        const T dr = (s0 * w0.x + s1 * w1.x + s2 * w2.x) / ss;
+        const T di = (s0 * w0.y + s1 * w1.y + s2 * w2.y) / ss;
+        w0.x -= s0 * dr; w0.y -= s0 * di;
+        w1.x -= s1 * dr; w1.y -= s1 * di;
+        w2.x -= s2 * dr; w2.y -= s2 * di;
+      }
+      v[0][e] = w0;
+      v[1][e] = w1;
+      v[2][e] = w2;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; c++) Fi::run(v[c], t, xch + yy * XSZ, tw);
+#pragma unroll
+  for (int c = 0; c < 3; c++)
+#pragma unroll
+    for (int i = 0; i < R2 / P; i++)
+#pragma unroll
+      for (int j = 0; j < R1; j++) g[c * cs + (int64_t)((t + P * i) + R2 * j) * N] = v[c][i * R1 + j];
+}
+
+// ------------------------------------------------------ pass x, inverse ----
+template <typename T, int R1, int R2>
+__global__ __launch_bounds__(3 * XfCfg<T>::YB / 2 * (R1 < R2 ? R1 : R2)) void k_xi(
+    const cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ tw, T scale, T *__restrict__ u) {
+  using F4 = Fft4<T, R1, R2, true, false>;
+  constexpr int N = R1 * R2, P = F4::P, E = F4::E, YB = XfCfg<T>::YB, NP = 3 * YB / 2;
+  constexpr int NH = N / 2 + 1, mask = N - 1, NT = NP * P;
+  constexpr int64_t G = (int64_t)N * N * N;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[XfSmem<T, R1, R2>::BYTES];
+  constexpr int OS = XfSmem<T, R1, R2>::OS;
+  cplx<T> *stage = (cplx<T> *)smem;                   // [3][NH][OS]
+  const int nyb = N / YB;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int y0 = (b % nyb) * YB, z = b / nyb;
+  const int tid = threadIdx.x;
+  {
+    // 16-byte loads of the (c, kx) runs along y, all issued before the LDS stores
+    using V = Vec16<T>;
+    constexpr int CPC = 16 / sizeof(cplx<T>), CPRUN = YB / CPC, TOT = 3 * NH * CPRUN, IT = (TOT + NT - 1) / NT;
+    V tmp[IT];
+#pragma unroll
+    for (int k = 0; k < IT; k++) {
+      const int e = tid + k * NT;
+      if (e < TOT) {
+        const int q = e % CPRUN, ck = e / CPRUN, kk = ck % NH, cc = ck / NH;
+        tmp[k] = *(const V *)(spec + (((int64_t)cc * NH + kk) * N + z) * N + y0 + q * CPC);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < IT; k++) {
+      const int e = tid + k * NT;
+      if (e < TOT) {
+        const int q = e % CPRUN, ck = e / CPRUN;
+#pragma unroll
+        for (int m = 0; m < CPC; m++) stage[ck * OS + q * CPC + m] = V16<T>::c(tmp[k], m);
+      }
+    }
+  }
+  __syncthreads();
+  const int p = tid / P, t = tid % P;
+  const int c = p / (YB / 2), rp = p % (YB / 2);
+  // Z[k] = A[k] + i B[k] with A, B the Hermitian spectra of rows 2rp, 2rp+1
+  cplx<T> v[E];
+#pragma unroll
+  for (int i = 0; i < R2 / P; i++)
+#pragma unroll
+    for (int j = 0; j < R1; j++) {
+      const int k = (t + P * i) + R2 * j;
+      const bool hi = k > N / 2;
+      const int kk = hi ? N - k : k;
+      cplx<T> a = stage[(c * NH + kk) * OS + 2 * rp];
+      cplx<T> bb = stage[(c * NH + kk) * OS + 2 * rp + 1];
+      if (hi) {
+        a.y = -a.y;
+        bb.y = -bb.y;
+      }
+      v[i * R1 + j] = cplx<T>{a.x - bb.y, a.y + bb.x};
+    }
+  __syncthreads();   // staging is dead; the buffer becomes pencil exchange space
+  F4::run(v, t, (cplx<T> *)smem + p * R1 * (R2 + 1), tw);
+  T *ra = u + c * G + ((int64_t)z * N + y0 + 2 * rp) * N;
+#pragma unroll
+  for (int i = 0; i < R1 / P; i++)
+#pragma unroll
+    for (int k2 = 0; k2 < R2; k2++) {
+      const int x = (t + P * i) + R1 * k2;
+      ra[x] = v[i * R2 + k2].x * scale;
+      ra[N + x] = v[i * R2 + k2].y * scale;
+    }
+}
+
+template <typename T, int R1, int R2>
+hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect, double f_scale, T *u_out) {
+  constexpr int N = R1 * R2, P = R1 < R2 ? R1 : R2, YB = XfCfg<T>::YB, NH = N / 2 + 1;
+  cplx<T> *spec = (cplx<T> *)c->ws.spec;
+  const cplx<T> *tw = (const cplx<T> *)c->ws.tw;
+  {
+    PhaseScope ps(c, PH_FFT_X);
+    hipLaunchKernelGGL((k_xf_rhs<T, R1, R2>), dim3(N * (N / YB)), dim3(3 * YB / 2 * P), 0, c->stream, u_in, Fg,
+                       c->ws.tile_flag, Fg ? fmode : 0, convect, (T)c->p.dt, (T)f_scale, (T)(1.0 / c->h), tw, spec);
+  }
+  const int64_t npen = (int64_t)3 * NH * N;
+  const unsigned ny = (unsigned)((npen + 256 / P - 1) / (256 / P));
+  {
+    PhaseScope ps(c, PH_FFT_Y);
+    hipLaunchKernelGGL((k_y<T, R1, R2, false>), dim3(ny), dim3(256), 0, c->stream, spec, npen, tw);
+  }
+  {
+    PhaseScope ps(c, PH_FFT_Z_SOLVE);
+    hipLaunchKernelGGL((k_z_solve<T, R1, R2>), dim3(NH * (N / YB)), dim3(YB * P), 0, c->stream, spec, tw,
+                       (const T *)c->ws.lam, (const T *)c->ws.sgrad, (T)(c->p.mu * c->p.dt / c->p.rho));
+  }
+  {
+    PhaseScope ps(c, PH_FFT_Y_INV);
+    hipLaunchKernelGGL((k_y<T, R1, R2, true>), dim3(ny), dim3(256), 0, c->stream, spec, npen, tw);
+  }
+  {
+    PhaseScope ps(c, PH_FFT_X_INV);
+    hipLaunchKernelGGL((k_xi<T, R1, R2>), dim3(N * (N / YB)), dim3(3 * YB / 2 * P), 0, c->stream, spec, tw,
+                       (T)(1.0 / (double)c->G), u_out);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool fluid_reg_supported(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }
+
+template <typename T>
+hipError_t launch_fluid_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect, double f_scale,
+                            T *u_out) {
+  switch (c->n) {
+    case 32: return run_reg<T, 8, 4>(c, u_in, Fg, fmode, convect, f_scale, u_out);
+    case 64: return run_reg<T, 8, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out);
+    case 128: return run_reg<T, 16, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out);
+    case 256: return run_reg<T, 16, 16>(c, u_in, Fg, fmode, convect, f_scale, u_out);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_fluid_reg<float>(ib_ctx *, const float *, const float *, int, int, double, float *);
+template hipError_t launch_fluid_reg<double>(ib_ctx *, const double *, const double *, int, int, double, double *);
+
+}  // namespace ib

@@ -25,8 +25,8 @@ constexpr int kFftBuf = kFftCap + kFftCap / 8;   // payload plus the n+1 row pad
 // ---------------------------------------------------------------- RHS ----
 template <typename T>
 __global__ __launch_bounds__(256) void k_rhs(const T *__restrict__ u, const T *__restrict__ Fg,
-                                             const int32_t *__restrict__ tile_flag, int n, int log2n,
-                                             T dt, T dt_rho, T h, int convect, int fmode, T *__restrict__ r) {
+                                             const int32_t *__restrict__ tile_flag, int n, int log2n, T dt,
+                                             T dt_rho, T h, int convect, int fmode, T *__restrict__ r) {
   const int64_t G = (int64_t)n << (2 * log2n);
   const int64_t p = gtid();
   if (p >= G) return;
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_rhs(const T *__restrict__ u, const T *_
     pm[2] = ((int64_t)((z - 1) & mask) << (2 * log2n)) + rowy + x;
     pp[2] = ((int64_t)((z + 1) & mask) << (2 * log2n)) + rowy + x;
   }
-  // fmode: 0 no force, 1 force only in tiles the spread marked, 2 dense force field
+  // fmode: 0 no force, 1 force in the tiles the spread marked, 2 dense force field
   bool hasF = fmode == 2;
   if (fmode == 1) {
     const int nt = n >> 3;
@@ -281,6 +281,16 @@ hipError_t launch_fluid_solve(ib_ctx *c, const T *r, T *u_out) {
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_fluid(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect, double f_scale, T *u_out) {
+  if (fluid_reg_supported(c->n)) return launch_fluid_reg<T>(c, u_in, Fg, fmode, convect, f_scale, u_out);
+  hipError_t e = launch_rhs<T>(c, u_in, Fg, fmode, convect, f_scale, (T *)c->ws.r);
+  if (e != hipSuccess) return e;
+  return launch_fluid_solve<T>(c, (const T *)c->ws.r, u_out);
+}
+
+template hipError_t launch_fluid<float>(ib_ctx *, const float *, const float *, int, int, double, float *);
+template hipError_t launch_fluid<double>(ib_ctx *, const double *, const double *, int, int, double, double *);
 template hipError_t launch_rhs<float>(ib_ctx *, const float *, const float *, int, int, double, float *);
 template hipError_t launch_rhs<double>(ib_ctx *, const double *, const double *, int, int, double, double *);
 template hipError_t launch_fluid_solve<float>(ib_ctx *, const float *, float *);

@@ -13,6 +13,27 @@ namespace ib {
 
 constexpr int kMaxLattices = 16;
 constexpr int kTile = 8;          // spreading tile: 8^3 grid nodes per block
+constexpr int kSpreadItem = 1024; // most markers one spreading work item takes
+
+// Sorted marker record (fluid precision): fractional offset s - floor(s) per
+// dimension, the spread force (or, in the adjoint, the staged dt * Xbar), and
+// the cell's x index.  16-byte aligned so a record is a few vector loads.
+template <typename T>
+struct Rec;
+template <>
+struct alignas(16) Rec<float> {
+  float f[3];
+  int cx;
+  float F[3];
+  int pad;
+};
+template <>
+struct alignas(16) Rec<double> {
+  double f[3];
+  double F[3];
+  int cx;
+  int pad[3];
+};
 
 struct LatticeDev {
   int64_t first;
@@ -44,13 +65,22 @@ struct Workspace {
   int nblk_sort;
   int32_t *row_start;          // [n^2 + 1]
   // sorted marker records (fluid precision)
-  void *frac;                  // [3][M] fractional offset s - floor(s)
-  void *Fs;                    // [3][M] spread force
+  void *recs;                  // [M] Rec<T>
   double *Flag;                // [3][M] force workspace (f64)
   double *fb;                  // [3][M] adjoint force cotangent (f64)
   // grid
   void *Fgrid;                 // [3][G] spread force density
-  int32_t *tile_flag;          // [(n/8)^3] 1 if the tile received force
+  // spreading work list (8^3 tiles)
+  int32_t *rowtab;             // [n^2][2 (n/8 + 1)] row boundary positions
+  int32_t *tile_count;         // [ntiles] markers listed per tile
+  int32_t *tile_flag;          // [ntiles] work items of the tile (0: no force; else dense in Fgrid)
+  int32_t *tile_part;          // [ntiles] first partial of a split tile
+  int32_t *tile_item0;         // [ntiles] first work item of the tile
+  int32_t *item_tile;          // [item_cap] tile of each work item
+  int32_t *nitems;             // [2] number of work items, number of split tiles
+  int32_t *split_list;         // [ntiles] tiles with more than one item
+  int32_t *scan_tmp;           // [3 * ceil(ntiles / 1024)] per-block scan totals
+  void *partials;              // [part_cap][3][512] partial tiles of split tiles
   void *r;                     // [3][G] right-hand side
   void *spec;                  // [3][n/2+1][n][n] complex spectrum
   int32_t *nonfinite;          // [1] flag for checked mode
@@ -95,6 +125,8 @@ struct ib_ctx {
   int64_t ws_bytes = 0;
   int sort_passes = 0, digit_bits = 0;
   int sorted_buf = 0;   // which keys/vals buffer holds the sorted result
+  int spread_grid = 0;  // blocks of the persistent spreading kernel
+  int64_t item_cap = 0, part_cap = 0;
   // instrumentation
   bool timing = false;
   std::vector<ib::TimerRec> trec;
@@ -117,12 +149,20 @@ template <typename T>
 hipError_t launch_rhs(ib_ctx *c, const T *u, const T *Fgrid, int fmode, int convect, double f_scale, T *r);
 template <typename T>
 hipError_t launch_fluid_solve(ib_ctx *c, const T *r, T *u_out);           // FFT, solve, iFFT
+// The whole NS update u_out = Lop(u_in - dt A(u_in) [convect] + f_scale F): register
+// FFT passes for n in {32, 64, 128, 256}, otherwise launch_rhs + launch_fluid_solve.
+bool fluid_reg_supported(int n);
+template <typename T>
+hipError_t launch_fluid_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect, double f_scale,
+                            T *u_out);
+template <typename T>
+hipError_t launch_fluid(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect, double f_scale, T *u_out);
 template <typename T>
 hipError_t launch_interp(ib_ctx *c, const T *u, double *X_inout, double *U_out, double dt);
 
 // adjoint pieces
 template <typename T>
-hipError_t launch_adj_interp(ib_ctx *c, const T *u_np1, double *Xbar);   // stages dt*Xbar in Fs
+hipError_t launch_adj_interp(ib_ctx *c, const T *u_np1, double *Xbar);   // stages dt*Xbar in recs[].F
 template <typename T>
 hipError_t launch_adj_spread(ib_ctx *c, const T *ubar_n, const double *F, double *Xbar, double *fbar);
 hipError_t launch_hessvec(ib_ctx *c, const double *X, const double *v, double *Xbar, double *kbar);

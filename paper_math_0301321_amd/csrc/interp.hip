@@ -21,7 +21,7 @@ __device__ __forceinline__ Cell key_cell(uint32_t key, int log2n, int mask) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_interp(const uint32_t *__restrict__ keys, const int32_t *__restrict__ perm,
-                                                const T *__restrict__ frac, const T *__restrict__ u, int n,
+                                                const Rec<T> *__restrict__ recs, const T *__restrict__ u, int n,
                                                 int log2n, int64_t M, double dt, double *__restrict__ X,
                                                 double *__restrict__ U) {
   const int64_t i = gtid();
@@ -29,10 +29,11 @@ __global__ __launch_bounds__(256) void k_interp(const uint32_t *__restrict__ key
   const int mask = n - 1;
   const int64_t G = (int64_t)n << (2 * log2n);
   const Cell cc = key_cell(keys[i], log2n, mask);
+  const T f0 = recs[i].f[0], f1 = recs[i].f[1], f2 = recs[i].f[2];
   T wx[4], wy[4], wz[4];
-  phi4<T>(frac[i], wx);
-  phi4<T>(frac[M + i], wy);
-  phi4<T>(frac[2 * M + i], wz);
+  phi4<T>(f0, wx);
+  phi4<T>(f1, wy);
+  phi4<T>(f2, wz);
   T a0 = 0, a1 = 0, a2 = 0;
   for (int c3 = 0; c3 < 4; c3++) {
     const int64_t zo = (int64_t)((cc.z + c3 - 1) & mask) << (2 * log2n);
@@ -67,10 +68,9 @@ __global__ __launch_bounds__(256) void k_interp(const uint32_t *__restrict__ key
 // interpolation, a spread without the 1/h^3 factor.
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__ keys,
-                                                    const int32_t *__restrict__ perm, const T *__restrict__ frac,
+                                                    const int32_t *__restrict__ perm, Rec<T> *__restrict__ recs,
                                                     const T *__restrict__ u, int n, int log2n, int64_t M,
-                                                    double dt, double inv_h, double *__restrict__ Xbar,
-                                                    T *__restrict__ Ub_sorted) {
+                                                    double dt, double inv_h, double *__restrict__ Xbar) {
   const int64_t i = gtid();
   if (i >= M) return;
   const int mask = n - 1;
@@ -79,16 +79,18 @@ __global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__
   const int64_t q = perm[i];
   const double xb0 = Xbar[q], xb1 = Xbar[M + q], xb2 = Xbar[2 * M + q];
   const T ub0 = (T)(dt * xb0), ub1 = (T)(dt * xb1), ub2 = (T)(dt * xb2);
-  Ub_sorted[i] = ub0;
-  Ub_sorted[M + i] = ub1;
-  Ub_sorted[2 * M + i] = ub2;
+  // stage Ubar as the record's force: the transpose of interpolation is a spread
+  recs[i].F[0] = ub0;
+  recs[i].F[1] = ub1;
+  recs[i].F[2] = ub2;
+  const T f0 = recs[i].f[0], f1 = recs[i].f[1], f2 = recs[i].f[2];
   T wx[4], wy[4], wz[4], gx[4], gy[4], gz[4];
-  phi4<T>(frac[i], wx);
-  phi4<T>(frac[M + i], wy);
-  phi4<T>(frac[2 * M + i], wz);
-  dphi4<T>(frac[i], gx);
-  dphi4<T>(frac[M + i], gy);
-  dphi4<T>(frac[2 * M + i], gz);
+  phi4<T>(f0, wx);
+  phi4<T>(f1, wy);
+  phi4<T>(f2, wz);
+  dphi4<T>(f0, gx);
+  dphi4<T>(f1, gy);
+  dphi4<T>(f2, gz);
   T g0 = 0, g1 = 0, g2 = 0;
   for (int c3 = 0; c3 < 4; c3++) {
     const int64_t zo = (int64_t)((cc.z + c3 - 1) & mask) << (2 * log2n);
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__
 //   Xbar_q += sum_x (Fbar(x) . f_q) dPhi_q/dX_q / h^3.
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_spread(const uint32_t *__restrict__ keys,
-                                                    const int32_t *__restrict__ perm, const T *__restrict__ frac,
+                                                    const int32_t *__restrict__ perm, const Rec<T> *__restrict__ recs,
                                                     const T *__restrict__ ub, const double *__restrict__ F, int n,
                                                     int log2n, int64_t M, double scale, double inv_h,
                                                     double *__restrict__ Xbar, double *__restrict__ fbar) {
@@ -124,13 +126,14 @@ __global__ __launch_bounds__(256) void k_adj_spread(const uint32_t *__restrict__
   const Cell cc = key_cell(keys[i], log2n, mask);
   const int64_t q = perm[i];
   const T f0 = (T)F[q], f1 = (T)F[M + q], f2 = (T)F[2 * M + q];
+  const T r0 = recs[i].f[0], r1 = recs[i].f[1], r2 = recs[i].f[2];
   T wx[4], wy[4], wz[4], gx[4], gy[4], gz[4];
-  phi4<T>(frac[i], wx);
-  phi4<T>(frac[M + i], wy);
-  phi4<T>(frac[2 * M + i], wz);
-  dphi4<T>(frac[i], gx);
-  dphi4<T>(frac[M + i], gy);
-  dphi4<T>(frac[2 * M + i], gz);
+  phi4<T>(r0, wx);
+  phi4<T>(r1, wy);
+  phi4<T>(r2, wz);
+  dphi4<T>(r0, gx);
+  dphi4<T>(r1, gy);
+  dphi4<T>(r2, gz);
   T a0 = 0, a1 = 0, a2 = 0, g0 = 0, g1 = 0, g2 = 0;
   for (int c3 = 0; c3 < 4; c3++) {
     const int64_t zo = (int64_t)((cc.z + c3 - 1) & mask) << (2 * log2n);
@@ -163,7 +166,7 @@ hipError_t launch_interp(ib_ctx *c, const T *u, double *X_inout, double *U_out, 
   if (c->M == 0) return hipSuccess;
   PhaseScope ps(c, PH_INTERP);
   hipLaunchKernelGGL(k_interp<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
-                     c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (const T *)c->ws.frac, u, c->n,
+                     c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (const Rec<T> *)c->ws.recs, u, c->n,
                      c->log2n, c->M, dt, X_inout, U_out);
   return hipGetLastError();
 }
@@ -173,8 +176,8 @@ hipError_t launch_adj_interp(ib_ctx *c, const T *u_np1, double *Xbar) {
   if (c->M == 0) return hipSuccess;
   PhaseScope ps(c, PH_ADJ_INTERP);
   hipLaunchKernelGGL(k_adj_interp<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
-                     c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (const T *)c->ws.frac, u_np1, c->n,
-                     c->log2n, c->M, c->p.dt, 1.0 / c->h, Xbar, (T *)c->ws.Fs);
+                     c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (Rec<T> *)c->ws.recs, u_np1, c->n,
+                     c->log2n, c->M, c->p.dt, 1.0 / c->h, Xbar);
   return hipGetLastError();
 }
 
@@ -184,7 +187,7 @@ hipError_t launch_adj_spread(ib_ctx *c, const T *ubar_n, const double *F, double
   PhaseScope ps(c, PH_ADJ_SPREAD);
   const double scale = (c->p.dt / c->p.rho) / (c->h * c->h * c->h);
   hipLaunchKernelGGL(k_adj_spread<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
-                     c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (const T *)c->ws.frac, ubar_n, F, c->n,
+                     c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (const Rec<T> *)c->ws.recs, ubar_n, F, c->n,
                      c->log2n, c->M, scale, 1.0 / c->h, Xbar, fbar);
   return hipGetLastError();
 }
