@@ -271,14 +271,21 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
     const int64_t spill = (8 * M + kSpreadItem - 1) / kSpreadItem;
     c->item_cap = ntiles + spill + 1;
     c->part_cap = 2 * spill + 1;
-    c->spread_grid = (int)std::min<int64_t>(c->item_cap, 1024);
+    // spreading blocks resident at once: LDS allows 3 (FP32) or 1 (FP64) per CU
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+        ncu = prop.multiProcessorCount;
+    }
+    c->spread_grid = (int)std::min<int64_t>(c->item_cap, (int64_t)ncu * (c->fp32 ? 3 : 1));
     chk_alloc(dalloc(c, &w.rowtab, (int64_t)n * n * 2 * (n / 8 + 1)));
     chk_alloc(dalloc(c, &w.tile_count, ntiles));
     chk_alloc(dalloc(c, &w.tile_flag, ntiles));
     chk_alloc(dalloc(c, &w.tile_part, ntiles));
     chk_alloc(dalloc(c, &w.tile_item0, ntiles));
     chk_alloc(dalloc(c, &w.item_tile, c->item_cap));
-    chk_alloc(dalloc(c, &w.nitems, 2));
+    chk_alloc(dalloc(c, &w.nitems, 3));
     chk_alloc(dalloc(c, &w.split_list, ntiles));
     chk_alloc(dalloc(c, &w.scan_tmp, 3 * ((ntiles + 1023) / 1024)));
     chk_alloc(dalloc_bytes(c, &w.partials, c->part_cap * 3 * 512 * (int64_t)ts));

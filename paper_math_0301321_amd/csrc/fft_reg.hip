@@ -8,12 +8,12 @@
 // inverse of a transform done with (R1, R2) uses (R2, R1), which leaves every
 // value in the register slot it started from.
 //
-// Five passes over HBM, each reading and writing its array once:
-//   k_xf_rhs   builds r = u - dt (upwind advection) + (dt/rho) F for a block of
-//              rows (all three components) from u staged in LDS and the force
-//              the spread left, and transforms the rows (two real rows packed
-//              as one complex pencil), writing modes kx = 0 .. n/2 to
-//              spec[c][kx][z][y] (runs of 128 bytes along y);
+// Six passes over HBM, each reading and writing its array once:
+//   k_rhs_v    r = u - dt (upwind advection) + (dt/rho) F, streamed (not an
+//              FFT pass: one read of u, one write of r);
+//   k_xf       transforms rows of r (two real rows packed as one complex
+//              pencil), writing modes kx = 0 .. n/2 to spec[c][kx][z][y]
+//              (runs of 128 bytes along y);
 //   k_y        forward or inverse along y (contiguous pencils);
 //   k_z_solve  forward along z for all three components of a (kx, y-block),
 //              the diagonal viscous solve and the projection per mode in
@@ -184,39 +184,107 @@ struct XfSmem {
   static constexpr int N = R1 * R2, YB = XfCfg<T>::YB, NP = 3 * YB / 2;
   static constexpr int US = N + 8;     // staged row stride: rows of one wave's pencils fall in different banks
   static constexpr int OS = YB + 1;    // output staging stride (complex values)
-  static constexpr size_t U = sizeof(T) * 3 * (YB + 2) * US;
+  static constexpr size_t U = sizeof(T) * 3 * YB * US;
   static constexpr size_t X = sizeof(cplx<T>) * NP * R1 * (R2 + 1);
   static constexpr size_t O = sizeof(cplx<T>) * 3 * (N / 2 + 1) * OS;
   static constexpr size_t BYTES = U > X ? (U > O ? U : O) : (X > O ? X : O);
 };
 
+// Right-hand side of eq. discreteNS1, r = u - dt (upwind advection) + f_scale F,
+// streamed: one thread per 16-byte run of x values of one (y, z) for all three
+// components; every load (node, both neighbours per direction, force) is
+// issued up front and the upwind side is chosen afterwards by select.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rhs_v(const T *__restrict__ u, const T *__restrict__ Fg,
+                                               const int32_t *__restrict__ tile_flag, int n, int log2n, int fmode,
+                                               int convect, T dt, T f_scale, T inv_h, T *__restrict__ r) {
+  constexpr int V = 16 / sizeof(T);
+  using VT = Vec16<T>;
+  const int64_t G = (int64_t)n << (2 * log2n);
+  const int64_t e = gtid();                 // run index
+  if (e * V >= G) return;
+  const int mask = n - 1;
+  const int64_t p = e * V;
+  const int x0 = (int)(p & mask), y = (int)((p >> log2n) & mask), z = (int)(p >> (2 * log2n));
+  const int64_t row = p - x0;
+  const int64_t ym = ((int64_t)z << (2 * log2n)) + ((int64_t)((y - 1) & mask) << log2n) + x0;
+  const int64_t yp = ((int64_t)z << (2 * log2n)) + ((int64_t)((y + 1) & mask) << log2n) + x0;
+  const int64_t zm = ((int64_t)((z - 1) & mask) << (2 * log2n)) + ((int64_t)y << log2n) + x0;
+  const int64_t zp = ((int64_t)((z + 1) & mask) << (2 * log2n)) + ((int64_t)y << log2n) + x0;
+  VT uc[3], vym[3], vyp[3], vzm[3], vzp[3], fv[3];
+  T xl[3], xr[3];
+  bool has = fmode == 2;
+  if (fmode == 1) {
+    const int nt = n >> 3;
+    has = tile_flag[((z >> 3) * nt + (y >> 3)) * nt + (x0 >> 3)] != 0;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    const T *uu = u + c * G;
+    uc[c] = *(const VT *)(uu + p);
+    if (convect) {
+      vym[c] = *(const VT *)(uu + ym);
+      vyp[c] = *(const VT *)(uu + yp);
+      vzm[c] = *(const VT *)(uu + zm);
+      vzp[c] = *(const VT *)(uu + zp);
+      xl[c] = uu[row + ((x0 - 1) & mask)];
+      xr[c] = uu[row + ((x0 + V) & mask)];
+    }
+    if (has) fv[c] = *(const VT *)(Fg + c * G + p);
+  }
+  VT out[3];
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+#pragma unroll
+    for (int i = 0; i < V; i++) {
+      const T ucc = uc[c][i];
+      T rv = ucc;
+      if (convect) {
+        const T uk0 = uc[0][i], uk1 = uc[1][i], uk2 = uc[2][i];
+        const T left = i == 0 ? xl[c] : uc[c][i - 1];
+        const T right = i == V - 1 ? xr[c] : uc[c][i + 1];
+        T acc = T(0);
+        if (uk0 > T(0)) acc += uk0 * ((ucc - left) * inv_h);
+        else if (uk0 < T(0)) acc += uk0 * ((right - ucc) * inv_h);
+        if (uk1 > T(0)) acc += uk1 * ((ucc - vym[c][i]) * inv_h);
+        else if (uk1 < T(0)) acc += uk1 * ((vyp[c][i] - ucc) * inv_h);
+        if (uk2 > T(0)) acc += uk2 * ((ucc - vzm[c][i]) * inv_h);
+        else if (uk2 < T(0)) acc += uk2 * ((vzp[c][i] - ucc) * inv_h);
+        rv = rv - dt * acc;
+      }
+      if (has) rv = rv + f_scale * fv[c][i];
+      out[c][i] = rv;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; c++) *(VT *)(r + c * G + p) = out[c];
+}
+
+// ---------------------------------------------------- pass x, forward ----
+// Real rows of r, two packed per complex pencil, to modes kx = 0 .. n/2 in
+// spec[c][kx][z][y] (runs of 128 bytes along y).
 template <typename T, int R1, int R2>
-__global__ __launch_bounds__(3 * XfCfg<T>::YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf_rhs(
-    const T *__restrict__ u, const T *__restrict__ Fg, const int32_t *__restrict__ tile_flag, int fmode,
-    int convect, T dt, T f_scale, T inv_h, const cplx<T> *__restrict__ tw, cplx<T> *__restrict__ spec) {
+__global__ __launch_bounds__(3 * XfCfg<T>::YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf(
+    const T *__restrict__ rin, const cplx<T> *__restrict__ tw, cplx<T> *__restrict__ spec) {
   using F4 = Fft4<T, R1, R2, false, false>;
   using SM = XfSmem<T, R1, R2>;
   constexpr int N = R1 * R2, P = F4::P, E = F4::E, YB = XfCfg<T>::YB, NP = 3 * YB / 2;
   constexpr int NH = N / 2 + 1, mask = N - 1, NT = NP * P, US = SM::US, OS = SM::OS;
-  constexpr int NTX = N / 8, TY = (YB + 7) / 8;
   constexpr int64_t G = (int64_t)N * N * N;
   __shared__ __attribute__((aligned(16))) unsigned char smem[SM::BYTES];
-  __shared__ int sflag[TY * NTX];
-  T *us = (T *)smem;                                   // [3][YB + 2][US]: rows y0-1 .. y0+YB
+  T *us = (T *)smem;                                   // [3][YB][US]
   const int nyb = N / YB;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int y0 = (b % nyb) * YB, z = b / nyb;
   const int tid = threadIdx.x;
-  // 1. stage u rows and the force flags of the block's tiles: all 16-byte
-  //    loads are issued before the first LDS store
+  // 1. stage the block's rows: all 16-byte loads issued before the LDS stores
   {
     using V = Vec16<T>;
-    constexpr int EPC = 16 / sizeof(T), CPR = N / EPC, TOT = 3 * (YB + 2) * CPR, IT = (TOT + NT - 1) / NT;
+    constexpr int EPC = 16 / sizeof(T), CPR = N / EPC, TOT = 3 * YB * CPR, IT = (TOT + NT - 1) / NT;
     V tmp[IT];
     auto src = [&](int e) {
-      const int row = e / CPR, x4 = e % CPR, c = row / (YB + 2), rr = row % (YB + 2);
-      const int y = (y0 - 1 + rr) & mask;
-      return (const V *)(u + c * G + ((int64_t)z * N + y) * N + x4 * EPC);
+      const int row = e / CPR, x4 = e % CPR, c = row / YB, rr = row % YB;
+      return (const V *)(rin + c * G + ((int64_t)z * N + y0 + rr) * N + x4 * EPC);
     };
     auto dst = [&](int e) { return (V *)(us + (e / CPR) * US + (e % CPR) * EPC); };
     if constexpr (TOT % NT == 0) {
@@ -233,55 +301,18 @@ __global__ __launch_bounds__(3 * XfCfg<T>::YB / 2 * (R1 < R2 ? R1 : R2)) void k_
         if (tid + k * NT < TOT) *dst(tid + k * NT) = tmp[k];
     }
   }
-  if (fmode == 1)
-    for (int e = tid; e < TY * NTX; e += NT)
-      sflag[e] = tile_flag[((z >> 3) * NTX + (y0 >> 3) + e / NTX) * NTX + e % NTX];
   __syncthreads();
-  // 2. right-hand side for this thread's values, packed two rows per pencil
+  // 2. this thread's values of its pencil (rows 2rp, 2rp+1 of component c)
   const int p = tid / P, t = tid % P;
   const int c = p / (YB / 2), rp = p % (YB / 2);
-  const int zm = (z - 1) & mask, zp = (z + 1) & mask;
   cplx<T> v[E];
 #pragma unroll
-  for (int i = 0; i < R2 / P; i++) {
+  for (int i = 0; i < R2 / P; i++)
 #pragma unroll
     for (int j = 0; j < R1; j++) {
       const int x = (t + P * i) + R2 * j;
-      T rv[2];
-#pragma unroll
-      for (int ab = 0; ab < 2; ab++) {
-        const int row = 2 * rp + ab;               // local row; staged row row + 1
-        const int y = y0 + row;
-        const T *uc = us + (c * (YB + 2) + row + 1) * US;
-        const T uk0 = us[(0 * (YB + 2) + row + 1) * US + x];
-        const T uk1 = us[(1 * (YB + 2) + row + 1) * US + x];
-        const T uk2 = us[(2 * (YB + 2) + row + 1) * US + x];
-        const T ucc = uc[x];
-        T r = ucc;
-        if (convect) {
-          // upwind side per direction: one load of the neighbour on that side
-          const T nx = uc[uk0 > T(0) ? ((x - 1) & mask) : ((x + 1) & mask)];
-          const T ny = uc[uk1 > T(0) ? x - US : x + US];
-          const T nz = u[c * G + ((int64_t)(uk2 > T(0) ? zm : zp) * N + y) * N + x];
-          T acc = T(0);
-          if (uk0 > T(0)) acc += uk0 * ((ucc - nx) * inv_h);
-          else if (uk0 < T(0)) acc += uk0 * ((nx - ucc) * inv_h);
-          if (uk1 > T(0)) acc += uk1 * ((ucc - ny) * inv_h);
-          else if (uk1 < T(0)) acc += uk1 * ((ny - ucc) * inv_h);
-          if (uk2 > T(0)) acc += uk2 * ((ucc - nz) * inv_h);
-          else if (uk2 < T(0)) acc += uk2 * ((nz - ucc) * inv_h);
-          r = r - dt * acc;
-        }
-        if (fmode != 0) {
-          const bool has = fmode == 2 || sflag[((y >> 3) - (y0 >> 3)) * NTX + (x >> 3)] != 0;
-          const T fv = has ? Fg[c * G + ((int64_t)z * N + y) * N + x] : T(0);
-          if (has) r = r + f_scale * fv;
-        }
-        rv[ab] = r;
-      }
-      v[i * R1 + j] = cplx<T>{rv[0], rv[1]};
+      v[i * R1 + j] = cplx<T>{us[(c * YB + 2 * rp) * US + x], us[(c * YB + 2 * rp + 1) * US + x]};
     }
-  }
   __syncthreads();   // the staged rows are dead; the buffer becomes pencil exchange space
   cplx<T> *xch = (cplx<T> *)smem + p * R1 * (R2 + 1);
   F4::run(v, t, xch, tw);
@@ -345,7 +376,7 @@ __global__ __launch_bounds__(256) void k_y(cplx<T> *__restrict__ spec, int64_t n
 
 // ------------------------------------------------- pass z with the solve ----
 template <typename T, int R1, int R2>
-__global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2)) void k_z_solve(
+__global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ? 2 : 1) void k_z_solve(
     cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ tw, const T *__restrict__ lam,
     const T *__restrict__ sg, T nu_dt) {
   using Ff = Fft4<T, R1, R2, false, true>;
@@ -380,15 +411,16 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2)) void k_z_solve(
     for (int k2 = 0; k2 < R2; k2++) {
       const int e = i * R2 + k2;
       const int kz = (t + P * i) + R1 * k2;
-      const T den = T(1) + nu_dt * (lxy + lam[kz]);
+      const T rden = T(1) / (T(1) + nu_dt * (lxy + lam[kz]));
       const T s2 = sg[kz];
-      cplx<T> w0{v[0][e].x / den, v[0][e].y / den};
-      cplx<T> w1{v[1][e].x / den, v[1][e].y / den};
-      cplx<T> w2{v[2][e].x / den, v[2][e].y / den};
+      cplx<T> w0{v[0][e].x * rden, v[0][e].y * rden};
+      cplx<T> w1{v[1][e].x * rden, v[1][e].y * rden};
+      cplx<T> w2{v[2][e].x * rden, v[2][e].y * rden};
       const T ss = s0 * s0 + s1 * s1 + s2 * s2;
       if (ss > T(0)) {
-        const T dr = (s0 * w0.x + s1 * w1.x + s2 * w2.x) / ss;
-        const T di = (s0 * w0.y + s1 * w1.y + s2 * w2.y) / ss;
+        const T rss = T(1) / ss;
+        const T dr = (s0 * w0.x + s1 * w1.x + s2 * w2.x) * rss;
+        const T di = (s0 * w0.y + s1 * w1.y + s2 * w2.y) * rss;
         w0.x -= s0 * dr; w0.y -= s0 * di;
         w1.x -= s1 * dr; w1.y -= s1 * di;
         w2.x -= s2 * dr; w2.y -= s2 * di;
@@ -485,9 +517,16 @@ hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect
   cplx<T> *spec = (cplx<T> *)c->ws.spec;
   const cplx<T> *tw = (const cplx<T> *)c->ws.tw;
   {
+    PhaseScope ps(c, PH_RHS);
+    constexpr int V = 16 / sizeof(T);
+    hipLaunchKernelGGL(k_rhs_v<T>, dim3((unsigned)((c->G / V + 255) / 256)), dim3(256), 0, c->stream, u_in, Fg,
+                       c->ws.tile_flag, N, c->log2n, Fg ? fmode : 0, convect, (T)c->p.dt, (T)f_scale,
+                       (T)(1.0 / c->h), (T *)c->ws.r);
+  }
+  {
     PhaseScope ps(c, PH_FFT_X);
-    hipLaunchKernelGGL((k_xf_rhs<T, R1, R2>), dim3(N * (N / YB)), dim3(3 * YB / 2 * P), 0, c->stream, u_in, Fg,
-                       c->ws.tile_flag, Fg ? fmode : 0, convect, (T)c->p.dt, (T)f_scale, (T)(1.0 / c->h), tw, spec);
+    hipLaunchKernelGGL((k_xf<T, R1, R2>), dim3(N * (N / YB)), dim3(3 * YB / 2 * P), 0, c->stream,
+                       (const T *)c->ws.r, tw, spec);
   }
   const int64_t npen = (int64_t)3 * NH * N;
   const unsigned ny = (unsigned)((npen + 256 / P - 1) / (256 / P));

@@ -77,7 +77,7 @@ struct Workspace {
   int32_t *tile_part;          // [ntiles] first partial of a split tile
   int32_t *tile_item0;         // [ntiles] first work item of the tile
   int32_t *item_tile;          // [item_cap] tile of each work item
-  int32_t *nitems;             // [2] number of work items, number of split tiles
+  int32_t *nitems;             // [3] work items, split tiles, next item to take
   int32_t *split_list;         // [ntiles] tiles with more than one item
   int32_t *scan_tmp;           // [3 * ceil(ntiles / 1024)] per-block scan totals
   void *partials;              // [part_cap][3][512] partial tiles of split tiles

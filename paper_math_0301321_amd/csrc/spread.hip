@@ -199,6 +199,7 @@ __global__ __launch_bounds__(1024) void k_tile_scan_top(int32_t *__restrict__ bl
   if (threadIdx.x == 0) {
     counts[0] = carry[0];
     counts[1] = carry[2];
+    counts[2] = 0;          // next work item for the spreading grid
   }
 }
 
@@ -253,15 +254,22 @@ __global__ __launch_bounds__(256) void k_spread(const int32_t *__restrict__ row_
                                                 const int32_t *__restrict__ tile_part,
                                                 const int32_t *__restrict__ tile_item0,
                                                 const int32_t *__restrict__ item_tile,
-                                                const int32_t *__restrict__ nitems, int n, T scale,
+                                                int32_t *__restrict__ nitems, int n, T scale,
                                                 T *__restrict__ Fgrid, T *__restrict__ partials) {
   __shared__ SpreadSmem<T> sm;
+  __shared__ int s_item;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nt = n >> 3, mask = n - 1, nj2 = 2 * (n / 8 + 1);
   const int64_t G = (int64_t)n * n * n;
   const int W = nitems[0];
   const int oa = lane & 3, ob = (lane >> 2) & 3, oc = lane >> 4;
-  for (int item = blockIdx.x; item < W; item += gridDim.x) {
+  // items are taken from a counter in index order (the grid is what fits on
+  // the device at once); each item writes fixed locations, so the result does
+  // not depend on which block takes which item
+  int32_t *next = (int32_t *)nitems + 2;
+  if (tid == 0) s_item = atomicAdd(next, 1);
+  __syncthreads();
+  for (int item = s_item; item < W;) {
     const int tile = item_tile[item];
     const int T1 = tile % nt, T2 = (tile / nt) % nt, T3 = tile / (nt * nt);
     if (tid < kRows) {
@@ -413,7 +421,9 @@ __global__ __launch_bounds__(256) void k_spread(const int32_t *__restrict__ row_
         Fgrid[c * G + base + ((int64_t)pz * n + py) * n + px] = v;
       }
     }
+    if (tid == 0) s_item = atomicAdd(next, 1);
     __syncthreads();   // LDS is reused by the next item
+    item = s_item;
   }
   (void)tile_count;
 }
