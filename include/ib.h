@@ -129,9 +129,11 @@ int ib_interp(ib_ctx *c, const double *X, const void *u, double *U);
 int ib_fluid(ib_ctx *c, void *u, const void *F_grid);
 
 /* The binning that partitions markers among grid cells (Sec. 3.3): the cell
- * of marker q is floor(X_q / h) per dimension wrapped into [0, n); key =
- * (c3*n + c2)*n + c1.  perm[i] lists marker ids by key, ties by id (stable);
- * keys_sorted[i] is the key of perm[i].  Both DEVICE arrays of length M. */
+ * of marker q is c = floor(X_q / h) per dimension wrapped into [0, n); cells
+ * are grouped in 8^3 tiles, tile = ((c3/8)*(n/8) + c2/8)*(n/8) + c1/8, and
+ * key = tile*512 + ((c3%8)*8 + c2%8)*8 + c1%8.  perm[i] lists marker ids by
+ * key, ties by id (stable); keys_sorted[i] is the key of perm[i].  Both
+ * DEVICE arrays of length M. */
 int ib_bin(ib_ctx *c, const double *X, uint32_t *keys_sorted, int32_t *perm);
 
 /* Adjoint of ib_step for convect = 0 (IB_ENOTSUP otherwise).  Inputs: X_n

@@ -112,6 +112,9 @@ def phi(r):
 
 
 def bin_markers(N, L, X):
+    """Cell-key binning of Sec. 3.3 (cells grouped in 8^3 blocks); N a multiple of 8."""
+    if N % 8 != 0:
+        raise ValueError("bin_markers: N must be a multiple of 8")
     X = _f64(X)
     M = X.shape[1]
     keys = np.zeros(M, np.uint32)

@@ -55,8 +55,10 @@ double ibo_phi(double r) {
 
 /* ------------------------------------------------------------------------
  * Binning (the grid/marker partition of Sec. 3.3).  The cell of a marker is
- * the node floor(X/h) in each dimension, wrapped periodically; markers are
- * ordered by the linear index of that node, ties by marker id.
+ * the node floor(X/h) in each dimension, wrapped periodically.  Cells are
+ * grouped in blocks of 8 x 8 x 8; markers are ordered by block (linear block
+ * index, x fastest), then by cell within the block (x fastest), ties by
+ * marker id.
  * ---------------------------------------------------------------------- */
 typedef struct { uint32_t key; int32_t id; } kv_t;
 
@@ -72,7 +74,9 @@ void ibo_bin(int N, double L, int64_t M, const double *X, uint32_t *keys_sorted,
   for (int64_t q = 0; q < M; q++) {
     int64_t c[3];
     for (int d = 0; d < 3; d++) c[d] = wrap((int64_t)floor(X[d * M + q] / h), N);
-    kv[q].key = (uint32_t)((c[2] * N + c[1]) * N + c[0]);
+    int64_t nb = N / 8;
+    int64_t blk = ((c[2] / 8) * nb + c[1] / 8) * nb + c[0] / 8;
+    kv[q].key = (uint32_t)(((blk * 8 + c[2] % 8) * 8 + c[1] % 8) * 8 + c[0] % 8);
     kv[q].id = (int32_t)q;
   }
   qsort(kv, (size_t)M, sizeof(kv_t), kv_cmp);

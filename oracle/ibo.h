@@ -34,9 +34,10 @@ extern "C" {
 /* phi(r) of Sec. 3.2; delta_h(x) = h^-3 phi(x1/h) phi(x2/h) phi(x3/h). */
 double ibo_phi(double r);
 
-/* Binning: cell of marker q is c_d = floor(X_d / h) wrapped into [0, N);
- * key = (c3 * N + c2) * N + c1.  perm lists marker ids ordered by key, ties
- * by marker id (a stable sort).  keys_sorted[i] = key of perm[i]. */
+/* Binning: cell of marker q is c_d = floor(X_d / h) wrapped into [0, N)
+ * (N a multiple of 8); with block b = ((c3/8) (N/8) + c2/8) (N/8) + c1/8,
+ * key = ((b * 8 + c3%8) * 8 + c2%8) * 8 + c1%8.  perm lists marker ids ordered
+ * by key, ties by marker id (a stable sort).  keys_sorted[i] = key of perm[i]. */
 void ibo_bin(int N, double L, int64_t M, const double *X,
              uint32_t *keys_sorted, int32_t *perm);
 

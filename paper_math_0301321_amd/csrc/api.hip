@@ -90,10 +90,10 @@ bool is_fin(double v) { return isfinite(v) != 0; }
 
 void free_ws(ib_ctx *c) {
   Workspace &w = c->ws;
-  void *ptrs[] = {w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.hist, w.row_start, w.recs, w.Flag, w.fb,
-                  w.Fgrid, w.rowtab, w.tile_count, w.tile_flag, w.tile_part, w.tile_item0, w.item_tile,
-                  w.nitems, w.split_list, w.scan_tmp, w.partials, w.r, w.spec, w.nonfinite, w.tw, w.lam, w.sgrad, w.drive_idx,
-                  w.drive_dir, w.sp_rowptr, w.sp_col, w.sp_rest};
+  void *ptrs[] = {w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.hist, w.tile_start, w.recs, w.Flag, w.fb,
+                  w.Fgrid, w.tile_nit, w.tile_item0, w.tile_touch, w.item_tile, w.nitems, w.split_list, w.scan_tmp, w.partials,
+                  w.r, w.spec, w.nonfinite, w.tw, w.lam, w.sgrad, w.drive_idx, w.drive_dir, w.sp_rowptr, w.sp_col,
+                  w.sp_rest, w.inv, w.drive_slot};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->ws = Workspace{};
@@ -226,6 +226,8 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
   c->stream = (hipStream_t)p->stream;
   const char *chk = getenv("IB_CHECK");
   c->check = chk && chk[0] == '1';
+  c->log2nt = c->log2n - 3;
+  c->ntiles = (int64_t)1 << (3 * c->log2nt);
   c->n_springs = S;
   c->n_drive = D;
   c->drive_A = e->drive_A;
@@ -259,36 +261,38 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
   chk_alloc(dalloc(c, &w.vals[0], M));
   chk_alloc(dalloc(c, &w.vals[1], M));
   chk_alloc(dalloc(c, &w.hist, sort_hist_words(M, c->digit_bits)));
-  chk_alloc(dalloc(c, &w.row_start, (int64_t)n * n + 1));
+  chk_alloc(dalloc(c, &w.tile_start, c->ntiles + 1));
+  chk_alloc(dalloc(c, &w.inv, M));
   chk_alloc(dalloc_bytes(c, &w.recs, M * (int64_t)(c->fp32 ? sizeof(Rec<float>) : sizeof(Rec<double>))));
   chk_alloc(dalloc(c, &w.Flag, 3 * M));
   chk_alloc(dalloc(c, &w.fb, 3 * M));
   chk_alloc(dalloc_bytes(c, &w.Fgrid, 3 * c->G * (int64_t)ts));
   {
-    // spreading work list: every marker is listed by at most 2^3 tiles, so the
-    // items number at most ntiles + 8M/kSpreadItem and split tiles at most twice that
-    const int64_t ntiles = (int64_t)(n / 8) * (n / 8) * (n / 8);
-    const int64_t spill = (8 * M + kSpreadItem - 1) / kSpreadItem;
-    c->item_cap = ntiles + spill + 1;
-    c->part_cap = 2 * spill + 1;
-    // spreading blocks resident at once: LDS allows 3 (FP32) or 1 (FP64) per CU
-    int dev = 0, ncu = 256;
+    // work list: a tile with K > 0 markers has ceil(K / kItem) <= K / kItem + 1 items
+    const int64_t ntiles = c->ntiles;
+    c->item_cap = std::min<int64_t>(ntiles, M) + M / kItem + 1;
+    if (c->item_cap * (int64_t)kPartStride >= (int64_t)INT32_MAX) {
+      g_create_error = "ib_create: too many markers for the spreading work list at this grid size";
+      free_ws(c);
+      delete c;
+      return IB_ENOTSUP;
+    }
+    // spreading waves resident at once: 24 KB of LDS per wave in FP32, 48 KB in FP64
+    int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) {
       hipDeviceProp_t prop;
       if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
-        ncu = prop.multiProcessorCount;
+        c->ncu = prop.multiProcessorCount;
     }
-    c->spread_grid = (int)std::min<int64_t>(c->item_cap, (int64_t)ncu * (c->fp32 ? 3 : 1));
-    chk_alloc(dalloc(c, &w.rowtab, (int64_t)n * n * 2 * (n / 8 + 1)));
-    chk_alloc(dalloc(c, &w.tile_count, ntiles));
-    chk_alloc(dalloc(c, &w.tile_flag, ntiles));
-    chk_alloc(dalloc(c, &w.tile_part, ntiles));
+    c->item_grid = (int)std::min<int64_t>(c->item_cap, (int64_t)c->ncu * (c->fp32 ? 6 : 3));
+    chk_alloc(dalloc(c, &w.tile_nit, ntiles));
     chk_alloc(dalloc(c, &w.tile_item0, ntiles));
+    chk_alloc(dalloc(c, &w.tile_touch, ntiles));
     chk_alloc(dalloc(c, &w.item_tile, c->item_cap));
-    chk_alloc(dalloc(c, &w.nitems, 3));
+    chk_alloc(dalloc(c, &w.nitems, 2));
     chk_alloc(dalloc(c, &w.split_list, ntiles));
-    chk_alloc(dalloc(c, &w.scan_tmp, 3 * ((ntiles + 1023) / 1024)));
-    chk_alloc(dalloc_bytes(c, &w.partials, c->part_cap * 3 * 512 * (int64_t)ts));
+    chk_alloc(dalloc(c, &w.scan_tmp, 2 * ((ntiles + 1023) / 1024)));
+    chk_alloc(dalloc_bytes(c, &w.partials, c->item_cap * kPartStride * (int64_t)ts));
   }
   chk_alloc(dalloc_bytes(c, &w.r, 3 * c->G * (int64_t)ts));
   chk_alloc(dalloc_bytes(c, &w.spec, 3 * nh * (int64_t)n * n * 2 * (int64_t)ts));
@@ -307,6 +311,11 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
   if (D > 0) {
     chk_alloc(hipMemcpy(w.drive_idx, e->drive_idx, sizeof(int32_t) * D, hipMemcpyHostToDevice));
     chk_alloc(hipMemcpy(w.drive_dir, e->drive_dir, sizeof(double) * 3 * D, hipMemcpyHostToDevice));
+    std::vector<int32_t> slot(M, -1);
+    for (int64_t j = 0; j < D; j++) slot[e->drive_idx[j]] = (int32_t)j;
+    chk_alloc(dalloc(c, &w.drive_slot, M));
+    if (err == hipSuccess)
+      chk_alloc(hipMemcpy(w.drive_slot, slot.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
   }
   if (S > 0) {
     // spring adjacency in CSR, neighbours of each marker in spring order
@@ -360,7 +369,7 @@ extern "C" void ib_destroy(ib_ctx *c) {
 }
 
 // ------------------------------------------------------ instrumentation ----
-static const char *kPhaseNames[PH_COUNT] = {"bin", "force", "prep", "spread", "rhs", "fft_x", "fft_y",
+static const char *kPhaseNames[PH_COUNT] = {"bin", "force", "prep", "spread", "gather", "rhs", "fft_x", "fft_y",
                                             "fft_z_solve", "fft_y_inv", "fft_x_inv", "interp", "adj_interp",
                                             "adj_spread", "hessvec"};
 
@@ -443,10 +452,8 @@ extern "C" int64_t ib_workspace_bytes(const ib_ctx *c) { return c ? c->ws_bytes 
 // -------------------------------------------------------- entry points ----
 template <typename T>
 static int step_impl(ib_ctx *c, double *X, T *u, double t, double *F_lag_out) {
-  double *F = F_lag_out ? F_lag_out : c->ws.Flag;
   IB_TRY(launch_bin(c, X));
-  IB_TRY(launch_force(c, X, drive_amp(c, t), F));
-  IB_TRY(launch_prep<T>(c, X, F));
+  IB_TRY(launch_force_rec<T>(c, X, drive_amp(c, t), F_lag_out));
   IB_TRY(launch_spread<T>(c, (T *)c->ws.Fgrid, false, 1.0 / (c->h * c->h * c->h)));
   IB_TRY(launch_fluid<T>(c, u, (const T *)c->ws.Fgrid, 1, c->p.convect, c->p.dt / c->p.rho, u));
   IB_TRY(launch_interp<T>(c, u, X, nullptr, c->p.dt));
@@ -533,8 +540,7 @@ static int adjoint_impl(ib_ctx *c, const double *X_n, const T *u_np1, double t, 
                         double *kbar) {
   // forward quantities at X^n: binning, weights, force f^n
   IB_TRY(launch_bin(c, X_n));
-  IB_TRY(launch_force(c, X_n, drive_amp(c, t), c->ws.Flag));
-  IB_TRY(launch_prep<T>(c, X_n, nullptr));
+  IB_TRY(launch_force_rec<T>(c, X_n, drive_amp(c, t), c->ws.Flag));
   // interpolation / move: phi' term into Xbar, stage Ubar = dt Xbar
   IB_TRY(launch_adj_interp<T>(c, u_np1, Xbar));
   // transpose of interpolation: ubar_tot = ubar + S(Ubar) h^3

@@ -1,13 +1,14 @@
 // Marker binning: the partition of markers among grid cells (Sec. 3.3).
 //
 // The paper partitions fluid and material grids so that no two processors
-// touch the same data.  Here the partition is a cell key per marker,
-// key = (c3*n + c2)*n + c1 with c = floor(X/h) wrapped into [0, n), and a
-// stable LSD radix sort of marker ids by key.  Sorting makes the markers of
-// one grid row (fixed c2, c3) contiguous and ordered by c1, so the spreading
-// kernel can gather a tile's markers row by row with two binary searches per
-// row (row_start gives each row's range).  Everything here is integer work
-// and bit-exact.
+// touch the same data.  Here the partition is a cell key per marker: cells
+// are grouped in 8^3 tiles and key = tile * 512 + cell within the tile, with
+// c = floor(X/h) wrapped into [0, n); a stable LSD radix sort orders marker
+// ids by key.  Sorting makes the markers of one tile a contiguous run of the
+// sorted order (tile_start gives each tile's range), ordered by cell.  The
+// runs are then cut into work items of at most kItem markers, which the
+// spreading and interpolation kernels take one per wave.  Everything here is
+// integer work and bit-exact.
 #include "dev_common.h"
 #include "ib_internal.h"
 
@@ -18,18 +19,17 @@ constexpr int kSortItems = 16;
 constexpr int kSortChunk = kSortThreads * kSortItems;
 
 __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ X, int64_t M, double h,
-                                              int n, int log2n, uint32_t *__restrict__ keys,
+                                              int n, int log2nt, uint32_t *__restrict__ keys,
                                               int32_t *__restrict__ vals) {
   const int64_t q = gtid();
   if (q >= M) return;
-  uint32_t key = 0;
-  for (int d = 2; d >= 0; d--) {
+  int c[3];
+  for (int d = 0; d < 3; d++) {
     const double s = X[d * M + q] / h;
-    int64_t c = isfinite(s) ? (int64_t)floor(s) : 0;
-    c &= (int64_t)(n - 1);                 // periodic wrap (n is a power of two)
-    key = (key << log2n) | (uint32_t)c;
+    int64_t cd = isfinite(s) ? (int64_t)floor(s) : 0;
+    c[d] = (int)(cd & (int64_t)(n - 1));   // periodic wrap (n is a power of two)
   }
-  keys[q] = key;
+  keys[q] = cell_key(c[0], c[1], c[2], log2nt);
   vals[q] = (int32_t)q;
 }
 
@@ -89,13 +89,15 @@ __global__ __launch_bounds__(256) void k_radix_scan_digit(uint32_t *__restrict__
 }
 
 // Stable scatter: items are ranked in their original order (round, wave, lane)
-// using wave ballots to find lanes holding the same digit.
+// using wave ballots to find lanes holding the same digit.  The last pass also
+// records each marker's sorted position (inv).
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restrict__ kin,
                                                        const int32_t *__restrict__ vin,
                                                        uint32_t *__restrict__ kout,
                                                        int32_t *__restrict__ vout, int64_t M, int shift,
                                                        int bits, const uint32_t *__restrict__ hist,
-                                                       const uint32_t *__restrict__ dtot, int nblk) {
+                                                       const uint32_t *__restrict__ dtot, int nblk,
+                                                       int32_t *__restrict__ inv) {
   const int R = 1 << bits;
   __shared__ uint32_t dbase[256];
   __shared__ uint32_t run[256];
@@ -142,33 +144,121 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
     if (valid) {
       kout[pos] = key;
       vout[pos] = val;
+      if (inv) inv[val] = (int32_t)pos;
     }
   }
 }
 
-// row_start[r] = first sorted position whose key is >= r * n, r in [0, n^2].
-__global__ __launch_bounds__(256) void k_row_start(const uint32_t *__restrict__ keys, int64_t M,
-                                                   int log2n, int64_t nrows, int32_t *__restrict__ row_start) {
-  const int64_t r = gtid();
-  if (r > nrows) return;
-  const uint64_t target = (uint64_t)r << log2n;
+// tile_start[t] = first sorted position whose key is >= t * 512, t in [0, ntiles].
+__global__ __launch_bounds__(256) void k_tile_start(const uint32_t *__restrict__ keys, int64_t M, int64_t ntiles,
+                                                    int32_t *__restrict__ tile_start) {
+  const int64_t t = gtid();
+  if (t > ntiles) return;
+  const uint64_t target = (uint64_t)t << 9;
   int64_t lo = 0, hi = M;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
     if ((uint64_t)keys[mid] < target) lo = mid + 1;
     else hi = mid;
   }
-  row_start[r] = (int32_t)lo;
+  tile_start[t] = (int32_t)lo;
+}
+
+// ---------------------------------------------------------- work list ----
+// Items per tile: ceil(K / kItem) for the K markers of the tile; item j of a
+// tile covers its markers [j kItem, min((j + 1) kItem, K)).  Tiles with more
+// than one item ("split") are listed for the reduction of their halos.  Both
+// are numbered by exclusive scans over the tiles in three launches: per-block
+// scans of 1024 tiles, a scan of the block totals, and the writes (tile_nit,
+// tile_item0, item_tile, split_list).
+__device__ __forceinline__ int2 tile_items(const int32_t *tile_start, int64_t t, int64_t ntiles) {
+  if (t >= ntiles) return make_int2(0, 0);
+  const int K = tile_start[t + 1] - tile_start[t];
+  const int it = (K + kItem - 1) / kItem;
+  return make_int2(it, it > 1 ? 1 : 0);
+}
+
+// Exclusive scan of two values per thread over a 1024-thread block.
+__device__ __forceinline__ int2 scan1024(int2 v, int2 *wsum, int2 *total) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int2 incl = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int x = __shfl_up(incl.x, o, 64), y = __shfl_up(incl.y, o, 64);
+    if (lane >= o) {
+      incl.x += x;
+      incl.y += y;
+    }
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int2 wb = make_int2(0, 0), tot = make_int2(0, 0);
+  for (int i = 0; i < 16; i++) {
+    if (i < w) {
+      wb.x += wsum[i].x;
+      wb.y += wsum[i].y;
+    }
+    tot.x += wsum[i].x;
+    tot.y += wsum[i].y;
+  }
+  __syncthreads();
+  *total = tot;
+  return make_int2(wb.x + incl.x - v.x, wb.y + incl.y - v.y);
+}
+
+__global__ __launch_bounds__(1024) void k_item_scan_blocks(const int32_t *__restrict__ tile_start, int64_t ntiles,
+                                                           int2 *__restrict__ block_tot) {
+  __shared__ int2 wsum[16];
+  int2 tot;
+  (void)scan1024(tile_items(tile_start, (int64_t)blockIdx.x * 1024 + threadIdx.x, ntiles), wsum, &tot);
+  if (threadIdx.x == 0) block_tot[blockIdx.x] = tot;
+}
+
+// counts[0] = work items, counts[1] = split tiles
+__global__ __launch_bounds__(1024) void k_item_scan_top(int2 *__restrict__ block_tot, int nblk,
+                                                        int32_t *__restrict__ counts) {
+  __shared__ int2 wsum[16];
+  int2 carry = make_int2(0, 0);
+  for (int base = 0; base < nblk; base += 1024) {
+    const int b = base + threadIdx.x;
+    int2 tot;
+    const int2 off = scan1024(b < nblk ? block_tot[b] : make_int2(0, 0), wsum, &tot);
+    if (b < nblk) block_tot[b] = make_int2(carry.x + off.x, carry.y + off.y);
+    carry.x += tot.x;
+    carry.y += tot.y;
+  }
+  if (threadIdx.x == 0) {
+    counts[0] = carry.x;
+    counts[1] = carry.y;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_item_scan_write(const int32_t *__restrict__ tile_start, int64_t ntiles,
+                                                          const int2 *__restrict__ block_off,
+                                                          int32_t *__restrict__ tile_nit,
+                                                          int32_t *__restrict__ tile_item0,
+                                                          int32_t *__restrict__ item_tile,
+                                                          int32_t *__restrict__ split_list) {
+  __shared__ int2 wsum[16];
+  const int64_t t = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  const int2 v = tile_items(tile_start, t, ntiles);
+  int2 tot;
+  const int2 off = scan1024(v, wsum, &tot);
+  if (t < ntiles) {
+    const int i0 = block_off[blockIdx.x].x + off.x;
+    tile_nit[t] = v.x;
+    tile_item0[t] = i0;
+    for (int j = 0; j < v.x; j++) item_tile[i0 + j] = (int32_t)t;
+    if (v.y) split_list[block_off[blockIdx.x].y + off.y] = (int32_t)t;
+  }
 }
 
 hipError_t launch_bin(ib_ctx *c, const double *X) {
   PhaseScope ps(c, PH_BIN);
   const int64_t M = c->M;
   Workspace &ws = c->ws;
-  const int nrows = c->n * c->n;
   if (M > 0) {
     const int gb = (int)((M + 255) / 256);
-    hipLaunchKernelGGL(k_keys, dim3(gb), dim3(256), 0, c->stream, X, M, c->h, c->n, c->log2n,
+    hipLaunchKernelGGL(k_keys, dim3(gb), dim3(256), 0, c->stream, X, M, c->h, c->n, c->log2nt,
                        ws.keys[0], ws.vals[0]);
     int cur = 0;
     const int bits = c->digit_bits, R = 1 << bits;
@@ -181,15 +271,22 @@ hipError_t launch_bin(ib_ctx *c, const double *X) {
                          ws.hist + (int64_t)R * nblk);
       hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kSortThreads), 0, c->stream, ws.keys[cur],
                          ws.vals[cur], ws.keys[cur ^ 1], ws.vals[cur ^ 1], M, shift, bits, ws.hist,
-                         ws.hist + (int64_t)R * nblk, nblk);
+                         ws.hist + (int64_t)R * nblk, nblk, pass == c->sort_passes - 1 ? ws.inv : nullptr);
       cur ^= 1;
     }
     c->sorted_buf = cur;
   } else {
     c->sorted_buf = 0;
   }
-  hipLaunchKernelGGL(k_row_start, dim3((nrows + 1 + 255) / 256), dim3(256), 0, c->stream,
-                     ws.keys[c->sorted_buf], M, c->log2n, (int64_t)nrows, ws.row_start);
+  const int64_t nt = c->ntiles;
+  hipLaunchKernelGGL(k_tile_start, dim3((unsigned)((nt + 1 + 255) / 256)), dim3(256), 0, c->stream,
+                     ws.keys[c->sorted_buf], M, nt, ws.tile_start);
+  const int nsb = (int)((nt + 1023) / 1024);
+  int2 *tmp = (int2 *)ws.scan_tmp;
+  hipLaunchKernelGGL(k_item_scan_blocks, dim3(nsb), dim3(1024), 0, c->stream, ws.tile_start, nt, tmp);
+  hipLaunchKernelGGL(k_item_scan_top, dim3(1), dim3(1024), 0, c->stream, tmp, nsb, ws.nitems);
+  hipLaunchKernelGGL(k_item_scan_write, dim3(nsb), dim3(1024), 0, c->stream, ws.tile_start, nt, tmp, ws.tile_nit,
+                     ws.tile_item0, ws.item_tile, ws.split_list);
   return hipGetLastError();
 }
 

@@ -196,7 +196,7 @@ struct XfSmem {
 // issued up front and the upwind side is chosen afterwards by select.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rhs_v(const T *__restrict__ u, const T *__restrict__ Fg,
-                                               const int32_t *__restrict__ tile_flag, int n, int log2n, int fmode,
+                                               const int32_t *__restrict__ tile_touch, int n, int log2n, int fmode,
                                                int convect, T dt, T f_scale, T inv_h, T *__restrict__ r) {
   constexpr int V = 16 / sizeof(T);
   using VT = Vec16<T>;
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void k_rhs_v(const T *__restrict__ u, const T 
   bool has = fmode == 2;
   if (fmode == 1) {
     const int nt = n >> 3;
-    has = tile_flag[((z >> 3) * nt + (y >> 3)) * nt + (x0 >> 3)] != 0;
+    has = tile_touch[((z >> 3) * nt + (y >> 3)) * nt + (x0 >> 3)] != 0;
   }
 #pragma unroll
   for (int c = 0; c < 3; c++) {
@@ -520,7 +520,7 @@ hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect
     PhaseScope ps(c, PH_RHS);
     constexpr int V = 16 / sizeof(T);
     hipLaunchKernelGGL(k_rhs_v<T>, dim3((unsigned)((c->G / V + 255) / 256)), dim3(256), 0, c->stream, u_in, Fg,
-                       c->ws.tile_flag, N, c->log2n, Fg ? fmode : 0, convect, (T)c->p.dt, (T)f_scale,
+                       c->ws.tile_touch, N, c->log2n, Fg ? fmode : 0, convect, (T)c->p.dt, (T)f_scale,
                        (T)(1.0 / c->h), (T *)c->ws.r);
   }
   {

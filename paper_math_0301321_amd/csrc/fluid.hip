@@ -25,7 +25,7 @@ constexpr int kFftBuf = kFftCap + kFftCap / 8;   // payload plus the n+1 row pad
 // ---------------------------------------------------------------- RHS ----
 template <typename T>
 __global__ __launch_bounds__(256) void k_rhs(const T *__restrict__ u, const T *__restrict__ Fg,
-                                             const int32_t *__restrict__ tile_flag, int n, int log2n, T dt,
+                                             const int32_t *__restrict__ tile_touch, int n, int log2n, T dt,
                                              T dt_rho, T h, int convect, int fmode, T *__restrict__ r) {
   const int64_t G = (int64_t)n << (2 * log2n);
   const int64_t p = gtid();
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void k_rhs(const T *__restrict__ u, const T *_
   bool hasF = fmode == 2;
   if (fmode == 1) {
     const int nt = n >> 3;
-    hasF = tile_flag[((z >> 3) * nt + (y >> 3)) * nt + (x >> 3)] != 0;
+    hasF = tile_touch[((z >> 3) * nt + (y >> 3)) * nt + (x >> 3)] != 0;
   }
   for (int c = 0; c < 3; c++) {
     const T *uc = u + c * G;
@@ -229,7 +229,7 @@ hipError_t launch_rhs(ib_ctx *c, const T *u, const T *Fgrid, int fmode, int conv
   PhaseScope ps(c, PH_RHS);
   const double dt = c->p.dt;
   hipLaunchKernelGGL(k_rhs<T>, dim3((unsigned)((c->G + 255) / 256)), dim3(256), 0, c->stream, u, Fgrid,
-                     c->ws.tile_flag, c->n, c->log2n, (T)dt, (T)f_scale, (T)c->h, convect, Fgrid ? fmode : 0, r);
+                     c->ws.tile_touch, c->n, c->log2n, (T)dt, (T)f_scale, (T)c->h, convect, Fgrid ? fmode : 0, r);
   return hipGetLastError();
 }
 

@@ -4,8 +4,9 @@
 // edges, bend triples in which it is an end or the centre, springs through a
 // CSR adjacency, its tether), so no two threads write the same output and the
 // result does not depend on scheduling.  Each edge / triple is evaluated once
-// per marker it touches.  The window drive is added by a second kernel over
-// the (distinct) driven markers.  Force laws: see include/ib.h.
+// per marker it touches; the window drive is added through a per-marker slot
+// of the drive list.  In the time step the same pass also writes the marker's
+// sorted record for the spreading.  Force laws: see include/ib.h.
 #include "dev_common.h"
 #include "ib_internal.h"
 
@@ -84,12 +85,10 @@ __device__ void lattice_force(const Material &m, const LatticeDev &L, const doub
   }
 }
 
-__global__ __launch_bounds__(256) void k_force(Material m, const double *__restrict__ X,
-                                               double *__restrict__ F) {
-  const int64_t q = gtid();
+// Elastic force on marker q (every term except the drive).
+__device__ __forceinline__ V3 marker_force(const Material &m, const double *__restrict__ X, int64_t q,
+                                           const V3 &xq) {
   const int64_t M = m.M;
-  if (q >= M) return;
-  const V3 xq = ld3(X, M, q);
   V3 f{0.0, 0.0, 0.0};
   for (int l = 0; l < m.lat.n; l++) {
     const LatticeDev &L = m.lat.l[l];
@@ -120,33 +119,93 @@ __global__ __launch_bounds__(256) void k_force(Material m, const double *__restr
       f.z += -kw * (xq.z - y.z);
     }
   }
+  return f;
+}
+
+// Window drive (Sec. 4) on marker q: amp = A sin(2 pi f t) evaluated on the
+// host in FP64, times w_q, along the marker's direction (slot j of the drive list).
+__device__ __forceinline__ void add_drive(const Material &m, const int32_t *__restrict__ slot,
+                                          const double *__restrict__ dir, int64_t D, double amp, int64_t q, V3 &f) {
+  if (!slot || amp == 0.0) return;
+  const int j = slot[q];
+  if (j < 0) return;
+  const double s = amp * m.w[q];
+  f.x += s * dir[j];
+  f.y += s * dir[D + j];
+  f.z += s * dir[2 * D + j];
+}
+
+__global__ __launch_bounds__(256) void k_force(Material m, const double *__restrict__ X,
+                                               const int32_t *__restrict__ slot, const double *__restrict__ dir,
+                                               int64_t D, double amp, double *__restrict__ F) {
+  const int64_t q = gtid();
+  const int64_t M = m.M;
+  if (q >= M) return;
+  const V3 xq = ld3(X, M, q);
+  V3 f = marker_force(m, X, q, xq);
+  add_drive(m, slot, dir, D, amp, q, f);
   F[q] = f.x;
   F[M + q] = f.y;
   F[2 * M + q] = f.z;
 }
 
-// Window drive (Sec. 4): amp = A sin(2 pi f t) evaluated on the host in FP64.
-__global__ __launch_bounds__(256) void k_drive(const int32_t *__restrict__ idx, const double *__restrict__ dir,
-                                               int64_t D, const double *__restrict__ w, double amp, int64_t M,
-                                               double *__restrict__ F) {
-  const int64_t j = gtid();
-  if (j >= D) return;
-  const int64_t q = idx[j];
-  const double s = amp * w[q];
-  F[q] += s * dir[j];
-  F[M + q] += s * dir[D + j];
-  F[2 * M + q] += s * dir[2 * D + j];
+// Force and sorted record in one pass: the record of marker q (fractional
+// offsets and cell key from X as the binning forms them, force in the fluid
+// precision) goes to its sorted position inv[q]; the FP64 force is written
+// only when asked for.
+template <typename T>
+__global__ __launch_bounds__(256) void k_force_rec(Material m, const double *__restrict__ X,
+                                                   const int32_t *__restrict__ slot, const double *__restrict__ dir,
+                                                   int64_t D, double amp, const int32_t *__restrict__ inv, double h,
+                                                   int n, int log2nt, double *__restrict__ F, Rec<T> *__restrict__ recs) {
+  const int64_t q = gtid();
+  const int64_t M = m.M;
+  if (q >= M) return;
+  const V3 xq = ld3(X, M, q);
+  V3 f = marker_force(m, X, q, xq);
+  add_drive(m, slot, dir, D, amp, q, f);
+  if (F) {
+    F[q] = f.x;
+    F[M + q] = f.y;
+    F[2 * M + q] = f.z;
+  }
+  Rec<T> r{};
+  const double xs[3] = {xq.x, xq.y, xq.z};
+  int cc[3];
+  for (int d = 0; d < 3; d++) {
+    const double s = xs[d] / h;
+    const double fl = floor(s);
+    r.f[d] = (T)(s - fl);
+    const int64_t ci = isfinite(s) ? (int64_t)fl : 0;
+    cc[d] = (int)(ci & (int64_t)(n - 1));
+  }
+  r.F[0] = (T)f.x;
+  r.F[1] = (T)f.y;
+  r.F[2] = (T)f.z;
+  r.key = cell_key(cc[0], cc[1], cc[2], log2nt);
+  recs[inv[q]] = r;
 }
 
 hipError_t launch_force(ib_ctx *c, const double *X, double amp, double *F) {
   if (c->M == 0) return hipSuccess;
   PhaseScope ps(c, PH_FORCE);
-  hipLaunchKernelGGL(k_force, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream, c->mat, X, F);
-  if (c->n_drive > 0 && amp != 0.0)
-    hipLaunchKernelGGL(k_drive, dim3((unsigned)((c->n_drive + 255) / 256)), dim3(256), 0, c->stream,
-                       c->ws.drive_idx, c->ws.drive_dir, c->n_drive, c->mat.w, amp, c->M, F);
+  hipLaunchKernelGGL(k_force, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream, c->mat, X,
+                     c->ws.drive_slot, c->ws.drive_dir, c->n_drive, amp, F);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_force_rec(ib_ctx *c, const double *X, double amp, double *F) {
+  if (c->M == 0) return hipSuccess;
+  PhaseScope ps(c, PH_FORCE);
+  hipLaunchKernelGGL(k_force_rec<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream, c->mat, X,
+                     c->ws.drive_slot, c->ws.drive_dir, c->n_drive, amp, c->ws.inv, c->h, c->n, c->log2nt, F,
+                     (Rec<T> *)c->ws.recs);
+  return hipGetLastError();
+}
+
+template hipError_t launch_force_rec<float>(ib_ctx *, const double *, double, double *);
+template hipError_t launch_force_rec<double>(ib_ctx *, const double *, double, double *);
 
 }  // namespace ib
 

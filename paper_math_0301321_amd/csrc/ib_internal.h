@@ -12,18 +12,21 @@
 namespace ib {
 
 constexpr int kMaxLattices = 16;
-constexpr int kTile = 8;          // spreading tile: 8^3 grid nodes per block
-constexpr int kSpreadItem = 1024; // most markers one spreading work item takes
+constexpr int kTile = 8;          // cells per tile edge: markers are binned by 8^3-cell tiles
+constexpr int kHalo = 11;         // nodes per edge of a tile's stencil halo (cells -1 .. 9)
+constexpr int kHalo3 = kHalo * kHalo * kHalo;
+constexpr int kItem = 512;        // markers per work item (the last item of a tile takes the rest)
+constexpr int kPartStride = 3996;  // values per item halo: 3 * 11^3 padded to a multiple of 4
 
 // Sorted marker record (fluid precision): fractional offset s - floor(s) per
 // dimension, the spread force (or, in the adjoint, the staged dt * Xbar), and
-// the cell's x index.  16-byte aligned so a record is a few vector loads.
+// the cell key.  16-byte aligned so a record is a few vector loads.
 template <typename T>
 struct Rec;
 template <>
 struct alignas(16) Rec<float> {
   float f[3];
-  int cx;
+  uint32_t key;
   float F[3];
   int pad;
 };
@@ -31,9 +34,22 @@ template <>
 struct alignas(16) Rec<double> {
   double f[3];
   double F[3];
-  int cx;
+  uint32_t key;
   int pad[3];
 };
+
+// Cell key (binning of Sec. 3.3): cells are grouped in 8^3 tiles;
+// key = tile * 512 + (lz * 8 + ly) * 8 + lx with l the cell within the tile and
+// tile = (tz * nt + ty) * nt + tx, nt = n / 8.  A tile's markers are one
+// contiguous run of the sorted order.
+__host__ __device__ __forceinline__ uint32_t cell_key(int cx, int cy, int cz, int log2nt) {
+  const uint32_t tile = ((uint32_t)(cz >> 3) << (2 * log2nt)) | ((uint32_t)(cy >> 3) << log2nt) | (uint32_t)(cx >> 3);
+  return (tile << 9) | ((uint32_t)(cz & 7) << 6) | ((uint32_t)(cy & 7) << 3) | (uint32_t)(cx & 7);
+}
+// Position of a cell's stencil origin (node cell - 1) in its tile's 11^3 halo.
+__host__ __device__ __forceinline__ int halo_base(uint32_t key) {
+  return (int)((key >> 6) & 7) * (kHalo * kHalo) + (int)((key >> 3) & 7) * kHalo + (int)(key & 7);
+}
 
 struct LatticeDev {
   int64_t first;
@@ -63,24 +79,23 @@ struct Workspace {
   int32_t *vals[2];
   uint32_t *hist;
   int nblk_sort;
-  int32_t *row_start;          // [n^2 + 1]
+  int32_t *tile_start;         // [ntiles + 1] first sorted position of each tile
+  int32_t *inv;                // [M] sorted position of each marker
   // sorted marker records (fluid precision)
   void *recs;                  // [M] Rec<T>
   double *Flag;                // [3][M] force workspace (f64)
   double *fb;                  // [3][M] adjoint force cotangent (f64)
   // grid
   void *Fgrid;                 // [3][G] spread force density
-  // spreading work list (8^3 tiles)
-  int32_t *rowtab;             // [n^2][2 (n/8 + 1)] row boundary positions
-  int32_t *tile_count;         // [ntiles] markers listed per tile
-  int32_t *tile_flag;          // [ntiles] work items of the tile (0: no force; else dense in Fgrid)
-  int32_t *tile_part;          // [ntiles] first partial of a split tile
+  // work list over tiles: each tile's markers cut into items of <= kItem
+  int32_t *tile_nit;           // [ntiles] work items of the tile
   int32_t *tile_item0;         // [ntiles] first work item of the tile
+  int32_t *tile_touch;         // [ntiles] 1 if the spread force reaches the tile (dense in Fgrid), else 0
   int32_t *item_tile;          // [item_cap] tile of each work item
-  int32_t *nitems;             // [3] work items, split tiles, next item to take
+  int32_t *nitems;             // [2] work items, split tiles
   int32_t *split_list;         // [ntiles] tiles with more than one item
-  int32_t *scan_tmp;           // [3 * ceil(ntiles / 1024)] per-block scan totals
-  void *partials;              // [part_cap][3][512] partial tiles of split tiles
+  int32_t *scan_tmp;           // [2 ceil(ntiles / 1024)] per-block scan totals
+  void *partials;              // [item_cap][kPartStride] each item's spread halo, [3][11^3] + pad
   void *r;                     // [3][G] right-hand side
   void *spec;                  // [3][n/2+1][n][n] complex spectrum
   int32_t *nonfinite;          // [1] flag for checked mode
@@ -91,6 +106,7 @@ struct Workspace {
   // drive
   int32_t *drive_idx;          // [D]
   double *drive_dir;           // [3][D]
+  int32_t *drive_slot;         // [M] index into the drive list, -1 if not driven (null when D = 0)
   // spring adjacency
   int32_t *sp_rowptr, *sp_col;
   double *sp_rest;
@@ -98,7 +114,7 @@ struct Workspace {
 
 // Phases timed by the optional HIP-event instrumentation.
 enum Phase {
-  PH_BIN = 0, PH_FORCE, PH_PREP, PH_SPREAD, PH_RHS, PH_FFT_X, PH_FFT_Y, PH_FFT_Z_SOLVE, PH_FFT_Y_INV,
+  PH_BIN = 0, PH_FORCE, PH_PREP, PH_SPREAD, PH_GATHER, PH_RHS, PH_FFT_X, PH_FFT_Y, PH_FFT_Z_SOLVE, PH_FFT_Y_INV,
   PH_FFT_X_INV, PH_INTERP, PH_ADJ_INTERP, PH_ADJ_SPREAD, PH_HESSVEC, PH_COUNT
 };
 
@@ -125,8 +141,11 @@ struct ib_ctx {
   int64_t ws_bytes = 0;
   int sort_passes = 0, digit_bits = 0;
   int sorted_buf = 0;   // which keys/vals buffer holds the sorted result
-  int spread_grid = 0;  // blocks of the persistent spreading kernel
-  int64_t item_cap = 0, part_cap = 0;
+  int log2nt = 0;       // log2(n / 8)
+  int64_t ntiles = 0;
+  int ncu = 256;        // compute units of the device
+  int item_grid = 0;    // single-wave blocks of the spreading kernel
+  int64_t item_cap = 0;
   // instrumentation
   bool timing = false;
   std::vector<ib::TimerRec> trec;
@@ -138,12 +157,15 @@ struct ib_ctx {
 namespace ib {
 
 // ---- launchers (each returns hipError_t of the launch) ----
-hipError_t launch_bin(ib_ctx *c, const double *X);   // -> keys/vals[sorted_buf], row_start
+hipError_t launch_bin(ib_ctx *c, const double *X);   // -> keys/vals[sorted_buf], inv, tile_start, work list
 hipError_t launch_force(ib_ctx *c, const double *X, double amp, double *F);
+// force and the sorted records in one pass (needs the binning); F nullable
+template <typename T>
+hipError_t launch_force_rec(ib_ctx *c, const double *X, double amp, double *F);
 template <typename T>
 hipError_t launch_prep(ib_ctx *c, const double *X, const double *F);      // sorted records
 template <typename T>
-hipError_t launch_spread(ib_ctx *c, T *Fgrid, bool dense_zero, double scale);  // -> Fgrid, tile_flag
+hipError_t launch_spread(ib_ctx *c, T *Fgrid, bool dense_zero, double scale);  // -> Fgrid, tile_touch
 // r = u - dt A(u) [convect] + f_scale F; fmode 0: no F, 1: F in marked tiles, 2: dense F
 template <typename T>
 hipError_t launch_rhs(ib_ctx *c, const T *u, const T *Fgrid, int fmode, int convect, double f_scale, T *r);

@@ -1,11 +1,15 @@
 // Interpolation and marker move, sub-step 4 (eq. discreteX), and the two
 // gathers of the adjoint step that share its stencil.
 //
-// One thread per marker in sorted (cell) order, so neighbouring threads read
-// overlapping 4^3 stencils of the grid and the loads coalesce in L1/L2.  The
-// weights come from the same X^n fractional offsets the spread used (eq.
-// discreteX interpolates u^{n+1} at X^n).  Velocities accumulate in the fluid
-// precision; the position update X += dt U is FP64.
+// k_interp: blocks of 256 threads take the work items of the binning (up to
+// kItem markers of one 8^3-cell tile) round robin.  For each item the block
+// stages the velocity on the tile's 11^3 halo (nodes -1 .. 9, wrapped) in LDS,
+// three components per node; then each thread interpolates one marker at a
+// time from LDS.  The weights come from the same X^n fractional offsets the
+// spread used (eq. discreteX interpolates u^{n+1} at X^n).  Velocities
+// accumulate in the fluid precision; the position update X += dt U is FP64.
+#include <algorithm>
+
 #include "dev_common.h"
 #include "ib_internal.h"
 
@@ -15,50 +19,109 @@ struct Cell {
   int x, y, z;
 };
 
-__device__ __forceinline__ Cell key_cell(uint32_t key, int log2n, int mask) {
-  return Cell{(int)(key & (uint32_t)mask), (int)((key >> log2n) & (uint32_t)mask), (int)(key >> (2 * log2n))};
+// Cell of a key: tile * 512 + (lz * 8 + ly) * 8 + lx.
+__device__ __forceinline__ Cell key_cell(uint32_t key, int log2nt) {
+  const uint32_t tile = key >> 9, tmask = (1u << log2nt) - 1u;
+  return Cell{(int)(((tile & tmask) << 3) | (key & 7u)), (int)((((tile >> log2nt) & tmask) << 3) | ((key >> 3) & 7u)),
+              (int)(((tile >> (2 * log2nt)) << 3) | ((key >> 6) & 7u))};
 }
 
+__device__ __forceinline__ void wave_sync_lds_i() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// velocity of one halo node, padded to a 16-byte (FP32) or 32-byte (FP64) vector
 template <typename T>
-__global__ __launch_bounds__(256) void k_interp(const uint32_t *__restrict__ keys, const int32_t *__restrict__ perm,
-                                                const Rec<T> *__restrict__ recs, const T *__restrict__ u, int n,
-                                                int log2n, int64_t M, double dt, double *__restrict__ X,
-                                                double *__restrict__ U) {
-  const int64_t i = gtid();
-  if (i >= M) return;
-  const int mask = n - 1;
-  const int64_t G = (int64_t)n << (2 * log2n);
-  const Cell cc = key_cell(keys[i], log2n, mask);
-  const T f0 = recs[i].f[0], f1 = recs[i].f[1], f2 = recs[i].f[2];
-  T wx[4], wy[4], wz[4];
-  phi4<T>(f0, wx);
-  phi4<T>(f1, wy);
-  phi4<T>(f2, wz);
-  T a0 = 0, a1 = 0, a2 = 0;
-  for (int c3 = 0; c3 < 4; c3++) {
-    const int64_t zo = (int64_t)((cc.z + c3 - 1) & mask) << (2 * log2n);
-    for (int c2 = 0; c2 < 4; c2++) {
-      const int64_t yo = zo + ((int64_t)((cc.y + c2 - 1) & mask) << log2n);
-      const T wyz = wy[c2];
-      for (int c1 = 0; c1 < 4; c1++) {
-        const int64_t p = yo + ((cc.x + c1 - 1) & mask);
-        const T wt = (wx[c1] * wyz) * wz[c3];
-        a0 += u[p] * wt;
-        a1 += u[G + p] * wt;
-        a2 += u[2 * G + p] * wt;
+struct alignas(4 * sizeof(T)) U4 {
+  T x, y, z, pad;
+};
+
+constexpr int kInterpThreads = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__restrict__ tile_start,
+                                                           const int32_t *__restrict__ tile_item0,
+                                                           const int32_t *__restrict__ item_tile,
+                                                           const int32_t *__restrict__ counts,
+                                                           const int32_t *__restrict__ perm,
+                                                           const Rec<T> *__restrict__ recs, const T *__restrict__ u,
+                                                           int n, int log2nt, int64_t M, double dt,
+                                                           double *__restrict__ X, double *__restrict__ U) {
+  __shared__ U4<T> uh[kHalo3];
+  const int tid = threadIdx.x;
+  const int W = counts[0];
+  const int mask = n - 1, tmask = (1 << log2nt) - 1;
+  const int64_t G = (int64_t)n * n * n;
+  for (int item = blockIdx.x; item < W; item += gridDim.x) {
+    const int tile = item_tile[item];
+    const int j0 = tile_start[tile] + (item - tile_item0[tile]) * kItem;
+    const int j1 = min(j0 + kItem, tile_start[tile + 1]);
+    const int x0 = 8 * (tile & tmask) - 1, y0 = 8 * ((tile >> log2nt) & tmask) - 1, z0 = 8 * (tile >> (2 * log2nt)) - 1;
+    __syncthreads();   // the previous item's reads of the halo are done
+    constexpr int kPer = (kHalo3 + kInterpThreads - 1) / kInterpThreads;
+    T hv[kPer][3];
+#pragma unroll
+    for (int i = 0; i < kPer; i++) {
+      const int e = tid + kInterpThreads * i;
+      if (e < kHalo3) {
+        const int hz = e / (kHalo * kHalo), r = e - hz * (kHalo * kHalo), hy = r / kHalo, hx = r - hy * kHalo;
+        const int64_t p = ((int64_t)((z0 + hz) & mask) * n + ((y0 + hy) & mask)) * n + ((x0 + hx) & mask);
+        hv[i][0] = u[p];
+        hv[i][1] = u[G + p];
+        hv[i][2] = u[2 * G + p];
       }
     }
-  }
-  const int64_t q = perm[i];
-  if (U) {
-    U[q] = (double)a0;
-    U[M + q] = (double)a1;
-    U[2 * M + q] = (double)a2;
-  }
-  if (X) {
-    X[q] = X[q] + dt * (double)a0;
-    X[M + q] = X[M + q] + dt * (double)a1;
-    X[2 * M + q] = X[2 * M + q] + dt * (double)a2;
+#pragma unroll
+    for (int i = 0; i < kPer; i++) {
+      const int e = tid + kInterpThreads * i;
+      if (e < kHalo3) {
+        U4<T> v;
+        v.x = hv[i][0];
+        v.y = hv[i][1];
+        v.z = hv[i][2];
+        v.pad = T(0);
+        uh[e] = v;
+      }
+    }
+    __syncthreads();
+    for (int j = j0 + tid; j < j1; j += kInterpThreads) {
+      const Rec<T> rec = recs[j];
+      const int64_t q = perm[j];
+      T wx[4], wy[4], wz[4];
+      phi4<T>(rec.f[0], wx);
+      phi4<T>(rec.f[1], wy);
+      phi4<T>(rec.f[2], wz);
+      const int base = halo_base(rec.key);
+      T a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+      for (int c3 = 0; c3 < 4; c3++) {
+#pragma unroll
+        for (int c2 = 0; c2 < 4; c2++) {
+          const int row = base + c3 * (kHalo * kHalo) + c2 * kHalo;
+          const T wyz = wy[c2] * wz[c3];
+#pragma unroll
+          for (int c1 = 0; c1 < 4; c1++) {
+            const U4<T> v = uh[row + c1];
+            const T wt = wx[c1] * wyz;
+            a0 += v.x * wt;
+            a1 += v.y * wt;
+            a2 += v.z * wt;
+          }
+        }
+      }
+      if (U) {
+        U[q] = (double)a0;
+        U[M + q] = (double)a1;
+        U[2 * M + q] = (double)a2;
+      }
+      if (X) {
+        X[q] = X[q] + dt * (double)a0;
+        X[M + q] = X[M + q] + dt * (double)a1;
+        X[2 * M + q] = X[2 * M + q] + dt * (double)a2;
+      }
+    }
   }
 }
 
@@ -69,13 +132,13 @@ __global__ __launch_bounds__(256) void k_interp(const uint32_t *__restrict__ key
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__ keys,
                                                     const int32_t *__restrict__ perm, Rec<T> *__restrict__ recs,
-                                                    const T *__restrict__ u, int n, int log2n, int64_t M,
+                                                    const T *__restrict__ u, int n, int log2n, int log2nt, int64_t M,
                                                     double dt, double inv_h, double *__restrict__ Xbar) {
   const int64_t i = gtid();
   if (i >= M) return;
   const int mask = n - 1;
   const int64_t G = (int64_t)n << (2 * log2n);
-  const Cell cc = key_cell(keys[i], log2n, mask);
+  const Cell cc = key_cell(keys[i], log2nt);
   const int64_t q = perm[i];
   const double xb0 = Xbar[q], xb1 = Xbar[M + q], xb2 = Xbar[2 * M + q];
   const T ub0 = (T)(dt * xb0), ub1 = (T)(dt * xb1), ub2 = (T)(dt * xb2);
@@ -117,13 +180,13 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_adj_spread(const uint32_t *__restrict__ keys,
                                                     const int32_t *__restrict__ perm, const Rec<T> *__restrict__ recs,
                                                     const T *__restrict__ ub, const double *__restrict__ F, int n,
-                                                    int log2n, int64_t M, double scale, double inv_h,
+                                                    int log2n, int log2nt, int64_t M, double scale, double inv_h,
                                                     double *__restrict__ Xbar, double *__restrict__ fbar) {
   const int64_t i = gtid();
   if (i >= M) return;
   const int mask = n - 1;
   const int64_t G = (int64_t)n << (2 * log2n);
-  const Cell cc = key_cell(keys[i], log2n, mask);
+  const Cell cc = key_cell(keys[i], log2nt);
   const int64_t q = perm[i];
   const T f0 = (T)F[q], f1 = (T)F[M + q], f2 = (T)F[2 * M + q];
   const T r0 = recs[i].f[0], r1 = recs[i].f[1], r2 = recs[i].f[2];
@@ -165,9 +228,11 @@ template <typename T>
 hipError_t launch_interp(ib_ctx *c, const T *u, double *X_inout, double *U_out, double dt) {
   if (c->M == 0) return hipSuccess;
   PhaseScope ps(c, PH_INTERP);
-  hipLaunchKernelGGL(k_interp<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
-                     c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (const Rec<T> *)c->ws.recs, u, c->n,
-                     c->log2n, c->M, dt, X_inout, U_out);
+  // blocks resident at once: the 11^3 halo takes 21 KB (FP32) or 42 KB (FP64) of LDS
+  const int grid = (int)std::min<int64_t>(c->item_cap, (int64_t)c->ncu * (c->fp32 ? 7 : 3));
+  hipLaunchKernelGGL(k_interp<T>, dim3(grid), dim3(kInterpThreads), 0, c->stream, c->ws.tile_start,
+                     c->ws.tile_item0, c->ws.item_tile, c->ws.nitems, c->ws.vals[c->sorted_buf],
+                     (const Rec<T> *)c->ws.recs, u, c->n, c->log2nt, c->M, dt, X_inout, U_out);
   return hipGetLastError();
 }
 
@@ -177,7 +242,7 @@ hipError_t launch_adj_interp(ib_ctx *c, const T *u_np1, double *Xbar) {
   PhaseScope ps(c, PH_ADJ_INTERP);
   hipLaunchKernelGGL(k_adj_interp<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
                      c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (Rec<T> *)c->ws.recs, u_np1, c->n,
-                     c->log2n, c->M, c->p.dt, 1.0 / c->h, Xbar);
+                     c->log2n, c->log2nt, c->M, c->p.dt, 1.0 / c->h, Xbar);
   return hipGetLastError();
 }
 
@@ -188,7 +253,7 @@ hipError_t launch_adj_spread(ib_ctx *c, const T *ubar_n, const double *F, double
   const double scale = (c->p.dt / c->p.rho) / (c->h * c->h * c->h);
   hipLaunchKernelGGL(k_adj_spread<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
                      c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (const Rec<T> *)c->ws.recs, ubar_n, F, c->n,
-                     c->log2n, c->M, scale, 1.0 / c->h, Xbar, fbar);
+                     c->log2n, c->log2nt, c->M, scale, 1.0 / c->h, Xbar, fbar);
   return hipGetLastError();
 }
 

@@ -92,9 +92,12 @@ def test_rollout_config4_vs_finite_differences(mods):
             XT, _ = rollout.rollout(dev(k), X0, ctx.new_grid(), ctx, n, ck)
             return float(rollout.membrane_loss(XT, X0, it))
 
-    # scaling every membrane stiffness: d/de L(k (1 + e v))
+    # scaling every membrane stiffness: d/de L(k (1 + e v)).  The FP64 loss
+    # carries ~4e-8 relative rounding noise (nm displacements on O(1)
+    # positions), i.e. ~1e-4 relative FD error at eps = 1e-4; at eps >= 1e-2
+    # that noise is ~1e-6 and the O(eps^2) truncation ~1e-5.
     v = np.where(np.arange(wl.M) < nb, wl.k, 0.0)
-    for eps in (1e-4, 1e-3):
+    for eps in (1e-2, 2e-2):
         dfd = (loss(wl.k + eps * v) - loss(wl.k - eps * v)) / (2 * eps)
         assert abs(g @ v - dfd) <= 1e-4 * abs(g @ v), (eps, g @ v, dfd)
     # a random direction over all 200k membrane stiffnesses (seed 3)

@@ -56,7 +56,10 @@ def _brute_bin(N, L, X):
     out = []
     for q in range(M):
         c = [int(math.floor(X[d, q] / h)) % N for d in range(3)]
-        out.append(((c[2] * N + c[1]) * N + c[0], q))
+        b = [cd // 8 for cd in c]
+        nb = N // 8
+        key = 512 * ((b[2] * nb + b[1]) * nb + b[0]) + 64 * (c[2] % 8) + 8 * (c[1] % 8) + c[0] % 8
+        out.append((key, q))
     out.sort()
     return np.array([o[0] for o in out], np.uint32), np.array([o[1] for o in out], np.int32)
 
@@ -72,7 +75,11 @@ def test_bin_brute_force_and_containment(oracle_mod, N):
     assert np.array_equal(keys, bk) and np.array_equal(perm, bp)
     assert np.array_equal(np.sort(perm), np.arange(M))
     h = 1.0 / N
-    c1, c2, c3 = keys % N, (keys // N) % N, keys // (N * N)
+    nb = N // 8
+    blk = keys // 512
+    c1 = 8 * (blk % nb) + keys % 8
+    c2 = 8 * ((blk // nb) % nb) + (keys // 8) % 8
+    c3 = 8 * (blk // (nb * nb)) + (keys // 64) % 8
     for d, c in enumerate((c1, c2, c3)):
         xw = np.mod(X[d, perm], 1.0)
         assert np.all(c * h <= xw + 1e-15) and np.all(xw < (c + 1) * h + 1e-15)
