@@ -7,14 +7,15 @@ tube wall), dt = 2.5e-5, 1 kHz window drive; synthetic inputs from the seeded
 generator.  A "step" is one full time step: binning, force, spreading with
 advection/RHS, FFT Navier-Stokes solve, interpolation and move.
 
-The timed region runs ``--steps`` steps of the mixed-precision step (FP32
-fluid, FP64 markers) after ``--warmup`` untimed steps, bracketed by
-synchronisations; ``value`` is steps/s.  The same steps are then run with an
-FP64 fluid for comparison, and the maximum relative velocity difference
-between the two is reported.  Per-phase HIP-event timers give the dominant
-kernel's average duration, from which the roofline fraction follows.  The
-oracle (plain FP64 CPU) is timed on a bounded sample for ``cpu_baseline``.
-Prints one JSON line.
+A short run with every phase timed gives the per-phase breakdown and picks
+the dominant single-kernel phase.  The timed region then runs ``--steps``
+steps of the mixed-precision step (FP32 fluid, FP64 markers) after
+``--warmup`` untimed steps, bracketed by synchronisations, with events only
+around the dominant kernel (its average duration gives the roofline
+fraction); ``value`` is steps/s.  The same steps are then run with an FP64
+fluid for comparison, and the maximum relative velocity difference between
+the two is reported.  The oracle (plain FP64 CPU) is timed on a bounded
+sample for ``cpu_baseline``.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -31,28 +32,84 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 
+# phases timed by exactly one kernel launch (the roofline kernel is chosen among them)
+SINGLE_KERNEL = {"force": "k_force_rec", "spread": "k_spread", "split": "k_split_reduce",
+                 "gather": "k_spread_gather", "rhs": "k_rhs_v", "fft_x": "k_xf", "fft_y": "k_y",
+                 "fft_z_solve": "k_z_solve", "fft_y_inv": "k_y", "fft_x_inv": "k_xi", "interp": "k_interp"}
 
-def phase_bytes(phase: str, N: int, M: int, b: int, touched_tiles: int) -> float:
-    """Algorithmic HBM bytes per launch of each phase (the per-unit figures of the design notes)."""
+
+def worklist_sizes(wl):
+    """Sizes of the spreading work list for the markers at X0 (8^3-cell tiles, items of 512
+    markers): items, tiles with markers, tiles the spread force reaches, and the tiles cut
+    into several items with their items."""
+    import numpy as np
+    n, nt = wl.N, wl.N // 8
+    c = np.floor(wl.X0 / wl.h).astype(np.int64) & (n - 1)
+    t = c // 8
+    tile = (t[2] * nt + t[1]) * nt + t[0]
+    K = np.bincount(tile, minlength=nt ** 3)
+    nit = (K + 511) // 512
+    items = int(nit.sum())
+    split_items = int(nit[nit > 1].sum())
+    occ = (K > 0).reshape(nt, nt, nt)
+    touched = np.zeros_like(occ)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                touched |= np.roll(occ, (dz, dy, dx), axis=(0, 1, 2))
+    return {"items": items, "tiles_with_markers": int(occ.sum()), "tiles_touched": int(touched.sum()),
+            "split_items": split_items, "split_tiles": int((nit > 1).sum())}
+
+
+def phase_bytes(phase, N, M, b, wls):
+    """Algorithmic HBM bytes per launch of each single-kernel phase (fluid precision b bytes):
+    every input read once and every output written once, at the sizes of the design notes."""
     G = N ** 3
-    spec = 3 * (N // 2 + 1) * N * N * 2 * b
+    spec = 3 * (N // 2 + 1) * N * N * 2 * b       # half spectrum, 3 components
     grid = 3 * G * b
+    rec = 32 if b == 4 else 64                    # sorted marker record
+    halo = 3 * 11 ** 3 * b                        # one work item's spread halo
+    items, touched = wls["items"], wls["tiles_touched"]
     return {
+        "force": M * (24 + 8 + 8 + 24 + 8 + 4 + 4 + rec),     # X, w, k, X_ref, kappa, inv, drive slot; record
+        "spread": M * rec + items * halo,                       # records in, item halos out
+        "split": wls["split_items"] * halo + wls["split_tiles"] * halo,   # split tiles' halos in, sums out
+        "gather": items * halo + touched * 512 * 3 * b,         # halos in, touched tiles out
+        "rhs": 2 * grid + touched * 512 * 3 * b,                # u in, r out, force of touched tiles
         "fft_x": grid + spec,
         "fft_y": 2 * spec,
         "fft_z_solve": 2 * spec,
         "fft_y_inv": 2 * spec,
         "fft_x_inv": spec + grid,
-        "rhs": 2 * grid + touched_tiles * 512 * 3 * b,
-        "spread": M * (4 + 6 * b) + touched_tiles * 512 * 3 * b,
-        "interp": M * (4 + 4 + 3 * b + 48),
-        "bin": M * (24 + 8) + 3 * M * 20,
-        "force": M * (24 + 24 + 8 + 8 + 8 + 24),
-        "prep": M * (4 + 24 + 24 + 6 * b),
-    }.get(phase, float("nan"))
+        "interp": M * (rec + 4 + 48) + touched * 512 * 3 * b,  # records, perm, X in/out; u of touched tiles
+    }.get(phase)
 
 
-def run_gpu(wl, precision, steps, warmup, timers=False):
+KERNEL_SOURCE = {"k_force_rec": "force.hip", "k_spread": "spread.hip", "k_split_reduce": "spread.hip",
+                 "k_spread_gather": "spread.hip", "k_rhs_v": "fft_reg.hip", "k_xf": "fft_reg.hip",
+                 "k_y": "fft_reg.hip", "k_z_solve": "fft_reg.hip", "k_xi": "fft_reg.hip", "k_interp": "interp.hip"}
+
+
+def traffic_for(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the factor a plain copy of known size
+    gives), or None when there is none or the kernel's source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_math_0301321_amd", "csrc", KERNEL_SOURCE[kernel])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec.get("source_sha256"):
+            return None
+    return round(rec["fetch_kib"] * 1024 * rec["fetch_factor"] + rec["write_kib"] * 1024 * rec["write_factor"])
+
+
+def run_gpu(wl, precision, steps, warmup, timed_phases=()):
+    """Run warmup + steps; time the steps with events; per-phase timers only for timed_phases
+    (a list of phase names, or None for all phases)."""
     import torch
     from paper_math_0301321_amd import ib
     ctx = ib.Context(wl, precision)
@@ -63,7 +120,9 @@ def run_gpu(wl, precision, steps, warmup, timers=False):
         ctx.step(X, u, n * wl.dt)
         n += 1
     torch.cuda.synchronize()
-    if timers:
+    timing = timed_phases is None or len(timed_phases) > 0
+    if timing:
+        ctx.timers_select(None if timed_phases is None else list(timed_phases))
         ctx.timers_enable(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -75,8 +134,8 @@ def run_gpu(wl, precision, steps, warmup, timers=False):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = ev0.elapsed_time(ev1)
-    ph = ctx.timers_read() if timers else {}
-    if timers:
+    ph = ctx.timers_read() if timing else {}
+    if timing:
         ctx.timers_enable(False)
     return dict(ctx=ctx, X=X, u=u, wall=wall, ev_ms=ev_ms, phases=ph)
 
@@ -106,6 +165,8 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain 256 MiB device copy (reference kernel for traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -118,25 +179,42 @@ def main():
 
     wl = W.config3(N=args.grid)
     print(f"[bench] workload {wl.name}: N={wl.N} M={wl.M}", file=sys.stderr, flush=True)
-    mixed = run_gpu(wl, "fp32", args.steps, args.warmup, timers=True)
+    wls = worklist_sizes(wl)
+    # 1) phase breakdown (every phase timed; not the headline number)
+    if args.calibrate_copy:
+        # a plain device copy of known size, the reference for the traffic counters
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {a.numel() * 4} bytes read, {b.numel() * 4} written", file=sys.stderr,
+              flush=True)
+        del a, b
+    brk = run_gpu(wl, "fp32", max(5, args.steps // 5), args.warmup, timed_phases=None)
+    ph = brk["phases"]
+    phases = {k: v[0] / v[1] for k, v in ph.items()}
+    cand = {k: v for k, v in phases.items() if k in SINGLE_KERNEL}
+    dom = max(cand, key=cand.get)
+    print(f"[bench] phases (ms/launch): {json.dumps({k: round(v, 4) for k, v in phases.items()})}",
+          file=sys.stderr, flush=True)
+    # 2) the timed run: only the dominant kernel's phase records events
+    mixed = run_gpu(wl, "fp32", args.steps, args.warmup, timed_phases=[dom])
     ms_per_step = mixed["ev_ms"] / args.steps
     value = args.steps / (mixed["ev_ms"] / 1e3)
     print(f"[bench] mixed: {ms_per_step:.4f} ms/step ({value:.1f} steps/s), wall {mixed['wall']:.3f} s",
           file=sys.stderr, flush=True)
-
-    # dominant kernel and its roofline
-    ph = mixed["phases"]
-    phases = {k: {"ms_avg": v[0] / v[1], "launches": v[1]} for k, v in ph.items()}
-    dom = max(ph.items(), key=lambda kv: kv[1][0])[0] if ph else None
-    roof = None
-    if dom:
-        avg_ms = ph[dom][0] / ph[dom][1]
-        nbytes = phase_bytes(dom, wl.N, wl.M, 4, 0)
-        ach = nbytes / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": nbytes, "avg_ms": round(avg_ms, 5)}
-    step_bytes = sum(phase_bytes(k, wl.N, wl.M, 4, 0) * v[1] for k, v in ph.items()) / max(1, args.steps)
+    tot, calls = mixed["phases"][dom]
+    avg_ms = tot / calls
+    nbytes = phase_bytes(dom, wl.N, wl.M, 4, wls)
+    ach = nbytes / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": SINGLE_KERNEL[dom], "phase": dom, "achieved": round(ach, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": traffic_for(SINGLE_KERNEL[dom], wl.name),
+            "bytes_per_launch": nbytes, "avg_ms": round(avg_ms, 5), "launches": calls}
+    brk_steps = max(5, args.steps // 5)
+    step_bytes = sum(phase_bytes(k, wl.N, wl.M, 4, wls) * v[1]
+                     for k, v in ph.items() if k in SINGLE_KERNEL) / brk_steps
 
     extra = {}
     if not args.no_fp64:
@@ -168,8 +246,9 @@ def main():
                    "precision": "FP32 fluid, FP64 markers and forces", "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "phases_ms": {k: round(v["ms_avg"], 5) for k, v in phases.items()},
-        "model_bytes_per_step": step_bytes,
+        "phases_ms": {k: round(v, 5) for k, v in phases.items()},
+        "model_bytes_per_step_single_kernel_phases": step_bytes,
+        "worklist": wls,
         **extra,
     }
     print(json.dumps(out), flush=True)

@@ -159,6 +159,9 @@ int64_t ib_workspace_bytes(const ib_ctx *c);
  * ib_timer_name(i) (NULL past the last phase).  Enabling resets the sums. */
 #define IB_N_TIMERS 16
 int ib_timers_enable(ib_ctx *c, int on);
+/* Restrict the timed phases to those whose bit (1u << i) is set in mask (all
+ * phases by default); each timed phase adds two events to the stream. */
+int ib_timers_select(ib_ctx *c, uint32_t mask);
 int ib_timers_read(ib_ctx *c, double *ms, int64_t *calls, int max);
 const char *ib_timer_name(int i);
 

@@ -369,7 +369,7 @@ extern "C" void ib_destroy(ib_ctx *c) {
 }
 
 // ------------------------------------------------------ instrumentation ----
-static const char *kPhaseNames[PH_COUNT] = {"bin", "force", "prep", "spread", "gather", "rhs", "fft_x", "fft_y",
+static const char *kPhaseNames[PH_COUNT] = {"bin", "force", "prep", "spread", "split", "gather", "rhs", "fft_x", "fft_y",
                                             "fft_z_solve", "fft_y_inv", "fft_x_inv", "interp", "adj_interp",
                                             "adj_spread", "hessvec"};
 
@@ -387,7 +387,11 @@ static void timers_fold(ib_ctx *c) {
 }
 
 void ib::timer_begin(ib_ctx *c, int phase) {
-  if (!c->timing) return;
+  if (!c->timing || !((c->tmask >> phase) & 1u)) {
+    c->tskip = true;
+    return;
+  }
+  c->tskip = false;
   if (c->tused == c->trec.size()) {
     TimerRec r{phase, nullptr, nullptr};
     if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) {
@@ -401,7 +405,7 @@ void ib::timer_begin(ib_ctx *c, int phase) {
 }
 
 void ib::timer_end(ib_ctx *c) {
-  if (!c->timing) return;
+  if (!c->timing || c->tskip) return;
   (void)hipEventRecord(c->trec[c->tused].b, c->stream);
   if (++c->tused >= 8192) timers_fold(c);
 }
@@ -414,6 +418,12 @@ extern "C" int ib_timers_enable(ib_ctx *c, int on) {
     c->tcalls[i] = 0;
   }
   c->timing = on != 0;
+  return IB_OK;
+}
+
+extern "C" int ib_timers_select(ib_ctx *c, uint32_t mask) {
+  if (!c) return IB_EINVAL;
+  c->tmask = mask;
   return IB_OK;
 }
 

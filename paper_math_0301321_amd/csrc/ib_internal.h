@@ -114,8 +114,8 @@ struct Workspace {
 
 // Phases timed by the optional HIP-event instrumentation.
 enum Phase {
-  PH_BIN = 0, PH_FORCE, PH_PREP, PH_SPREAD, PH_GATHER, PH_RHS, PH_FFT_X, PH_FFT_Y, PH_FFT_Z_SOLVE, PH_FFT_Y_INV,
-  PH_FFT_X_INV, PH_INTERP, PH_ADJ_INTERP, PH_ADJ_SPREAD, PH_HESSVEC, PH_COUNT
+  PH_BIN = 0, PH_FORCE, PH_PREP, PH_SPREAD, PH_SPLIT, PH_GATHER, PH_RHS, PH_FFT_X, PH_FFT_Y, PH_FFT_Z_SOLVE,
+  PH_FFT_Y_INV, PH_FFT_X_INV, PH_INTERP, PH_ADJ_INTERP, PH_ADJ_SPREAD, PH_HESSVEC, PH_COUNT
 };
 
 struct TimerRec {
@@ -148,6 +148,8 @@ struct ib_ctx {
   int64_t item_cap = 0;
   // instrumentation
   bool timing = false;
+  uint32_t tmask = 0xFFFFFFFFu;   // phases that record events while timing
+  bool tskip = false;             // the open phase is not timed
   std::vector<ib::TimerRec> trec;
   size_t tused = 0;
   double tms[ib::PH_COUNT] = {};

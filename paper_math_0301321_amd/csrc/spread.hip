@@ -354,10 +354,12 @@ hipError_t launch_spread(ib_ctx *c, T *Fgrid, bool dense, double scale) {
       hipLaunchKernelGGL(k_spread<T>, dim3(c->item_grid), dim3(64), 0, c->stream, c->ws.tile_start, c->ws.tile_item0,
                          c->ws.item_tile, c->ws.nitems, (const Rec<T> *)c->ws.recs, (T)scale, (T *)c->ws.partials);
   }
-  if (c->M > 0)
+  if (c->M > 0) {
+    PhaseScope ps(c, PH_SPLIT);
     hipLaunchKernelGGL(k_split_reduce<T>, dim3((unsigned)std::min<int64_t>(c->ntiles, 4 * c->ncu)), dim3(256), 0,
                        c->stream, c->ws.split_list, c->ws.nitems, c->ws.tile_nit, c->ws.tile_item0,
                        (T *)c->ws.partials);
+  }
   PhaseScope ps(c, PH_GATHER);
   hipLaunchKernelGGL(k_spread_gather<T>, dim3((unsigned)((c->ntiles + 3) / 4)), dim3(256), 0, c->stream,
                      c->ws.tile_nit, c->ws.tile_item0, (const T *)c->ws.partials, c->n, c->log2nt, c->ntiles,

@@ -54,7 +54,7 @@ class ib_elastic(C.Structure):
 
 EXPORTS = ["ib_create", "ib_destroy", "ib_set_material", "ib_set_stream", "ib_step", "ib_force",
            "ib_spread", "ib_interp", "ib_fluid", "ib_bin", "ib_adjoint_step", "ib_last_error",
-           "ib_workspace_bytes", "ib_timers_enable", "ib_timers_read", "ib_timer_name"]
+           "ib_workspace_bytes", "ib_timers_enable", "ib_timers_select", "ib_timers_read", "ib_timer_name"]
 IB_N_TIMERS = 16
 
 _lib = None
@@ -87,6 +87,7 @@ def load_library():
     lib.ib_workspace_bytes.argtypes = [vp]
     lib.ib_workspace_bytes.restype = C.c_int64
     lib.ib_timers_enable.argtypes = [vp, C.c_int]
+    lib.ib_timers_select.argtypes = [vp, C.c_uint32]
     lib.ib_timers_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
     lib.ib_timer_name.argtypes = [C.c_int]
     lib.ib_timer_name.restype = C.c_char_p
@@ -197,6 +198,20 @@ class Context:
     def timers_enable(self, on: bool = True):
         """Start (and reset) or stop the per-phase HIP-event timers."""
         self._check(self.lib.ib_timers_enable(self._h, 1 if on else 0))
+
+    def timers_select(self, phases=None):
+        """Time only the named phases (None: all)."""
+        if phases is None:
+            mask = 0xFFFFFFFF
+        else:
+            names = [self.lib.ib_timer_name(i) for i in range(IB_N_TIMERS)]
+            names = [n.decode() if n else None for n in names]
+            mask = 0
+            for p in phases:
+                if p not in names:
+                    raise ValueError(f"unknown phase {p!r}")
+                mask |= 1 << names.index(p)
+        self._check(self.lib.ib_timers_select(self._h, mask))
 
     def timers_read(self) -> dict:
         """{phase: (total_ms, launches)} since the timers were enabled (synchronises the stream)."""

@@ -119,3 +119,20 @@ def test_product_and_oracle_are_independent():
         if f.endswith((".c", ".h")):
             txt = open(os.path.join(ROOT, "oracle", f)).read()
             assert "ib_internal" not in txt and "include/ib.h" not in txt, f
+
+
+def test_bench_byte_model_covers_every_timed_kernel():
+    """bench.py prices every single-kernel phase it may pick as the roofline kernel."""
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(os.path.dirname(__file__), "..", "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    from paper_math_0301321_amd import workloads as W
+    wl = W.tiny_helix()
+    wls = bench.worklist_sizes(wl)
+    assert wls["items"] >= wls["tiles_with_markers"] > 0 and wls["tiles_touched"] >= wls["tiles_with_markers"]
+    for phase, kernel in bench.SINGLE_KERNEL.items():
+        v = bench.phase_bytes(phase, wl.N, wl.M, 4, wls)
+        assert v is not None and (v > 0 or (phase == "split" and wls["split_tiles"] == 0)), phase
+        assert kernel in bench.KERNEL_SOURCE
