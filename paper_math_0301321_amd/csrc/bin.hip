@@ -33,10 +33,13 @@ __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ X, int6
   vals[q] = (int32_t)q;
 }
 
-// Per-block digit histogram, layout hist[digit * nblk + block].
+// A block owns a contiguous chunk of kSortChunk keys; within it each wave owns
+// a contiguous quarter (16 rounds of 64).  Digit counts per block, layout
+// hist[digit * nblk + block].
+constexpr int kWaveKeys = 64 * kSortItems;
+
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t M,
-                                                    int shift, int radix, uint32_t *__restrict__ hist,
-                                                    int nblk) {
+                                                    int shift, int radix, uint32_t *__restrict__ hist, int nblk) {
   __shared__ uint32_t cnt[256];
   for (int i = threadIdx.x; i < 256; i += kSortThreads) cnt[i] = 0;
   __syncthreads();
@@ -88,8 +91,17 @@ __global__ __launch_bounds__(256) void k_radix_scan_digit(uint32_t *__restrict__
   if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
 }
 
-// Stable scatter: items are ranked in their original order (round, wave, lane)
-// using wave ballots to find lanes holding the same digit.  The last pass also
+__device__ __forceinline__ void wave_sync_b() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Stable scatter with a block-local reorder.  Each wave ranks its quarter
+// round by round (in key order) with ballots that find the lanes holding the
+// same digit, keeping a running count per digit in its own LDS row; the
+// block then places its keys in LDS in (digit, original order) and writes
+// each digit's run contiguously to its global position.  The last pass also
 // records each marker's sorted position (inv).
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restrict__ kin,
                                                        const int32_t *__restrict__ vin,
@@ -99,53 +111,83 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
                                                        const uint32_t *__restrict__ dtot, int nblk,
                                                        int32_t *__restrict__ inv) {
   const int R = 1 << bits;
-  __shared__ uint32_t dbase[256];
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t wcnt[4][256];
+  __shared__ uint32_t run[4][256];     // per wave: running count, then the wave's offset within the digit
+  __shared__ uint32_t lstart[256];     // block-local start of each digit
+  __shared__ uint32_t gstart[256];     // global start of each digit's run of this block
+  __shared__ uint32_t sk[kSortChunk];
+  __shared__ int32_t sv[kSortChunk];
   __shared__ uint32_t sh[4];
-  const int tid = threadIdx.x, w = tid >> 6;
-  {
-    const uint32_t v = tid < R ? dtot[tid] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan256(v, sh, &tot);
-    dbase[tid] = tid < R ? ex + hist[(int64_t)tid * nblk + blockIdx.x] : 0u;
-    run[tid] = 0;
-    for (int i = 0; i < 4; i++) wcnt[i][tid] = 0;
-  }
-  __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int d = lane; d < 256; d += 64) run[w][d] = 0;
+  wave_sync_b();
   const uint64_t lt = lanemask_lt();
-  const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+  const int64_t base = (int64_t)blockIdx.x * kSortChunk + (int64_t)w * kWaveKeys;
+  uint32_t key[kSortItems], rk[kSortItems];
+  int32_t val[kSortItems];
+#pragma unroll
   for (int it = 0; it < kSortItems; it++) {
-    const int64_t i = base + (int64_t)it * kSortThreads + tid;
-    const bool valid = i < M;
-    const uint32_t key = valid ? kin[i] : 0u;
-    const int32_t val = valid ? vin[i] : 0;
-    const uint32_t d = (key >> shift) & (uint32_t)(R - 1);
+    const int64_t i = base + (int64_t)it * 64 + lane;
+    key[it] = i < M ? kin[i] : 0xFFFFFFFFu;
+    val[it] = i < M ? vin[i] : 0;
+  }
+#pragma unroll
+  for (int it = 0; it < kSortItems; it++) {
+    const bool valid = base + (int64_t)it * 64 + lane < M;
+    const uint32_t d = (key[it] >> shift) & (uint32_t)(R - 1);
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < bits; b++) {
       const uint64_t bb = __ballot((d >> b) & 1u);
       peers &= ((d >> b) & 1u) ? bb : ~bb;
     }
-    const uint32_t rank = __popcll(peers & lt);
-    if (valid && (peers & lt) == 0) wcnt[w][d] = __popcll(peers);
-    __syncthreads();
-    uint32_t pos = 0;
+    rk[it] = valid ? run[w][d] + (uint32_t)__popcll(peers & lt) : 0u;
+    wave_sync_b();
+    // the last lane of each digit group advances that digit's count
+    if (valid && (peers >> lane) == 1ull) run[w][d] += (uint32_t)__popcll(peers);
+    wave_sync_b();
+  }
+  __syncthreads();
+  // per digit: block count, offsets of the waves, block-local and global starts
+  {
+    const int d = tid;
+    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+    if (d < R) {
+      c0 = run[0][d];
+      c1 = run[1][d];
+      c2 = run[2][d];
+      c3 = run[3][d];
+    }
+    uint32_t tot;
+    const uint32_t ls = block_excl_scan256(c0 + c1 + c2 + c3, sh, &tot);
+    uint32_t db;
+    const uint32_t dex = block_excl_scan256(d < R ? dtot[d] : 0u, sh, &tot);
+    db = dex + (d < R ? hist[(int64_t)d * nblk + blockIdx.x] : 0u);
+    lstart[d] = ls;
+    gstart[d] = db;
+    run[0][d] = ls;
+    run[1][d] = ls + c0;
+    run[2][d] = ls + c0 + c1;
+    run[3][d] = ls + c0 + c1 + c2;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kSortItems; it++) {
+    const bool valid = base + (int64_t)it * 64 + lane < M;
     if (valid) {
-      uint32_t off = run[d];
-      for (int ww = 0; ww < w; ww++) off += wcnt[ww][d];
-      pos = dbase[d] + off + rank;
+      const uint32_t d = (key[it] >> shift) & (uint32_t)(R - 1);
+      const uint32_t lp = run[w][d] + rk[it];
+      sk[lp] = key[it];
+      sv[lp] = val[it];
     }
-    __syncthreads();
-    if (tid < R) {
-      run[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
-      wcnt[0][tid] = wcnt[1][tid] = wcnt[2][tid] = wcnt[3][tid] = 0;
-    }
-    __syncthreads();
-    if (valid) {
-      kout[pos] = key;
-      vout[pos] = val;
-      if (inv) inv[val] = (int32_t)pos;
-    }
+  }
+  __syncthreads();
+  const int64_t cnt = min((int64_t)kSortChunk, M - (int64_t)blockIdx.x * kSortChunk);
+  for (int i = tid; i < cnt; i += kSortThreads) {
+    const uint32_t k = sk[i];
+    const uint32_t d = (k >> shift) & (uint32_t)(R - 1);
+    const uint32_t pos = gstart[d] + (uint32_t)i - lstart[d];
+    kout[pos] = k;
+    vout[pos] = sv[i];
+    if (inv) inv[sv[i]] = (int32_t)pos;
   }
 }
 

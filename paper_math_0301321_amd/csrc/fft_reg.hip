@@ -374,6 +374,27 @@ __global__ __launch_bounds__(256) void k_y(cplx<T> *__restrict__ spec, int64_t n
     for (int k2 = 0; k2 < R2; k2++) g[(t + P * i) + R1 * k2] = v[i * R2 + k2];
 }
 
+// Raw buffer access to the spectrum: a per-thread byte offset plus a uniform
+// one, so that no per-value 64-bit address stays live in registers.  Offsets
+// past num_records read 0 and drop stores.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t spec_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ cplx<float> bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float) {
+  return __builtin_bit_cast(cplx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ cplx<double> bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double) {
+  return __builtin_bit_cast(cplx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, cplx<float> v) {
+  using B = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, cplx<double> v) {
+  using B = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(B, v), r, (int)voff, (int)soff, 0);
+}
+
 // ------------------------------------------------- pass z with the solve ----
 template <typename T, int R1, int R2>
 __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ? 2 : 1) void k_z_solve(
@@ -390,15 +411,18 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ?
   const int nyb = N / YB;
   const int kx = blockIdx.x / nyb, y0 = (blockIdx.x % nyb) * YB;
   const int yy = threadIdx.x % YB, t = threadIdx.x / YB;
-  const int64_t cs = (int64_t)NH * N * N;
-  cplx<T> *g = spec + ((int64_t)kx * N) * N + y0 + yy;   // + c cs + z N
+  constexpr uint32_t CB = sizeof(cplx<T>);
+  constexpr uint32_t cs = (uint32_t)NH * N * N * CB;                // component stride, bytes
+  const __amdgpu_buffer_rsrc_t rs = spec_rsrc(spec, 3 * cs);
+  const uint32_t voff = ((uint32_t)(kx * N + t) * N + y0 + yy) * CB;  // (kx, z = t, y)
   cplx<T> v[3][E];
 #pragma unroll
   for (int c = 0; c < 3; c++)
 #pragma unroll
     for (int i = 0; i < R2 / P; i++)
 #pragma unroll
-      for (int j = 0; j < R1; j++) v[c][i * R1 + j] = g[c * cs + (int64_t)((t + P * i) + R2 * j) * N];
+      for (int j = 0; j < R1; j++)
+        v[c][i * R1 + j] = bload(rs, voff, c * cs + (uint32_t)((P * i + R2 * j) * N) * CB, T(0));
 #pragma unroll
   for (int c = 0; c < 3; c++) Ff::run(v[c], t, xch + yy * XSZ, tw);
   // per mode (kx, ky, kz): w = r^/(1 + nu dt lambda), then remove the s-component
@@ -437,7 +461,7 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ?
 #pragma unroll
     for (int i = 0; i < R2 / P; i++)
 #pragma unroll
-      for (int j = 0; j < R1; j++) g[c * cs + (int64_t)((t + P * i) + R2 * j) * N] = v[c][i * R1 + j];
+      for (int j = 0; j < R1; j++) bstore(rs, voff, c * cs + (uint32_t)((P * i + R2 * j) * N) * CB, v[c][i * R1 + j]);
 }
 
 // ------------------------------------------------------ pass x, inverse ----
