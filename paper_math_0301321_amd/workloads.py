@@ -182,7 +182,9 @@ def helicoid_in_tube(nb1, nb2, nw1, nw2, win1, win2, *, N, dt, n_steps, freq,
     around C(s), every marker tethered to its initial position.  The window
     patch (wall i1 < win1, i2 < win2) is driven along the outward normal.
     """
-    # ---- basilar membrane lattice: index = i2 * nb1 + i1 ----
+    # ---- basilar membrane lattice, fibre by fibre (the membrane's fibres run
+    # across its width): index = i1 * nb2 + i2 for station i1 < nb1 along the
+    # length and position i2 < nb2 across ----
     s = np.linspace(0.0, 1.0, nb1)
     C, dC, er = _centre(s)
     b = 0.015 + 0.041 * s
@@ -215,6 +217,8 @@ def helicoid_in_tube(nb1, nb2, nw1, nw2, win1, win2, *, N, dt, n_steps, freq,
     w_w = np.broadcast_to(dsw_len * 2.0 * math.pi * a / nw2, (nw2, nw1))
 
     M_bm, M_w = nb1 * nb2, nw1 * nw2
+    BM = BM.transpose(0, 2, 1)                      # (3, nb1, nb2): across-width fastest
+    w_bm, k_bm, kap_bm, s_bm = (a.T for a in (w_bm, k_bm, kap_bm, s_bm))
     X0 = np.concatenate([BM.reshape(3, M_bm), WALL.reshape(3, M_w)], axis=1)
     X0 = np.ascontiguousarray(X0)
     w = np.concatenate([w_bm.reshape(-1), w_w.reshape(-1)])
@@ -225,8 +229,8 @@ def helicoid_in_tube(nb1, nb2, nw1, nw2, win1, win2, *, N, dt, n_steps, freq,
     didx = (M_bm + i2w * nw1 + i1w).reshape(-1).astype(np.int32)
     ddir = nrm[i2w.reshape(-1), i1w.reshape(-1), :].T.copy()
 
-    lattices = [Lattice(0, nb1, nb2, False, Ks, Kb), Lattice(M_bm, nw1, nw2, True, 0.0, 0.0)]
-    meta = {"bm_first": 0, "bm_n1": nb1, "bm_n2": nb2, "wall_first": M_bm,
+    lattices = [Lattice(0, nb2, nb1, False, Ks, Kb), Lattice(M_bm, nw1, nw2, True, 0.0, 0.0)]
+    meta = {"bm_first": 0, "bm_along": nb1, "bm_across": nb2, "wall_first": M_bm,
             "wall_n1": nw1, "wall_n2": nw2, "s_bm": s_bm.reshape(-1).copy()}
     return Workload(
         name=name, N=N, L=1.0, rho=1.0, mu=0.01, dt=dt, n_steps=n_steps, convect=convect,
@@ -252,11 +256,24 @@ def config3(N: int = 256, freq: float = C3_FREQS[2]) -> Workload:
                             freq=freq, jitter_seed=0, name="helix256")
 
 
+def bm_index(wl: Workload, station, across) -> np.ndarray:
+    """Marker ids of BM points (station along the length, position across the width)."""
+    st, ac = np.meshgrid(np.atleast_1d(station), np.atleast_1d(across), indexing="ij")
+    return (wl.meta["bm_first"] + st * wl.meta["bm_across"] + ac).reshape(-1).astype(np.int64)
+
+
+def bm_station(wl: Workload, q) -> np.ndarray:
+    """Station along the length of BM marker ids q."""
+    return (np.asarray(q) - wl.meta["bm_first"]) // wl.meta["bm_across"]
+
+
+def bm_count(wl: Workload) -> int:
+    return wl.meta["bm_along"] * wl.meta["bm_across"]
+
+
 def loss_window(wl: Workload, lo: int = 238, hi: int = 241) -> np.ndarray:
-    """BM markers at stations i1 in [lo, hi] across the full width (1,000 markers at 800 x 250)."""
-    n1, n2 = wl.meta["bm_n1"], wl.meta["bm_n2"]
-    i2, i1 = np.meshgrid(np.arange(n2), np.arange(lo, hi + 1), indexing="ij")
-    return (wl.meta["bm_first"] + i2 * n1 + i1).reshape(-1).astype(np.int64)
+    """BM markers at stations [lo, hi] across the full width (1,000 markers at 800 x 250)."""
+    return np.sort(bm_index(wl, np.arange(lo, hi + 1), np.arange(wl.meta["bm_across"])))
 
 
 def config4(N: int = 128) -> Workload:

