@@ -192,8 +192,11 @@ struct XfSmem {
 
 // Right-hand side of eq. discreteNS1, r = u - dt (upwind advection) + f_scale F,
 // streamed: one thread per 16-byte run of x values of one (y, z) for all three
-// components; every load (node, both neighbours per direction, force) is
-// issued up front and the upwind side is chosen afterwards by select.
+// components; every load (node, both neighbours in y and z, force) is issued
+// up front.  A row's n / V runs are consecutive lanes; when they fit in one
+// wave the x neighbours come from the adjacent lanes by shuffle.  Upwind
+// difference per direction: u_k (u_k > 0 ? u - u_minus : u_plus - u), zero
+// when u_k = 0, the sum scaled by 1/h once.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rhs_v(const T *__restrict__ u, const T *__restrict__ Fg,
                                                const int32_t *__restrict__ tile_touch, int n, int log2n, int fmode,
@@ -202,17 +205,17 @@ __global__ __launch_bounds__(256) void k_rhs_v(const T *__restrict__ u, const T 
   using VT = Vec16<T>;
   const int64_t G = (int64_t)n << (2 * log2n);
   const int64_t e = gtid();                 // run index
-  if (e * V >= G) return;
+  if (e * V >= G) return;                   // whole rows only (G / V is a multiple of n / V)
   const int mask = n - 1;
+  const int rw = n / V;                     // runs per row
   const int64_t p = e * V;
   const int x0 = (int)(p & mask), y = (int)((p >> log2n) & mask), z = (int)(p >> (2 * log2n));
-  const int64_t row = p - x0;
-  const int64_t ym = ((int64_t)z << (2 * log2n)) + ((int64_t)((y - 1) & mask) << log2n) + x0;
-  const int64_t yp = ((int64_t)z << (2 * log2n)) + ((int64_t)((y + 1) & mask) << log2n) + x0;
-  const int64_t zm = ((int64_t)((z - 1) & mask) << (2 * log2n)) + ((int64_t)y << log2n) + x0;
-  const int64_t zp = ((int64_t)((z + 1) & mask) << (2 * log2n)) + ((int64_t)y << log2n) + x0;
+  const int64_t zo = (int64_t)z << (2 * log2n), yo = (int64_t)y << log2n;
+  const int64_t ym = zo + ((int64_t)((y - 1) & mask) << log2n) + x0;
+  const int64_t yp = zo + ((int64_t)((y + 1) & mask) << log2n) + x0;
+  const int64_t zm = ((int64_t)((z - 1) & mask) << (2 * log2n)) + yo + x0;
+  const int64_t zp = ((int64_t)((z + 1) & mask) << (2 * log2n)) + yo + x0;
   VT uc[3], vym[3], vyp[3], vzm[3], vzp[3], fv[3];
-  T xl[3], xr[3];
   bool has = fmode == 2;
   if (fmode == 1) {
     const int nt = n >> 3;
@@ -227,10 +230,27 @@ __global__ __launch_bounds__(256) void k_rhs_v(const T *__restrict__ u, const T 
       vyp[c] = *(const VT *)(uu + yp);
       vzm[c] = *(const VT *)(uu + zm);
       vzp[c] = *(const VT *)(uu + zp);
-      xl[c] = uu[row + ((x0 - 1) & mask)];
-      xr[c] = uu[row + ((x0 + V) & mask)];
     }
     if (has) fv[c] = *(const VT *)(Fg + c * G + p);
+  }
+  T xl[3] = {T(0), T(0), T(0)}, xr[3] = {T(0), T(0), T(0)};
+  if (convect && rw <= 64) {
+    // lanes of one row: run j of the row sits in lane (lane - j) + j
+    const int lane = threadIdx.x & 63, j = (int)((p & mask) / V);
+    const int l0 = lane - j;
+    const int lm = l0 + ((j - 1 + rw) & (rw - 1)), lp = l0 + ((j + 1) & (rw - 1));
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      xl[c] = __shfl(uc[c][V - 1], lm, 64);
+      xr[c] = __shfl(uc[c][0], lp, 64);
+    }
+  } else if (convect) {             // a row spans several waves
+    const int64_t row = p - x0;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      xl[c] = u[c * G + row + ((x0 - 1) & mask)];
+      xr[c] = u[c * G + row + ((x0 + V) & mask)];
+    }
   }
   VT out[3];
 #pragma unroll
@@ -243,14 +263,11 @@ __global__ __launch_bounds__(256) void k_rhs_v(const T *__restrict__ u, const T 
         const T uk0 = uc[0][i], uk1 = uc[1][i], uk2 = uc[2][i];
         const T left = i == 0 ? xl[c] : uc[c][i - 1];
         const T right = i == V - 1 ? xr[c] : uc[c][i + 1];
-        T acc = T(0);
-        if (uk0 > T(0)) acc += uk0 * ((ucc - left) * inv_h);
-        else if (uk0 < T(0)) acc += uk0 * ((right - ucc) * inv_h);
-        if (uk1 > T(0)) acc += uk1 * ((ucc - vym[c][i]) * inv_h);
-        else if (uk1 < T(0)) acc += uk1 * ((vyp[c][i] - ucc) * inv_h);
-        if (uk2 > T(0)) acc += uk2 * ((ucc - vzm[c][i]) * inv_h);
-        else if (uk2 < T(0)) acc += uk2 * ((vzp[c][i] - ucc) * inv_h);
-        rv = rv - dt * acc;
+        const T dx = uk0 > T(0) ? ucc - left : right - ucc;
+        const T dy = uk1 > T(0) ? ucc - vym[c][i] : vyp[c][i] - ucc;
+        const T dz = uk2 > T(0) ? ucc - vzm[c][i] : vzp[c][i] - ucc;
+        const T acc = uk0 * dx + uk1 * dy + uk2 * dz;
+        rv = rv - (dt * inv_h) * acc;
       }
       if (has) rv = rv + f_scale * fv[c][i];
       out[c][i] = rv;
