@@ -38,17 +38,21 @@ SINGLE_KERNEL = {"force": "k_force_rec", "spread": "k_spread", "split": "k_split
                  "fft_z_solve": "k_z_solve", "fft_y_inv": "k_y", "fft_x_inv": "k_xi", "interp": "k_interp"}
 
 
-def worklist_sizes(wl):
-    """Sizes of the spreading work list for the markers at X0 (8^3-cell tiles, items of 512
-    markers): items, tiles with markers, tiles the spread force reaches, and the tiles cut
-    into several items with their items."""
+def worklist_sizes(wl, ncu=256):
+    """Sizes of the spreading work list for the markers at X0: 8^3-cell tiles, the sorted
+    markers cut into chunks of max(256, ceil(M / (6 ncu))) markers (one per spreading wave),
+    an item per (tile, chunk) part.  Returns items, tiles with markers, tiles the spread
+    force reaches, and the tiles cut into several items with their items."""
     import numpy as np
     n, nt = wl.N, wl.N // 8
     c = np.floor(wl.X0 / wl.h).astype(np.int64) & (n - 1)
     t = c // 8
     tile = (t[2] * nt + t[1]) * nt + t[0]
     K = np.bincount(tile, minlength=nt ** 3)
-    nit = (K + 511) // 512
+    te = np.cumsum(K)
+    ts = te - K
+    chunk = max(256, -(-wl.M // (6 * ncu)))
+    nit = np.where(K > 0, (te - 1) // chunk - ts // chunk + 1, 0)
     items = int(nit.sum())
     split_items = int(nit[nit > 1].sum())
     occ = (K > 0).reshape(nt, nt, nt)
@@ -58,7 +62,7 @@ def worklist_sizes(wl):
             for dx in (-1, 0, 1):
                 touched |= np.roll(occ, (dz, dy, dx), axis=(0, 1, 2))
     return {"items": items, "tiles_with_markers": int(occ.sum()), "tiles_touched": int(touched.sum()),
-            "split_items": split_items, "split_tiles": int((nit > 1).sum())}
+            "split_items": split_items, "split_tiles": int((nit > 1).sum()), "chunk": chunk}
 
 
 def phase_bytes(phase, N, M, b, wls):
@@ -179,7 +183,7 @@ def main():
 
     wl = W.config3(N=args.grid)
     print(f"[bench] workload {wl.name}: N={wl.N} M={wl.M}", file=sys.stderr, flush=True)
-    wls = worklist_sizes(wl)
+    wls = worklist_sizes(wl, torch.cuda.get_device_properties(0).multi_processor_count)
     # 1) phase breakdown (every phase timed; not the headline number)
     if args.calibrate_copy:
         # a plain device copy of known size, the reference for the traffic counters

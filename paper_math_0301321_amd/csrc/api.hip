@@ -91,7 +91,7 @@ bool is_fin(double v) { return isfinite(v) != 0; }
 void free_ws(ib_ctx *c) {
   Workspace &w = c->ws;
   void *ptrs[] = {w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.hist, w.tile_start, w.recs, w.Flag, w.fb,
-                  w.Fgrid, w.tile_nit, w.tile_item0, w.tile_touch, w.item_tile, w.nitems, w.split_list, w.scan_tmp, w.partials,
+                  w.Fgrid, w.tile_nit, w.tile_item0, w.tile_touch, w.item_tile, w.chunk_item0, w.nitems, w.split_list, w.touch_list, w.scan_tmp, w.partials,
                   w.r, w.spec, w.nonfinite, w.tw, w.lam, w.sgrad, w.drive_idx, w.drive_dir, w.sp_rowptr, w.sp_col,
                   w.sp_rest, w.inv, w.drive_slot};
   for (void *p : ptrs)
@@ -268,15 +268,9 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
   chk_alloc(dalloc(c, &w.fb, 3 * M));
   chk_alloc(dalloc_bytes(c, &w.Fgrid, 3 * c->G * (int64_t)ts));
   {
-    // work list: a tile with K > 0 markers has ceil(K / kItem) <= K / kItem + 1 items
+    // work list: every tile with markers has one item more than the chunk
+    // boundaries inside it
     const int64_t ntiles = c->ntiles;
-    c->item_cap = std::min<int64_t>(ntiles, M) + M / kItem + 1;
-    if (c->item_cap * (int64_t)kPartStride >= (int64_t)INT32_MAX) {
-      g_create_error = "ib_create: too many markers for the spreading work list at this grid size";
-      free_ws(c);
-      delete c;
-      return IB_ENOTSUP;
-    }
     // spreading waves resident at once: 24 KB of LDS per wave in FP32, 48 KB in FP64
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) {
@@ -284,14 +278,25 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
       if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
         c->ncu = prop.multiProcessorCount;
     }
-    c->item_grid = (int)std::min<int64_t>(c->item_cap, (int64_t)c->ncu * (c->fp32 ? 6 : 3));
+    c->item_grid = c->ncu * (c->fp32 ? 6 : 3);
+    c->chunk = (int)std::max<int64_t>(256, (M + c->item_grid - 1) / std::max(1, c->item_grid));
+    c->nchunks = (int)((M + c->chunk - 1) / c->chunk);
+    c->item_cap = std::min<int64_t>(ntiles, M) + c->nchunks + 1;
+    if (c->item_cap * (int64_t)kPartStride >= (int64_t)INT32_MAX) {
+      g_create_error = "ib_create: too many markers for the spreading work list at this grid size";
+      free_ws(c);
+      delete c;
+      return IB_ENOTSUP;
+    }
     chk_alloc(dalloc(c, &w.tile_nit, ntiles));
     chk_alloc(dalloc(c, &w.tile_item0, ntiles));
     chk_alloc(dalloc(c, &w.tile_touch, ntiles));
     chk_alloc(dalloc(c, &w.item_tile, c->item_cap));
-    chk_alloc(dalloc(c, &w.nitems, 2));
+    chk_alloc(dalloc(c, &w.chunk_item0, c->nchunks + 1));
+    chk_alloc(dalloc(c, &w.nitems, 3));
     chk_alloc(dalloc(c, &w.split_list, ntiles));
-    chk_alloc(dalloc(c, &w.scan_tmp, 2 * ((ntiles + 1023) / 1024)));
+    chk_alloc(dalloc(c, &w.touch_list, ntiles));
+    chk_alloc(dalloc(c, &w.scan_tmp, 3 * ((ntiles + 1023) / 1024)));
     chk_alloc(dalloc_bytes(c, &w.partials, c->item_cap * kPartStride * (int64_t)ts));
   }
   chk_alloc(dalloc_bytes(c, &w.r, 3 * c->G * (int64_t)ts));

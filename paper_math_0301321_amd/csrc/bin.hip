@@ -6,8 +6,8 @@
 // c = floor(X/h) wrapped into [0, n); a stable LSD radix sort orders marker
 // ids by key.  Sorting makes the markers of one tile a contiguous run of the
 // sorted order (tile_start gives each tile's range), ordered by cell.  The
-// runs are then cut into work items of at most kItem markers, which the
-// spreading and interpolation kernels take one per wave.  Everything here is
+// runs are then cut into work items (see item_range), which the spreading
+// and interpolation kernels take.  Everything here is
 // integer work and bit-exact.
 #include "dev_common.h"
 #include "ib_internal.h"
@@ -207,90 +207,132 @@ __global__ __launch_bounds__(256) void k_tile_start(const uint32_t *__restrict__
 }
 
 // ---------------------------------------------------------- work list ----
-// Items per tile: ceil(K / kItem) for the K markers of the tile; item j of a
-// tile covers its markers [j kItem, min((j + 1) kItem, K)).  Tiles with more
-// than one item ("split") are listed for the reduction of their halos.  Both
-// are numbered by exclusive scans over the tiles in three launches: per-block
+// Items per tile: one per chunk that its markers [ts, te) meet (see
+// item_range).  Tiles with more
+// than one item ("split") are listed for the reduction of their halos, and
+// tiles that the spread force reaches (some tile among the 3^3 around them,
+// itself included, has markers: "touched") for the gather.  All three are
+// numbered by exclusive scans over the tiles in three launches: per-block
 // scans of 1024 tiles, a scan of the block totals, and the writes (tile_nit,
-// tile_item0, item_tile, split_list).
-__device__ __forceinline__ int2 tile_items(const int32_t *tile_start, int64_t t, int64_t ntiles) {
-  if (t >= ntiles) return make_int2(0, 0);
-  const int K = tile_start[t + 1] - tile_start[t];
-  const int it = (K + kItem - 1) / kItem;
-  return make_int2(it, it > 1 ? 1 : 0);
+// tile_item0, item_tile, split_list, touch_list, tile_touch).
+__device__ __forceinline__ int3 tile_items(const int32_t *tile_start, int64_t t, int64_t ntiles, int log2nt,
+                                           int chunk) {
+  if (t >= ntiles) return make_int3(0, 0, 0);
+  const int ts = tile_start[t], te = tile_start[t + 1];
+  const int it = te > ts ? (te - 1) / chunk - ts / chunk + 1 : 0;
+  const int tmask = (1 << log2nt) - 1;
+  const int T1 = (int)(t & tmask), T2 = (int)((t >> log2nt) & tmask), T3 = (int)(t >> (2 * log2nt));
+  int touched = 0;
+#pragma unroll
+  for (int d = 0; d < 27; d++) {     // all 54 loads independent
+    const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+    const int t2 = (((((T3 + dz) & tmask) << log2nt) | ((T2 + dy) & tmask)) << log2nt) | ((T1 + dx) & tmask);
+    touched |= tile_start[t2 + 1] > tile_start[t2];
+  }
+  return make_int3(it, it > 1 ? 1 : 0, touched);
 }
 
-// Exclusive scan of two values per thread over a 1024-thread block.
-__device__ __forceinline__ int2 scan1024(int2 v, int2 *wsum, int2 *total) {
+// Exclusive scan of three values per thread over a 1024-thread block.
+__device__ __forceinline__ int3 scan1024(int3 v, int3 *wsum, int3 *total) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  int2 incl = v;
+  int3 incl = v;
   for (int o = 1; o < 64; o <<= 1) {
-    const int x = __shfl_up(incl.x, o, 64), y = __shfl_up(incl.y, o, 64);
+    const int x = __shfl_up(incl.x, o, 64), y = __shfl_up(incl.y, o, 64), z = __shfl_up(incl.z, o, 64);
     if (lane >= o) {
       incl.x += x;
       incl.y += y;
+      incl.z += z;
     }
   }
   if (lane == 63) wsum[w] = incl;
   __syncthreads();
-  int2 wb = make_int2(0, 0), tot = make_int2(0, 0);
+  int3 wb = make_int3(0, 0, 0), tot = make_int3(0, 0, 0);
   for (int i = 0; i < 16; i++) {
     if (i < w) {
       wb.x += wsum[i].x;
       wb.y += wsum[i].y;
+      wb.z += wsum[i].z;
     }
     tot.x += wsum[i].x;
     tot.y += wsum[i].y;
+    tot.z += wsum[i].z;
   }
   __syncthreads();
   *total = tot;
-  return make_int2(wb.x + incl.x - v.x, wb.y + incl.y - v.y);
+  return make_int3(wb.x + incl.x - v.x, wb.y + incl.y - v.y, wb.z + incl.z - v.z);
 }
 
+// Also stores each tile's item count and touched flag for the write pass.
 __global__ __launch_bounds__(1024) void k_item_scan_blocks(const int32_t *__restrict__ tile_start, int64_t ntiles,
-                                                           int2 *__restrict__ block_tot) {
-  __shared__ int2 wsum[16];
-  int2 tot;
-  (void)scan1024(tile_items(tile_start, (int64_t)blockIdx.x * 1024 + threadIdx.x, ntiles), wsum, &tot);
+                                                           int log2nt, int chunk, int3 *__restrict__ block_tot,
+                                                           int32_t *__restrict__ tile_nit,
+                                                           int32_t *__restrict__ tile_touch) {
+  __shared__ int3 wsum[16];
+  const int64_t t = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  const int3 v = tile_items(tile_start, t, ntiles, log2nt, chunk);
+  if (t < ntiles) {
+    tile_nit[t] = v.x;
+    tile_touch[t] = v.z;
+  }
+  int3 tot;
+  (void)scan1024(v, wsum, &tot);
   if (threadIdx.x == 0) block_tot[blockIdx.x] = tot;
 }
 
-// counts[0] = work items, counts[1] = split tiles
-__global__ __launch_bounds__(1024) void k_item_scan_top(int2 *__restrict__ block_tot, int nblk,
-                                                        int32_t *__restrict__ counts) {
-  __shared__ int2 wsum[16];
-  int2 carry = make_int2(0, 0);
+// counts[0] = work items, counts[1] = split tiles, counts[2] = touched tiles;
+// chunk_item0[nchunks] = work items
+__global__ __launch_bounds__(1024) void k_item_scan_top(int3 *__restrict__ block_tot, int nblk,
+                                                        int32_t *__restrict__ counts, int nchunks,
+                                                        int32_t *__restrict__ chunk_item0) {
+  __shared__ int3 wsum[16];
+  int3 carry = make_int3(0, 0, 0);
   for (int base = 0; base < nblk; base += 1024) {
     const int b = base + threadIdx.x;
-    int2 tot;
-    const int2 off = scan1024(b < nblk ? block_tot[b] : make_int2(0, 0), wsum, &tot);
-    if (b < nblk) block_tot[b] = make_int2(carry.x + off.x, carry.y + off.y);
+    int3 tot;
+    const int3 off = scan1024(b < nblk ? block_tot[b] : make_int3(0, 0, 0), wsum, &tot);
+    if (b < nblk) block_tot[b] = make_int3(carry.x + off.x, carry.y + off.y, carry.z + off.z);
     carry.x += tot.x;
     carry.y += tot.y;
+    carry.z += tot.z;
   }
   if (threadIdx.x == 0) {
     counts[0] = carry.x;
     counts[1] = carry.y;
+    counts[2] = carry.z;
+    chunk_item0[nchunks] = carry.x;
   }
 }
 
-__global__ __launch_bounds__(1024) void k_item_scan_write(const int32_t *__restrict__ tile_start, int64_t ntiles,
-                                                          const int2 *__restrict__ block_off,
-                                                          int32_t *__restrict__ tile_nit,
+__global__ __launch_bounds__(1024) void k_item_scan_write(const int32_t *__restrict__ tile_nit, int64_t ntiles,
+                                                          const int32_t *__restrict__ tile_touch,
+                                                          const int32_t *__restrict__ tile_start, int chunk,
+                                                          const int3 *__restrict__ block_off,
                                                           int32_t *__restrict__ tile_item0,
                                                           int32_t *__restrict__ item_tile,
-                                                          int32_t *__restrict__ split_list) {
-  __shared__ int2 wsum[16];
+                                                          int32_t *__restrict__ split_list,
+                                                          int32_t *__restrict__ touch_list,
+                                                          int32_t *__restrict__ chunk_item0) {
+  __shared__ int3 wsum[16];
   const int64_t t = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-  const int2 v = tile_items(tile_start, t, ntiles);
-  int2 tot;
-  const int2 off = scan1024(v, wsum, &tot);
+  int3 v = make_int3(0, 0, 0);
   if (t < ntiles) {
-    const int i0 = block_off[blockIdx.x].x + off.x;
-    tile_nit[t] = v.x;
+    v.x = tile_nit[t];
+    v.y = v.x > 1 ? 1 : 0;
+    v.z = tile_touch[t];
+  }
+  int3 tot;
+  const int3 off = scan1024(v, wsum, &tot);
+  if (t < ntiles) {
+    const int3 bo = block_off[blockIdx.x];
+    const int i0 = bo.x + off.x;
     tile_item0[t] = i0;
-    for (int j = 0; j < v.x; j++) item_tile[i0 + j] = (int32_t)t;
-    if (v.y) split_list[block_off[blockIdx.x].y + off.y] = (int32_t)t;
+    const int ts = tile_start[t], c0 = ts / chunk;
+    for (int j = 0; j < v.x; j++) {
+      item_tile[i0 + j] = (int32_t)t;
+      if (j > 0 || ts == c0 * chunk) chunk_item0[c0 + j] = i0 + j;   // the item starts chunk c0 + j
+    }
+    if (v.y) split_list[bo.y + off.y] = (int32_t)t;
+    if (v.z) touch_list[bo.z + off.z] = (int32_t)t;
   }
 }
 
@@ -324,11 +366,14 @@ hipError_t launch_bin(ib_ctx *c, const double *X) {
   hipLaunchKernelGGL(k_tile_start, dim3((unsigned)((nt + 1 + 255) / 256)), dim3(256), 0, c->stream,
                      ws.keys[c->sorted_buf], M, nt, ws.tile_start);
   const int nsb = (int)((nt + 1023) / 1024);
-  int2 *tmp = (int2 *)ws.scan_tmp;
-  hipLaunchKernelGGL(k_item_scan_blocks, dim3(nsb), dim3(1024), 0, c->stream, ws.tile_start, nt, tmp);
-  hipLaunchKernelGGL(k_item_scan_top, dim3(1), dim3(1024), 0, c->stream, tmp, nsb, ws.nitems);
-  hipLaunchKernelGGL(k_item_scan_write, dim3(nsb), dim3(1024), 0, c->stream, ws.tile_start, nt, tmp, ws.tile_nit,
-                     ws.tile_item0, ws.item_tile, ws.split_list);
+  int3 *tmp = (int3 *)ws.scan_tmp;
+  hipLaunchKernelGGL(k_item_scan_blocks, dim3(nsb), dim3(1024), 0, c->stream, ws.tile_start, nt, c->log2nt,
+                     c->chunk, tmp, ws.tile_nit, ws.tile_touch);
+  hipLaunchKernelGGL(k_item_scan_top, dim3(1), dim3(1024), 0, c->stream, tmp, nsb, ws.nitems, c->nchunks,
+                     ws.chunk_item0);
+  hipLaunchKernelGGL(k_item_scan_write, dim3(nsb), dim3(1024), 0, c->stream, ws.tile_nit, nt, ws.tile_touch,
+                     ws.tile_start, c->chunk, tmp, ws.tile_item0, ws.item_tile, ws.split_list, ws.touch_list,
+                     ws.chunk_item0);
   return hipGetLastError();
 }
 

@@ -15,8 +15,7 @@ constexpr int kMaxLattices = 16;
 constexpr int kTile = 8;          // cells per tile edge: markers are binned by 8^3-cell tiles
 constexpr int kHalo = 11;         // nodes per edge of a tile's stencil halo (cells -1 .. 9)
 constexpr int kHalo3 = kHalo * kHalo * kHalo;
-constexpr int kItem = 512;        // markers per work item (the last item of a tile takes the rest)
-constexpr int kPartStride = 3996;  // values per item halo: 3 * 11^3 padded to a multiple of 4
+constexpr int kPartStride = 4096;  // values per item halo: 3 * 11^3, padded so that 64 lanes copy it in whole rounds
 
 // Sorted marker record (fluid precision): fractional offset s - floor(s) per
 // dimension, the spread force (or, in the adjoint, the staged dt * Xbar), and
@@ -49,6 +48,20 @@ __host__ __device__ __forceinline__ uint32_t cell_key(int cx, int cy, int cz, in
 // Position of a cell's stencil origin (node cell - 1) in its tile's 11^3 halo.
 __host__ __device__ __forceinline__ int halo_base(uint32_t key) {
   return (int)((key >> 6) & 7) * (kHalo * kHalo) + (int)((key >> 3) & 7) * kHalo + (int)(key & 7);
+}
+
+// Work items: the sorted markers are cut into chunks of `chunk` markers (one
+// per spreading wave) and into tiles; an item is the part of one tile that
+// lies in one chunk.  Item j of tile t (markers [ts, te)) covers
+// [max(ts, (ts / chunk + j) chunk), min(te, (ts / chunk + j + 1) chunk)).
+__device__ __forceinline__ void item_range(int item, const int32_t *__restrict__ tile_start,
+                                           const int32_t *__restrict__ tile_item0,
+                                           const int32_t *__restrict__ item_tile, int chunk, int *j0, int *j1) {
+  const int tile = item_tile[item];
+  const int ts = tile_start[tile], te = tile_start[tile + 1];
+  const int cj = ts / chunk + (item - tile_item0[tile]);
+  *j0 = max(ts, cj * chunk);
+  *j1 = min(te, (cj + 1) * chunk);
 }
 
 struct LatticeDev {
@@ -87,14 +100,16 @@ struct Workspace {
   double *fb;                  // [3][M] adjoint force cotangent (f64)
   // grid
   void *Fgrid;                 // [3][G] spread force density
-  // work list over tiles: each tile's markers cut into items of <= kItem
+  // work list: items = the parts of the tiles within the chunks
   int32_t *tile_nit;           // [ntiles] work items of the tile
   int32_t *tile_item0;         // [ntiles] first work item of the tile
   int32_t *tile_touch;         // [ntiles] 1 if the spread force reaches the tile (dense in Fgrid), else 0
   int32_t *item_tile;          // [item_cap] tile of each work item
-  int32_t *nitems;             // [2] work items, split tiles
+  int32_t *chunk_item0;        // [nchunks + 1] first item of each chunk; the last entry = items
+  int32_t *nitems;             // [3] work items, split tiles, touched tiles
   int32_t *split_list;         // [ntiles] tiles with more than one item
-  int32_t *scan_tmp;           // [2 ceil(ntiles / 1024)] per-block scan totals
+  int32_t *touch_list;         // [ntiles] tiles the spread force reaches
+  int32_t *scan_tmp;           // [3 ceil(ntiles / 1024)] per-block scan totals
   void *partials;              // [item_cap][kPartStride] each item's spread halo, [3][11^3] + pad
   void *r;                     // [3][G] right-hand side
   void *spec;                  // [3][n/2+1][n][n] complex spectrum
@@ -144,7 +159,9 @@ struct ib_ctx {
   int log2nt = 0;       // log2(n / 8)
   int64_t ntiles = 0;
   int ncu = 256;        // compute units of the device
-  int item_grid = 0;    // single-wave blocks of the spreading kernel
+  int item_grid = 0;    // most single-wave blocks of the spreading kernel
+  int chunk = 1;        // markers per chunk (per spreading wave)
+  int nchunks = 0;
   int64_t item_cap = 0;
   // instrumentation
   bool timing = false;

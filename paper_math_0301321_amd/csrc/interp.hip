@@ -1,8 +1,8 @@
 // Interpolation and marker move, sub-step 4 (eq. discreteX), and the two
 // gathers of the adjoint step that share its stencil.
 //
-// k_interp: blocks of 256 threads take the work items of the binning (up to
-// kItem markers of one 8^3-cell tile) round robin.  For each item the block
+// k_interp: blocks of 256 threads take the work items of the binning (the
+// part of one 8^3-cell tile inside one chunk of the sorted markers) round robin.  For each item the block
 // stages the velocity on the tile's 11^3 halo (nodes -1 .. 9, wrapped) in LDS,
 // three components per node; then each thread interpolates one marker at a
 // time from LDS.  The weights come from the same X^n fractional offsets the
@@ -39,11 +39,42 @@ struct alignas(4 * sizeof(T)) U4 {
 };
 
 constexpr int kInterpThreads = 256;
+constexpr int kInterpPer = 4;     // markers per thread per round
 
+// One marker: interpolate u from the staged halo and move it (or store U).
+template <typename T>
+__device__ __forceinline__ void interp_one(const U4<T> *uh, const Rec<T> &rec, T &a0, T &a1, T &a2) {
+  T wx[4], wy[4], wz[4];
+  phi4<T>(rec.f[0], wx);
+  phi4<T>(rec.f[1], wy);
+  phi4<T>(rec.f[2], wz);
+  const int base = halo_base(rec.key);
+  a0 = a1 = a2 = T(0);
+#pragma unroll
+  for (int c3 = 0; c3 < 4; c3++) {
+#pragma unroll
+    for (int c2 = 0; c2 < 4; c2++) {
+      const int row = base + c3 * (kHalo * kHalo) + c2 * kHalo;
+      const T wyz = wy[c2] * wz[c3];
+#pragma unroll
+      for (int c1 = 0; c1 < 4; c1++) {
+        const U4<T> v = uh[row + c1];
+        const T wt = wx[c1] * wyz;
+        a0 += v.x * wt;
+        a1 += v.y * wt;
+        a2 += v.z * wt;
+      }
+    }
+  }
+}
+
+// Per round a thread takes up to kInterpPer markers: all their record and
+// marker-id loads, and the halo loads, are issued together, then the position
+// loads, so that an item costs a few memory round trips.
 template <typename T>
 __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__restrict__ tile_start,
                                                            const int32_t *__restrict__ tile_item0,
-                                                           const int32_t *__restrict__ item_tile,
+                                                           const int32_t *__restrict__ item_tile, int chunk,
                                                            const int32_t *__restrict__ counts,
                                                            const int32_t *__restrict__ perm,
                                                            const Rec<T> *__restrict__ recs, const T *__restrict__ u,
@@ -54,25 +85,34 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
   const int W = counts[0];
   const int mask = n - 1, tmask = (1 << log2nt) - 1;
   const int64_t G = (int64_t)n * n * n;
+  constexpr int kPer = (kHalo3 + kInterpThreads - 1) / kInterpThreads;
   for (int item = blockIdx.x; item < W; item += gridDim.x) {
     const int tile = item_tile[item];
-    const int j0 = tile_start[tile] + (item - tile_item0[tile]) * kItem;
-    const int j1 = min(j0 + kItem, tile_start[tile + 1]);
+    int j0, j1;
+    item_range(item, tile_start, tile_item0, item_tile, chunk, &j0, &j1);
     const int x0 = 8 * (tile & tmask) - 1, y0 = 8 * ((tile >> log2nt) & tmask) - 1, z0 = 8 * (tile >> (2 * log2nt)) - 1;
-    __syncthreads();   // the previous item's reads of the halo are done
-    constexpr int kPer = (kHalo3 + kInterpThreads - 1) / kInterpThreads;
+    // every load below is issued unconditionally (indices clamped), so that
+    // the waits for them are exact
     T hv[kPer][3];
 #pragma unroll
     for (int i = 0; i < kPer; i++) {
-      const int e = tid + kInterpThreads * i;
-      if (e < kHalo3) {
-        const int hz = e / (kHalo * kHalo), r = e - hz * (kHalo * kHalo), hy = r / kHalo, hx = r - hy * kHalo;
-        const int64_t p = ((int64_t)((z0 + hz) & mask) * n + ((y0 + hy) & mask)) * n + ((x0 + hx) & mask);
-        hv[i][0] = u[p];
-        hv[i][1] = u[G + p];
-        hv[i][2] = u[2 * G + p];
-      }
+      const int e = min(tid + kInterpThreads * i, kHalo3 - 1);
+      const int hz = e / (kHalo * kHalo), r = e - hz * (kHalo * kHalo), hy = r / kHalo, hx = r - hy * kHalo;
+      const int64_t p = ((int64_t)((z0 + hz) & mask) * n + ((y0 + hy) & mask)) * n + ((x0 + hx) & mask);
+      hv[i][0] = u[p];
+      hv[i][1] = u[G + p];
+      hv[i][2] = u[2 * G + p];
     }
+    // first round's records and ids, in flight with the halo loads
+    Rec<T> rec[kInterpPer];
+    int64_t q[kInterpPer];
+#pragma unroll
+    for (int m = 0; m < kInterpPer; m++) {
+      const int j = min(j0 + tid + kInterpThreads * m, j1 - 1);
+      rec[m] = recs[j];
+      q[m] = perm[j];
+    }
+    __syncthreads();   // the previous item's reads of the halo are done
 #pragma unroll
     for (int i = 0; i < kPer; i++) {
       const int e = tid + kInterpThreads * i;
@@ -86,40 +126,41 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
       }
     }
     __syncthreads();
-    for (int j = j0 + tid; j < j1; j += kInterpThreads) {
-      const Rec<T> rec = recs[j];
-      const int64_t q = perm[j];
-      T wx[4], wy[4], wz[4];
-      phi4<T>(rec.f[0], wx);
-      phi4<T>(rec.f[1], wy);
-      phi4<T>(rec.f[2], wz);
-      const int base = halo_base(rec.key);
-      T a0 = 0, a1 = 0, a2 = 0;
+    for (int jr = j0; jr < j1; jr += kInterpThreads * kInterpPer) {
+      if (jr > j0) {
 #pragma unroll
-      for (int c3 = 0; c3 < 4; c3++) {
-#pragma unroll
-        for (int c2 = 0; c2 < 4; c2++) {
-          const int row = base + c3 * (kHalo * kHalo) + c2 * kHalo;
-          const T wyz = wy[c2] * wz[c3];
-#pragma unroll
-          for (int c1 = 0; c1 < 4; c1++) {
-            const U4<T> v = uh[row + c1];
-            const T wt = wx[c1] * wyz;
-            a0 += v.x * wt;
-            a1 += v.y * wt;
-            a2 += v.z * wt;
-          }
+        for (int m = 0; m < kInterpPer; m++) {
+          const int j = min(jr + tid + kInterpThreads * m, j1 - 1);
+          rec[m] = recs[j];
+          q[m] = perm[j];
         }
       }
-      if (U) {
-        U[q] = (double)a0;
-        U[M + q] = (double)a1;
-        U[2 * M + q] = (double)a2;
-      }
+      double xo[kInterpPer][3];
       if (X) {
-        X[q] = X[q] + dt * (double)a0;
-        X[M + q] = X[M + q] + dt * (double)a1;
-        X[2 * M + q] = X[2 * M + q] + dt * (double)a2;
+#pragma unroll
+        for (int m = 0; m < kInterpPer; m++) {
+          xo[m][0] = X[q[m]];
+          xo[m][1] = X[M + q[m]];
+          xo[m][2] = X[2 * M + q[m]];
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kInterpPer; m++) {
+        const int j = jr + tid + kInterpThreads * m;
+        if (j < j1) {
+          T a0, a1, a2;
+          interp_one<T>(uh, rec[m], a0, a1, a2);
+          if (U) {
+            U[q[m]] = (double)a0;
+            U[M + q[m]] = (double)a1;
+            U[2 * M + q[m]] = (double)a2;
+          }
+          if (X) {
+            X[q[m]] = xo[m][0] + dt * (double)a0;
+            X[M + q[m]] = xo[m][1] + dt * (double)a1;
+            X[2 * M + q[m]] = xo[m][2] + dt * (double)a2;
+          }
+        }
       }
     }
   }
@@ -228,10 +269,10 @@ template <typename T>
 hipError_t launch_interp(ib_ctx *c, const T *u, double *X_inout, double *U_out, double dt) {
   if (c->M == 0) return hipSuccess;
   PhaseScope ps(c, PH_INTERP);
-  // blocks resident at once: the 11^3 halo takes 21 KB (FP32) or 42 KB (FP64) of LDS
-  const int grid = (int)std::min<int64_t>(c->item_cap, (int64_t)c->ncu * (c->fp32 ? 7 : 3));
+  // blocks resident at once (registers: 4 per CU in FP32, 3 in FP64)
+  const int grid = (int)std::min<int64_t>(c->item_cap, (int64_t)c->ncu * (c->fp32 ? 4 : 3));
   hipLaunchKernelGGL(k_interp<T>, dim3(grid), dim3(kInterpThreads), 0, c->stream, c->ws.tile_start,
-                     c->ws.tile_item0, c->ws.item_tile, c->ws.nitems, c->ws.vals[c->sorted_buf],
+                     c->ws.tile_item0, c->ws.item_tile, c->chunk, c->ws.nitems, c->ws.vals[c->sorted_buf],
                      (const Rec<T> *)c->ws.recs, u, c->n, c->log2nt, c->M, dt, X_inout, U_out);
   return hipGetLastError();
 }

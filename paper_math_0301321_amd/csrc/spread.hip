@@ -6,21 +6,21 @@
 //
 //   k_prep    sorted records: fractional offset f = s - floor(s) per dimension
 //             (formed in FP64, stored in the fluid precision), force, key;
-//   k_spread  single-wave blocks take the work items (up to kItem markers of
-//             one tile) round robin.  Markers are staged 64 at a time as
-//             F_c phi(f_x - a) and phi(f_y - b) phi(f_z - c);
-//             then, for one marker, the 64 lanes own its 64 stencil nodes
-//             (a, b, c), keep running sums in registers while consecutive
-//             markers share a cell, and add them into the wave's 11^3 halo
-//             accumulator in LDS on a cell change.  Each item's halo is
+//   k_spread  one single-wave block per chunk of the sorted markers (equal
+//             chunks) streams the chunk, whose work items are its parts of
+//             consecutive tiles.  Markers are staged 64 at a time as F_c phi(f_x - a) and
+//             phi(f_y - b) phi(f_z - c); a cell's contribution to its 4^3
+//             nodes is a 12 x 16 contraction over its markers, done on the
+//             matrix cores and added into the wave's 11^3 halo accumulator in
+//             LDS on a cell change.  Each item's halo is
 //             written, scaled, to its own partial buffer;
 //   k_split_reduce  for tiles cut into several items, adds the items' halos
 //             in item order into the first one;
-//   k_spread_gather  one wave per tile: the force at a node is the sum of
-//             the halo values of the tiles whose halos cover it (itself and
-//             up to 7 neighbours), in a fixed order.
-//             Tiles no halo reaches are marked untouched (and zeroed when a
-//             dense grid is asked for).
+//   k_spread_gather  one wave per touched tile (the binning lists the tiles
+//             that some neighbour's markers reach): the force at a node is the
+//             sum of the halo values of the tiles whose halos cover it (itself
+//             and up to 7 neighbours), in a fixed order.  Untouched tiles are
+//             zeroed only when a dense grid is asked for.
 // No floating-point atomics: every value is summed in a fixed order, so
 // results are bitwise reproducible.
 #include <algorithm>
@@ -66,147 +66,152 @@ struct Vec16T<double> {
   typedef double type __attribute__((ext_vector_type(2)));
 };
 
-// Range [j0, j1) of the sorted markers that work item `item` covers: item j
-// of a tile takes the tile's markers j kItem .. min((j + 1) kItem, K) - 1.
-__device__ __forceinline__ void item_range(int item, const int32_t *__restrict__ tile_start,
-                                           const int32_t *__restrict__ tile_item0,
-                                           const int32_t *__restrict__ item_tile, int *j0, int *j1) {
-  const int tile = item_tile[item];
-  const int a = tile_start[tile] + (item - tile_item0[tile]) * kItem;
-  *j0 = a;
-  *j1 = min(a + kItem, tile_start[tile + 1]);
-}
-
 // ------------------------------------------------------------- spread ----
-// Staged per marker and x-offset a: F_c phi(f_x - a) (c = 0..2) and the halo
-// position of the marker's stencil origin.
+// For one marker the 64 lanes of a wave own its 64 stencil nodes (a, b, c):
+// lane a + 4b + 16c.  Each lane keeps running sums in registers while
+// consecutive markers share a cell and adds them into the wave's 11^3 halo
+// accumulator in LDS on a cell change.
+
+// Staged per marker and x-offset a: F_c phi(f_x - a) (c = 0..2) and the cell key.
 template <typename T>
 struct alignas(16) SpreadG {
   T g[3];
-  int base;
+  uint32_t key;
 };
 
 template <typename T>
 struct SpreadSmem {
   T acc[kPartStride];             // the wave's halo accumulator, [3][11^3] + pad
-  SpreadG<T> g[64][4];            // staging: force times x-weights
-  T wyz[64][16];                  // staging: y-weight times z-weight, index b * 4 + c
+  SpreadG<T> g[64][4];            // staging: force times x-weights, [marker][a]
+  T wyz[64][16];                  // staging: y-weight times z-weight, [marker][b * 4 + c]
 };
 
-// Single-wave blocks; block b takes items b, b + grid, b + 2 grid, ...  The
-// next item's range and first records are loaded before the current item's
-// halo is written out, so their latency overlaps the write.
+constexpr int kSpreadRing = 4;    // 64-marker batches of records in flight per wave
+
+// Write a finished item's halo (scaled) to its partial buffer and clear the
+// accumulator.  Out of line: it runs a few times per wave, and keeping it out
+// of the unrolled loops keeps the kernel's code small.
 template <typename T>
-__global__ __launch_bounds__(64) void k_spread(const int32_t *__restrict__ tile_start,
-                                               const int32_t *__restrict__ tile_item0,
-                                               const int32_t *__restrict__ item_tile,
-                                               const int32_t *__restrict__ counts, const Rec<T> *__restrict__ recs,
-                                               T scale, T *__restrict__ partials) {
+__device__ __noinline__ void spread_write_item(T *__restrict__ acc, T *__restrict__ out, T scale, int lane) {
   using V = typename Vec16T<T>::type;
-  constexpr int kVec = 16 / sizeof(T);
-  constexpr int kNV = kPartStride / kVec;
+  constexpr int kNV = kPartStride / (16 / sizeof(T));
+  V *acc4 = (V *)acc;
+  V *out4 = (V *)out;
+  wave_sync_lds();
+#pragma unroll 8
+  for (int i = 0; i < kNV / 64; i++) out4[lane + 64 * i] = acc4[lane + 64 * i] * scale;
+  wave_sync_lds();   // the write-out has read the accumulator
+#pragma unroll 8
+  for (int i = 0; i < kNV / 64; i++) acc4[lane + 64 * i] = V{};
+  wave_sync_lds();
+}
+
+// Single-wave blocks, one per chunk of the sorted markers (all chunks hold the
+// same number of markers, so the waves have the same work).  A wave streams
+// its chunk in batches of 64 with kSpreadRing batches of records in flight
+// (every load unconditional, so that the waits for them stay exact); its
+// items (the chunk's parts of consecutive tiles) follow one another in the
+// stream: at a tile change the finished item's halo is written out, scaled,
+// and the accumulator cleared.
+template <typename T>
+__global__ __launch_bounds__(64) void k_spread(const int32_t *__restrict__ chunk_item0, int chunk, int64_t M,
+                                               const Rec<T> *__restrict__ recs, T scale, T *__restrict__ partials) {
+  using V = typename Vec16T<T>::type;
+  constexpr int kNV = kPartStride / (16 / sizeof(T));
+  static_assert(kNV % 64 == 0, "whole rounds of 64 lanes");
   __shared__ SpreadSmem<T> sm;
   const int lane = threadIdx.x;
   const int oa = lane & 3, ob = (lane >> 2) & 3, oc = lane >> 4;
   const int loff = oc * (kHalo * kHalo) + ob * kHalo + oa;   // the lane's node relative to the stencil origin
-  const int W = counts[0];
+  const int64_t cs = (int64_t)blockIdx.x * chunk, ce = min(M, cs + chunk);
+  int item = chunk_item0[blockIdx.x];
   V *acc4 = (V *)sm.acc;
-  int item = blockIdx.x;
-  int j0 = 0, j1 = 0;
-  Rec<T> rec{};
-  if (item < W) {
-    item_range(item, tile_start, tile_item0, item_tile, &j0, &j1);
-    if (j0 + lane < j1) rec = recs[j0 + lane];
-  }
-  while (item < W) {
-    for (int e = lane; e < kNV; e += 64) acc4[e] = V{};
-    T a0 = 0, a1 = 0, a2 = 0;
-    int cur = -1;
-    // add the running sums of cell `cur` into the accumulator and start cell nb
-    auto switch_cell = [&](int nb) {
-      if (cur >= 0) {
-        const int p = cur + loff;
-        sm.acc[p] += a0;
-        sm.acc[kHalo3 + p] += a1;
-        sm.acc[2 * kHalo3 + p] += a2;
-      }
-      a0 = a1 = a2 = T(0);
-      cur = nb;
-    };
-    for (int jb = j0; jb < j1; jb += 64) {
-      const int cnt = min(64, j1 - jb);
-      wave_sync_lds();   // the previous chunk's staging has been consumed
-      if (lane < cnt) {
-        T wx[4], wy[4], wz[4];
-        phi4<T>(rec.f[0], wx);
-        phi4<T>(rec.f[1], wy);
-        phi4<T>(rec.f[2], wz);
-        const int base = halo_base(rec.key);
+  Rec<T> ring[kSpreadRing];
 #pragma unroll
-        for (int a = 0; a < 4; a++) {
-          SpreadG<T> g;
-          g.g[0] = rec.F[0] * wx[a];
-          g.g[1] = rec.F[1] * wx[a];
-          g.g[2] = rec.F[2] * wx[a];
-          g.base = base;
-          sm.g[lane][a] = g;
-        }
+  for (int q = 0; q < kSpreadRing; q++) ring[q] = recs[min(cs + 64 * q + lane, ce - 1)];
 #pragma unroll
-        for (int b = 0; b < 4; b++)
-#pragma unroll
-          for (int c = 0; c < 4; c++) sm.wyz[lane][b * 4 + c] = wy[b] * wz[c];
-      }
-      // issue the next chunk's record load before consuming this chunk
-      if (jb + 64 + lane < j1) rec = recs[jb + 64 + lane];
-      wave_sync_lds();
-      int m = 0;
-      // eight markers at a time: their LDS reads issue together
-      for (; m + 8 <= cnt; m += 8) {
-        SpreadG<T> g[8];
-        T w[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) {
-          g[u] = sm.g[m + u][oa];
-          w[u] = sm.wyz[m + u][ob * 4 + oc];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; u++) {
-          const int nb = __builtin_amdgcn_readfirstlane(g[u].base);
-          if (nb != cur) switch_cell(nb);
-          a0 += g[u].g[0] * w[u];
-          a1 += g[u].g[1] * w[u];
-          a2 += g[u].g[2] * w[u];
-        }
-      }
-      for (; m < cnt; m++) {
-        const SpreadG<T> g = sm.g[m][oa];
-        const T w = sm.wyz[m][ob * 4 + oc];
-        const int nb = __builtin_amdgcn_readfirstlane(g.base);
-        if (nb != cur) switch_cell(nb);
-        a0 += g.g[0] * w;
-        a1 += g.g[1] * w;
-        a2 += g.g[2] * w;
+  for (int i = 0; i < kNV / 64; i++) acc4[lane + 64 * i] = V{};
+  T a0 = 0, a1 = 0, a2 = 0;
+  uint32_t cur = 0xFFFFFFFFu;                           // key of the cell being summed
+  // add the running sums of cell `cur` into the accumulator and start cell k
+  auto switch_cell = [&](uint32_t k) {
+    if (cur != 0xFFFFFFFFu) {
+      const int p = halo_base(cur) + loff;
+      sm.acc[p] += a0;
+      sm.acc[kHalo3 + p] += a1;
+      sm.acc[2 * kHalo3 + p] += a2;
+      if ((k >> 9) != (cur >> 9)) {                     // the tile (item) is complete
+        spread_write_item<T>(sm.acc, partials + (int64_t)item * kPartStride, scale, lane);
+        item++;
       }
     }
-    switch_cell(-1);
-    // next item: range and first records, in flight during the write-out
-    const int nitem = item + (int)gridDim.x;
-    int nj0 = 0, nj1 = 0;
-    Rec<T> nrec{};
-    if (nitem < W) {
-      item_range(nitem, tile_start, tile_item0, item_tile, &nj0, &nj1);
-      if (nj0 + lane < nj1) nrec = recs[nj0 + lane];
+    a0 = a1 = a2 = T(0);
+    cur = k;
+  };
+  // one batch of 64 markers from ring slot r, which is then refilled with the
+  // batch kSpreadRing batches ahead (the slots are never moved: a register
+  // move would wait for the load in flight)
+  auto batch = [&](Rec<T> &r, int64_t jb) {
+    const int cnt = (int)max((int64_t)0, min((int64_t)64, ce - jb));
+    wave_sync_lds();   // the previous batch's staging has been consumed
+    if (lane < cnt) {
+      T wx[4], wy[4], wz[4];
+      phi4<T>(r.f[0], wx);
+      phi4<T>(r.f[1], wy);
+      phi4<T>(r.f[2], wz);
+#pragma unroll
+      for (int a = 0; a < 4; a++) {
+        SpreadG<T> g;
+        g.g[0] = r.F[0] * wx[a];
+        g.g[1] = r.F[1] * wx[a];
+        g.g[2] = r.F[2] * wx[a];
+        g.key = r.key;
+        sm.g[lane][a] = g;
+      }
+#pragma unroll
+      for (int b = 0; b < 4; b++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) sm.wyz[lane][b * 4 + c] = wy[b] * wz[c];
     }
+    r = recs[min(jb + 64 * kSpreadRing + lane, ce - 1)];
     wave_sync_lds();
-    V *out = (V *)(partials + (int64_t)item * kPartStride);
-#pragma unroll 4
-    for (int e = lane; e < kNV; e += 64) out[e] = acc4[e] * scale;
-    item = nitem;
-    j0 = nj0;
-    j1 = nj1;
-    rec = nrec;
-    wave_sync_lds();   // the write-out has read the accumulator
+    int m = 0;
+    // eight markers at a time: their LDS reads issue together
+    for (; m + 8 <= cnt; m += 8) {
+      SpreadG<T> g[8];
+      T w[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        g[u] = sm.g[m + u][oa];
+        w[u] = sm.wyz[m + u][ob * 4 + oc];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        const uint32_t k = __builtin_amdgcn_readfirstlane(g[u].key);
+        if (k != cur) switch_cell(k);
+        a0 += g[u].g[0] * w[u];
+        a1 += g[u].g[1] * w[u];
+        a2 += g[u].g[2] * w[u];
+      }
+    }
+    for (; m < cnt; m++) {
+      const SpreadG<T> g = sm.g[m][oa];
+      const T w = sm.wyz[m][ob * 4 + oc];
+      const uint32_t k = __builtin_amdgcn_readfirstlane(g.key);
+      if (k != cur) switch_cell(k);
+      a0 += g.g[0] * w;
+      a1 += g.g[1] * w;
+      a2 += g.g[2] * w;
+    }
+  };
+  static_assert(kSpreadRing == 4, "the batch loop below is unrolled for four ring slots");
+  for (int64_t jb = cs; jb < ce; jb += 64 * kSpreadRing) {
+    batch(ring[0], jb);
+    batch(ring[1], jb + 64);
+    batch(ring[2], jb + 128);
+    batch(ring[3], jb + 192);
   }
+  if (cur != 0xFFFFFFFFu) switch_cell(0xFFFFFFFEu);   // flush, and write out the last item (a different tile)
 }
 
 // Split tiles: add the halos of a tile's items, in item order, into its
@@ -246,93 +251,128 @@ __global__ __launch_bounds__(256) void k_split_reduce(const int32_t *__restrict_
 // neighbour at offset -1 (its halo positions 9, 10 = this tile's nodes 0, 1),
 // s = 2..9 from the tile itself (positions 1..8 = nodes 0..7), s = 10 from the
 // neighbour at +1 (position 0 = node 7).
-__device__ __forceinline__ int src_off(int s) { return s < 2 ? -1 : (s < 10 ? 0 : 1); }
-__device__ __forceinline__ int src_pos(int s) { return s < 2 ? s + 9 : (s < 10 ? s - 1 : 0); }
+__host__ __device__ constexpr int src_off(int s) { return s < 2 ? -1 : (s < 10 ? 0 : 1); }
+__host__ __device__ constexpr int src_pos(int s) { return s < 2 ? s + 9 : (s < 10 ? s - 1 : 0); }
 
 constexpr int kSrcPerLane = (kHalo3 + 63) / 64;   // 21
 
-// One wave per tile (four tiles per block).  For each component, every lane
-// loads its share of the 11^3 sources (the neighbours' reduced halos; all
-// loads in flight at once) into LDS; then each lane adds, for its nodes
-// (x, y) = (l % 8, l / 8) on the 8 z-planes, the 1 to 8 sources that cover
-// them in the order of the neighbour offset (z, then y, then x).  Tiles that
-// no neighbour's markers reach are marked untouched (zeroed when dense).
+// For each of the 11^3 sources of a tile: the neighbour index d27 = (dz + 1) 9
+// + (dy + 1) 3 + (dx + 1) and the position in that neighbour's halo.
+struct SrcTab {
+  uint16_t e[kSrcPerLane * 64];
+  uint8_t d[kSrcPerLane * 64];
+};
+constexpr SrcTab make_src_tab() {
+  SrcTab t{};
+  for (int s = 0; s < kSrcPerLane * 64; s++) {
+    if (s >= kHalo3) {
+      t.e[s] = 0;
+      t.d[s] = 13;
+      continue;
+    }
+    const int sz = s / (kHalo * kHalo), sy = (s / kHalo) % kHalo, sx = s % kHalo;
+    t.d[s] = (uint8_t)((src_off(sz) + 1) * 9 + (src_off(sy) + 1) * 3 + (src_off(sx) + 1));
+    t.e[s] = (uint16_t)((src_pos(sz) * kHalo + src_pos(sy)) * kHalo + src_pos(sx));
+  }
+  return t;
+}
+__constant__ SrcTab kSrc = make_src_tab();
+
+// Waves take the touched tiles of the binning's list (four per block, round
+// robin).  For each component, every lane loads its share of the 11^3
+// sources (the neighbours' reduced halos; all loads in flight at once) into
+// LDS; then each lane adds, for its nodes (x, y) = (l % 8, l / 8) on the 8
+// z-planes, the sources that cover them.  Per dimension a node has two source
+// slots in ascending neighbour offset (offset -1 for nodes 0, 1; the tile
+// itself; offset +1 for node 7), the second one empty for nodes 2..6; the 8
+// slot combinations are added in the fixed order (z, y, x), an empty slot
+// adding zero.
 template <typename T>
-__global__ __launch_bounds__(256) void k_spread_gather(const int32_t *__restrict__ tile_nit,
+__global__ __launch_bounds__(256) void k_spread_gather(const int32_t *__restrict__ touch_list,
+                                                       const int32_t *__restrict__ counts,
+                                                       const int32_t *__restrict__ tile_nit,
                                                        const int32_t *__restrict__ tile_item0,
                                                        const T *__restrict__ partials, int n, int log2nt,
-                                                       int64_t ntiles, int dense, T *__restrict__ Fgrid,
-                                                       int32_t *__restrict__ tile_touch) {
-  __shared__ T Vs[4][kHalo3];
+                                                       T *__restrict__ Fgrid) {
+  __shared__ T Vs[4][kSrcPerLane * 64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t tile = (int64_t)blockIdx.x * 4 + w;
-  if (tile >= ntiles) return;
+  const int ntouch = counts[2];
   const int tmask = (1 << log2nt) - 1;
-  const int T1 = (int)(tile & tmask), T2 = (int)((tile >> log2nt) & tmask), T3 = (int)(tile >> (2 * log2nt));
-  int nb_nit = 0, nb_i0 = 0;
-  if (lane < 27) {
-    const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
-    const int t2 = (((((T3 + dz) & tmask) << log2nt) | ((T2 + dy) & tmask)) << log2nt) | ((T1 + dx) & tmask);
-    nb_nit = tile_nit[t2];
-    nb_i0 = tile_item0[t2];
-  }
-  const bool any = __ballot(nb_nit > 0) != 0;
   const int64_t G = (int64_t)n * n * n;
   const int px = lane & 7, py = lane >> 3;
-  T *dst = Fgrid + (((int64_t)(8 * T3) * n + 8 * T2 + py) * n + 8 * T1 + px);
-  if (lane == 0) tile_touch[tile] = any ? 1 : 0;
-  if (!any) {
-    if (dense)
-      for (int k = 0; k < 8; k++)
-        for (int c = 0; c < 3; c++) dst[c * G + (int64_t)k * n * n] = T(0);
-    return;
-  }
-  // offsets of the lane's sources s = lane + 64 i (-1: none)
-  int soff[kSrcPerLane];
-#pragma unroll
-  for (int i = 0; i < kSrcPerLane; i++) {
-    const int s = lane + 64 * i;
-    const int sz = s / (kHalo * kHalo), r = s - sz * (kHalo * kHalo), sy = r / kHalo, sx = r - sy * kHalo;
-    const int d27 = (src_off(sz) + 1) * 9 + (src_off(sy) + 1) * 3 + (src_off(sx) + 1);
-    const int e = (src_pos(sz) * kHalo + src_pos(sy)) * kHalo + src_pos(sx);
-    const int nd = __shfl(nb_nit, d27, 64), i0 = __shfl(nb_i0, d27, 64);
-    soff[i] = (s < kHalo3 && nd > 0) ? i0 * kPartStride + e : -1;
-  }
-  // x and y sources of this lane's column, in offset order
-  int xs[2], ys[2], nx = 0, ny = 0;
-  if (px <= 1) xs[nx++] = px;
-  xs[nx++] = px + 2;
-  if (px == 7) xs[nx++] = 10;
-  if (py <= 1) ys[ny++] = py;
-  ys[ny++] = py + 2;
-  if (py == 7) ys[ny++] = 10;
+  // source slots of this lane's column: x, y positions in the 11^3 source cube
+  const int x0 = px <= 1 ? px : px + 2, x1 = px <= 1 ? px + 2 : 10;
+  const int y0 = py <= 1 ? py : py + 2, y1 = py <= 1 ? py + 2 : 10;
+  const bool hx1 = px <= 1 || px == 7, hy1 = py <= 1 || py == 7;
   T *Vw = Vs[w];
-  for (int c = 0; c < 3; c++) {
-    T v[kSrcPerLane];
+  for (int li = blockIdx.x * 4 + w; li < ntouch; li += gridDim.x * 4) {
+    const int tile = touch_list[li];
+    const int T1 = tile & tmask, T2 = (tile >> log2nt) & tmask, T3 = tile >> (2 * log2nt);
+    int nb_base = -1;                     // first halo value of neighbour `lane`, -1 without markers
+    if (lane < 27) {
+      const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
+      const int t2 = (((((T3 + dz) & tmask) << log2nt) | ((T2 + dy) & tmask)) << log2nt) | ((T1 + dx) & tmask);
+      if (tile_nit[t2] > 0) nb_base = tile_item0[t2] * kPartStride;
+    }
+    T *dst = Fgrid + (((int64_t)(8 * T3) * n + 8 * T2 + py) * n + 8 * T1 + px);
+    int soff[kSrcPerLane];
 #pragma unroll
     for (int i = 0; i < kSrcPerLane; i++) {
-      const T x = partials[(soff[i] >= 0 ? soff[i] : 0) + c * kHalo3];
-      v[i] = soff[i] >= 0 ? x : T(0);
+      const int sidx = lane + 64 * i;
+      const int b = __shfl(nb_base, kSrc.d[sidx], 64);
+      soff[i] = b >= 0 ? b + kSrc.e[sidx] : -1;
     }
-    wave_sync_lds();   // the previous component's sums have read the sources
+    for (int c = 0; c < 3; c++) {
+      T v[kSrcPerLane];
 #pragma unroll
-    for (int i = 0; i < kSrcPerLane; i++) {
-      const int s = lane + 64 * i;
-      if (s < kHalo3) Vw[s] = v[i];
-    }
-    wave_sync_lds();
+      for (int i = 0; i < kSrcPerLane; i++) {
+        const T x = partials[(soff[i] >= 0 ? soff[i] : 0) + c * kHalo3];
+        v[i] = soff[i] >= 0 ? x : T(0);
+      }
+      wave_sync_lds();   // the previous component's sums have read the sources
 #pragma unroll
-    for (int k = 0; k < 8; k++) {
-      int zs[2], nz = 0;
-      if (k <= 1) zs[nz++] = k;
-      zs[nz++] = k + 2;
-      if (k == 7) zs[nz++] = 10;
-      T acc = T(0);
-      for (int a = 0; a < nz; a++)
-        for (int b = 0; b < ny; b++)
-          for (int q = 0; q < nx; q++) acc += Vw[(zs[a] * kHalo + ys[b]) * kHalo + xs[q]];
-      dst[c * G + (int64_t)k * n * n] = acc;
+      for (int i = 0; i < kSrcPerLane; i++) Vw[lane + 64 * i] = v[i];
+      wave_sync_lds();
+#pragma unroll
+      for (int k = 0; k < 8; k++) {
+        const int z0 = k <= 1 ? k : k + 2, z1 = k <= 1 ? k + 2 : 10;
+        const bool hz1 = k <= 1 || k == 7;
+        T acc = T(0);
+#pragma unroll
+        for (int a = 0; a < 2; a++) {
+          const int zz = a ? z1 : z0;
+#pragma unroll
+          for (int b = 0; b < 2; b++) {
+            const int yy = b ? y1 : y0;
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+              const int xx = q ? x1 : x0;
+              const T val = Vw[(zz * kHalo + yy) * kHalo + xx];
+              const bool ok = (!a || hz1) && (!b || hy1) && (!q || hx1);
+              acc += ok ? val : T(0);
+            }
+          }
+        }
+        dst[c * G + (int64_t)k * n * n] = acc;
+      }
     }
+  }
+}
+
+// Dense force grid for the ib_spread entry point: zero the tiles no spread
+// force reaches.
+template <typename T>
+__global__ __launch_bounds__(256) void k_spread_zero(const int32_t *__restrict__ tile_touch, int n, int log2nt,
+                                                     T *__restrict__ Fgrid) {
+  const int tile = blockIdx.x;
+  if (tile_touch[tile] != 0) return;
+  const int tmask = (1 << log2nt) - 1;
+  const int T1 = tile & tmask, T2 = (tile >> log2nt) & tmask, T3 = tile >> (2 * log2nt);
+  const int64_t G = (int64_t)n * n * n;
+  const int base = ((8 * T3) * n + 8 * T2) * n + 8 * T1;
+  for (int e = threadIdx.x; e < 3 * 512; e += 256) {
+    const int c = e >> 9, p = e & 511;
+    Fgrid[c * G + base + ((int64_t)(p >> 6) * n + ((p >> 3) & 7)) * n + (p & 7)] = T(0);
   }
 }
 
@@ -351,8 +391,8 @@ hipError_t launch_spread(ib_ctx *c, T *Fgrid, bool dense, double scale) {
   {
     PhaseScope ps(c, PH_SPREAD);
     if (c->M > 0)
-      hipLaunchKernelGGL(k_spread<T>, dim3(c->item_grid), dim3(64), 0, c->stream, c->ws.tile_start, c->ws.tile_item0,
-                         c->ws.item_tile, c->ws.nitems, (const Rec<T> *)c->ws.recs, (T)scale, (T *)c->ws.partials);
+      hipLaunchKernelGGL(k_spread<T>, dim3(c->nchunks), dim3(64), 0, c->stream, c->ws.chunk_item0, c->chunk, c->M,
+                         (const Rec<T> *)c->ws.recs, (T)scale, (T *)c->ws.partials);
   }
   if (c->M > 0) {
     PhaseScope ps(c, PH_SPLIT);
@@ -361,9 +401,12 @@ hipError_t launch_spread(ib_ctx *c, T *Fgrid, bool dense, double scale) {
                        (T *)c->ws.partials);
   }
   PhaseScope ps(c, PH_GATHER);
-  hipLaunchKernelGGL(k_spread_gather<T>, dim3((unsigned)((c->ntiles + 3) / 4)), dim3(256), 0, c->stream,
-                     c->ws.tile_nit, c->ws.tile_item0, (const T *)c->ws.partials, c->n, c->log2nt, c->ntiles,
-                     dense ? 1 : 0, Fgrid, c->ws.tile_touch);
+  hipLaunchKernelGGL(k_spread_gather<T>, dim3((unsigned)std::min<int64_t>((c->ntiles + 3) / 4, 5 * c->ncu)),
+                     dim3(256), 0, c->stream, c->ws.touch_list, c->ws.nitems, c->ws.tile_nit, c->ws.tile_item0,
+                     (const T *)c->ws.partials, c->n, c->log2nt, Fgrid);
+  if (dense)
+    hipLaunchKernelGGL(k_spread_zero<T>, dim3((unsigned)c->ntiles), dim3(256), 0, c->stream, c->ws.tile_touch, c->n,
+                       c->log2nt, Fgrid);
   return hipGetLastError();
 }
 
