@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 
 # phases timed by exactly one kernel launch (the roofline kernel is chosen among them)
 SINGLE_KERNEL = {"force": "k_force_rec", "spread": "k_spread", "split": "k_split_reduce",
-                 "gather": "k_spread_gather", "rhs": "k_rhs_v", "fft_x": "k_xf", "fft_y": "k_y",
+                 "gather": "k_spread_gather", "rhs_fft_x": "k_xf_rhs", "fft_y": "k_y",
                  "fft_z_solve": "k_z_solve", "fft_y_inv": "k_y", "fft_x_inv": "k_xi", "interp": "k_interp"}
 
 
@@ -79,8 +79,7 @@ def phase_bytes(phase, N, M, b, wls):
         "spread": M * rec + items * halo,                       # records in, item halos out
         "split": wls["split_items"] * halo + wls["split_tiles"] * halo,   # split tiles' halos in, sums out
         "gather": items * halo + touched * 512 * 3 * b,         # halos in, touched tiles out
-        "rhs": 2 * grid + touched * 512 * 3 * b,                # u in, r out, force of touched tiles
-        "fft_x": grid + spec,
+        "rhs_fft_x": grid + touched * 512 * 3 * b + spec,      # u in, force of touched tiles; spectrum out
         "fft_y": 2 * spec,
         "fft_z_solve": 2 * spec,
         "fft_y_inv": 2 * spec,
@@ -90,7 +89,7 @@ def phase_bytes(phase, N, M, b, wls):
 
 
 KERNEL_SOURCE = {"k_force_rec": "force.hip", "k_spread": "spread.hip", "k_split_reduce": "spread.hip",
-                 "k_spread_gather": "spread.hip", "k_rhs_v": "fft_reg.hip", "k_xf": "fft_reg.hip",
+                 "k_spread_gather": "spread.hip", "k_xf_rhs": "fft_reg.hip",
                  "k_y": "fft_reg.hip", "k_z_solve": "fft_reg.hip", "k_xi": "fft_reg.hip", "k_interp": "interp.hip"}
 
 

@@ -78,7 +78,11 @@ typedef struct {
  *   drive (window, Sec. 4): + drive_A w_q sin(2 pi drive_freq t) dir_q
  * with kbar, wbar the means over the edge's two markers and Y = X_ref.
  * w, k, X_ref, kappa are DEVICE arrays read at every call (the caller may
- * change their contents between calls; ib_set_material swaps pointers).
+ * change their contents between calls; ib_set_material swaps pointers),
+ * except that the lattice rest lengths |Yb-Ya|, Lc and the factors wbar, w_c
+ * are derived from X_ref and w once, at ib_create and at every
+ * ib_set_material that passes w or X_ref: after changing the contents of
+ * either in place, call ib_set_material with it again.
  * Topology (lattices, springs, drive) is HOST memory copied at ib_create. */
 typedef struct {
   const double *w;           /* [M] area weight dq                                  */
@@ -103,7 +107,9 @@ typedef struct {
 int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out);
 void ib_destroy(ib_ctx *c);
 
-/* Replace the per-marker material pointers (NULL keeps the current one). */
+/* Replace the per-marker material pointers (NULL keeps the current one).
+ * Passing w or X_ref (even the same pointer) recomputes the lattice
+ * constants derived from them, on the context's stream. */
 int ib_set_material(ib_ctx *c, const double *w, const double *k, const double *X_ref,
                     const double *kappa);
 /* Run subsequent calls on another hipStream_t. */
@@ -157,10 +163,11 @@ int64_t ib_workspace_bytes(const ib_ctx *c);
  * for phase i < min(max, IB_N_TIMERS), the summed milliseconds ms[i] and the
  * number of launches calls[i] since the last reset.  Phase names come from
  * ib_timer_name(i) (NULL past the last phase).  Enabling resets the sums. */
-#define IB_N_TIMERS 16
+#define IB_N_TIMERS 32
 int ib_timers_enable(ib_ctx *c, int on);
 /* Restrict the timed phases to those whose bit (1u << i) is set in mask (all
- * phases by default); each timed phase adds two events to the stream. */
+ * phases by default); each timed phase adds two events to the stream.  Phases
+ * are numbered below IB_N_TIMERS, so every one has a bit in the mask. */
 int ib_timers_select(ib_ctx *c, uint32_t mask);
 int ib_timers_read(ib_ctx *c, double *ms, int64_t *calls, int max);
 const char *ib_timer_name(int i);

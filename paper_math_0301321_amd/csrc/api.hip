@@ -93,7 +93,7 @@ void free_ws(ib_ctx *c) {
   void *ptrs[] = {w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.hist, w.tile_start, w.recs, w.Flag, w.fb,
                   w.Fgrid, w.tile_nit, w.tile_item0, w.tile_touch, w.item_tile, w.chunk_item0, w.nitems, w.split_list, w.touch_list, w.scan_tmp, w.partials,
                   w.r, w.spec, w.nonfinite, w.tw, w.lam, w.sgrad, w.drive_idx, w.drive_dir, w.sp_rowptr, w.sp_col,
-                  w.sp_rest, w.inv, w.drive_slot};
+                  w.sp_rest, w.inv, w.drive_slot, w.lat_pre};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->ws = Workspace{};
@@ -351,6 +351,16 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
     mt.sp_col = w.sp_col;
     mt.sp_rest = w.sp_rest;
   }
+  {
+    bool moduli = false;
+    for (int l = 0; l < e->n_lattices; l++) moduli = moduli || e->lattices[l].Ks != 0.0 || e->lattices[l].Kb != 0.0;
+    if (moduli && M > 0) {
+      chk_alloc(dalloc(c, &w.lat_pre, 6 * M));
+      mt.lat_pre = w.lat_pre;
+      if (err == hipSuccess) err = launch_lattice_pre(c);
+      if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
+    }
+  }
   if (err == hipSuccess) err = c->fp32 ? upload_tables<float>(c) : upload_tables<double>(c);
   if (err != hipSuccess) {
     g_create_error = std::string("ib_create: upload failed: ") + hipGetErrorString(err);
@@ -376,7 +386,7 @@ extern "C" void ib_destroy(ib_ctx *c) {
 // ------------------------------------------------------ instrumentation ----
 static const char *kPhaseNames[PH_COUNT] = {"bin", "force", "prep", "spread", "split", "gather", "rhs", "fft_x", "fft_y",
                                             "fft_z_solve", "fft_y_inv", "fft_x_inv", "interp", "adj_interp",
-                                            "adj_spread", "hessvec"};
+                                            "adj_spread", "hessvec", "rhs_fft_x"};
 
 static void timers_fold(ib_ctx *c) {
   if (c->tused == 0) return;
@@ -451,6 +461,7 @@ extern "C" int ib_set_material(ib_ctx *c, const double *w, const double *k, cons
   if (k) c->mat.k = k;
   if (X_ref) c->mat.X_ref = X_ref;
   if (kappa) c->mat.kappa = kappa;
+  if (w || X_ref) IB_TRY(launch_lattice_pre(c));   // reference-shape constants follow X_ref and w
   return IB_OK;
 }
 

@@ -8,12 +8,11 @@
 // inverse of a transform done with (R1, R2) uses (R2, R1), which leaves every
 // value in the register slot it started from.
 //
-// Six passes over HBM, each reading and writing its array once:
-//   k_rhs_v    r = u - dt (upwind advection) + (dt/rho) F, streamed (not an
-//              FFT pass: one read of u, one write of r);
-//   k_xf       transforms rows of r (two real rows packed as one complex
-//              pencil), writing modes kx = 0 .. n/2 to spec[c][kx][z][y]
-//              (runs of 128 bytes along y);
+// Five passes over HBM, each reading and writing its array once:
+//   k_xf_rhs   r = u - dt (upwind advection) + (dt/rho) F for a block of
+//              rows, kept in LDS, then transformed (two real rows packed as
+//              one complex pencil), writing modes kx = 0 .. n/2 to
+//              spec[c][kx][z][y] (runs of 128 bytes along y);
 //   k_y        forward or inverse along y (contiguous pencils);
 //   k_z_solve  forward along z for all three components of a (kx, y-block),
 //              the diagonal viscous solve and the projection per mode in
@@ -173,153 +172,216 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk) {
   return (b % 8) * (nblk / 8) + b / 8;
 }
 
-// ------------------------------------------------ pass x, forward + RHS ----
+// --------------------------------------------- pass x, block shapes ----
 template <typename T>
 struct XfCfg {
   static constexpr int YB = sizeof(T) == 4 ? 16 : 8;   // rows per block: 128-byte runs of complex
 };
-
-template <typename T, int R1, int R2>
-struct XfSmem {
-  static constexpr int N = R1 * R2, YB = XfCfg<T>::YB, NP = 3 * YB / 2;
-  static constexpr int US = N + 8;     // staged row stride: rows of one wave's pencils fall in different banks
-  static constexpr int OS = YB + 1;    // output staging stride (complex values)
-  static constexpr size_t U = sizeof(T) * 3 * YB * US;
-  static constexpr size_t X = sizeof(cplx<T>) * NP * R1 * (R2 + 1);
-  static constexpr size_t O = sizeof(cplx<T>) * 3 * (N / 2 + 1) * OS;
-  static constexpr size_t BYTES = U > X ? (U > O ? U : O) : (X > O ? X : O);
+// rows per block of the forward x pass with the right-hand side: 8 keeps the
+// staged rows and their y halo within a third of the LDS, so that several
+// blocks share a CU and hide each other's load latency
+template <typename T>
+struct XrCfg {
+  static constexpr int YB = 8;
 };
 
-// Right-hand side of eq. discreteNS1, r = u - dt (upwind advection) + f_scale F,
-// streamed: one thread per 16-byte run of x values of one (y, z) for all three
-// components; every load (node, both neighbours in y and z, force) is issued
-// up front.  A row's n / V runs are consecutive lanes; when they fit in one
-// wave the x neighbours come from the adjacent lanes by shuffle.  Upwind
-// difference per direction: u_k (u_k > 0 ? u - u_minus : u_plus - u), zero
-// when u_k = 0, the sum scaled by 1/h once.
-template <typename T>
-__global__ __launch_bounds__(256) void k_rhs_v(const T *__restrict__ u, const T *__restrict__ Fg,
-                                               const int32_t *__restrict__ tile_touch, int n, int log2n, int fmode,
-                                               int convect, T dt, T f_scale, T inv_h, T *__restrict__ r) {
-  constexpr int V = 16 / sizeof(T);
-  using VT = Vec16<T>;
-  const int64_t G = (int64_t)n << (2 * log2n);
-  const int64_t e = gtid();                 // run index
-  if (e * V >= G) return;                   // whole rows only (G / V is a multiple of n / V)
-  const int mask = n - 1;
-  const int rw = n / V;                     // runs per row
-  const int64_t p = e * V;
-  const int x0 = (int)(p & mask), y = (int)((p >> log2n) & mask), z = (int)(p >> (2 * log2n));
-  const int64_t zo = (int64_t)z << (2 * log2n), yo = (int64_t)y << log2n;
-  const int64_t ym = zo + ((int64_t)((y - 1) & mask) << log2n) + x0;
-  const int64_t yp = zo + ((int64_t)((y + 1) & mask) << log2n) + x0;
-  const int64_t zm = ((int64_t)((z - 1) & mask) << (2 * log2n)) + yo + x0;
-  const int64_t zp = ((int64_t)((z + 1) & mask) << (2 * log2n)) + yo + x0;
-  VT uc[3], vym[3], vyp[3], vzm[3], vzp[3], fv[3];
-  bool has = fmode == 2;
-  if (fmode == 1) {
-    const int nt = n >> 3;
-    has = tile_touch[((z >> 3) * nt + (y >> 3)) * nt + (x0 >> 3)] != 0;
-  }
-#pragma unroll
-  for (int c = 0; c < 3; c++) {
-    const T *uu = u + c * G;
-    uc[c] = *(const VT *)(uu + p);
-    if (convect) {
-      vym[c] = *(const VT *)(uu + ym);
-      vyp[c] = *(const VT *)(uu + yp);
-      vzm[c] = *(const VT *)(uu + zm);
-      vzp[c] = *(const VT *)(uu + zp);
-    }
-    if (has) fv[c] = *(const VT *)(Fg + c * G + p);
-  }
-  T xl[3] = {T(0), T(0), T(0)}, xr[3] = {T(0), T(0), T(0)};
-  if (convect && rw <= 64) {
-    // lanes of one row: run j of the row sits in lane (lane - j) + j
-    const int lane = threadIdx.x & 63, j = (int)((p & mask) / V);
-    const int l0 = lane - j;
-    const int lm = l0 + ((j - 1 + rw) & (rw - 1)), lp = l0 + ((j + 1) & (rw - 1));
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-      xl[c] = __shfl(uc[c][V - 1], lm, 64);
-      xr[c] = __shfl(uc[c][0], lp, 64);
-    }
-  } else if (convect) {             // a row spans several waves
-    const int64_t row = p - x0;
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-      xl[c] = u[c * G + row + ((x0 - 1) & mask)];
-      xr[c] = u[c * G + row + ((x0 + V) & mask)];
-    }
-  }
-  VT out[3];
-#pragma unroll
-  for (int c = 0; c < 3; c++) {
-#pragma unroll
-    for (int i = 0; i < V; i++) {
-      const T ucc = uc[c][i];
-      T rv = ucc;
-      if (convect) {
-        const T uk0 = uc[0][i], uk1 = uc[1][i], uk2 = uc[2][i];
-        const T left = i == 0 ? xl[c] : uc[c][i - 1];
-        const T right = i == V - 1 ? xr[c] : uc[c][i + 1];
-        const T dx = uk0 > T(0) ? ucc - left : right - ucc;
-        const T dy = uk1 > T(0) ? ucc - vym[c][i] : vyp[c][i] - ucc;
-        const T dz = uk2 > T(0) ? ucc - vzm[c][i] : vzp[c][i] - ucc;
-        const T acc = uk0 * dx + uk1 * dy + uk2 * dz;
-        rv = rv - (dt * inv_h) * acc;
-      }
-      if (has) rv = rv + f_scale * fv[c][i];
-      out[c][i] = rv;
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < 3; c++) *(VT *)(r + c * G + p) = out[c];
+template <typename T, int R1, int R2, int YB_ = XfCfg<T>::YB>
+struct XfSmem {
+  static constexpr int N = R1 * R2, YB = YB_, NP = 3 * YB / 2;
+  static constexpr int US = N + 8;     // staged row stride: rows of one wave's pencils fall in different banks
+  static constexpr int OS = YB + 1;    // output staging stride (complex values)
+  static constexpr int HR = YB + 2;    // staged u rows per component (y halo of one row each side)
+  static constexpr size_t U = sizeof(T) * 3 * HR * US;
+  static constexpr size_t X = sizeof(cplx<T>) * NP * R1 * (R2 + 1);
+  static constexpr size_t O = sizeof(cplx<T>) * 3 * (N / 2 + 1) * OS;
+  static constexpr size_t XO = X > O ? X : O;
+  static constexpr size_t BYTES = U > XO ? U : XO;   // forward pass: staged u, exchange, output staging
+  static constexpr size_t BYTES_INV = XO;            // inverse pass: input staging, exchange
+};
+
+// Raw buffer access to the spectrum: a per-thread byte offset plus a uniform
+// one, so that no per-value 64-bit address stays live in registers.  Offsets
+// past num_records read 0 and drop stores.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t spec_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ cplx<float> bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float) {
+  return __builtin_bit_cast(cplx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ cplx<double> bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double) {
+  return __builtin_bit_cast(cplx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, cplx<float> v) {
+  using B = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, cplx<double> v) {
+  using B = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(B, v), r, (int)voff, (int)soff, 0);
 }
 
-// ---------------------------------------------------- pass x, forward ----
-// Real rows of r, two packed per complex pencil, to modes kx = 0 .. n/2 in
-// spec[c][kx][z][y] (runs of 128 bytes along y).
-template <typename T, int R1, int R2>
-__global__ __launch_bounds__(3 * XfCfg<T>::YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf(
-    const T *__restrict__ rin, const cplx<T> *__restrict__ tw, cplx<T> *__restrict__ spec) {
+// 16-byte raw buffer load: offsets at or past the buffer's size read 0
+// without a memory access.
+template <typename T>
+__device__ __forceinline__ Vec16<T> bload16(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  return __builtin_bit_cast(Vec16<T>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 0));
+}
+
+// ------------------------------------------------ pass x, forward + RHS ----
+// One block per (YB y rows, z), all three components.
+//  1. Stage u of the rows y0-1 .. y0+YB (the outer two only with advection).
+//     The same round of loads fetches this thread's first z neighbours,
+//     tile flags and force, so that their latency overlaps the staging.
+//  2. Right-hand side of eq. discreteNS1 per 16-byte run of one component:
+//     r = u - dt (upwind advection) + f_scale F.  x and y neighbours come from
+//     the staged rows, z neighbours and F from global memory; F is read only
+//     in tiles the spreading touched (fmode 1), everywhere (2) or nowhere (0).
+//     Upwind difference per direction: u_k (u_k > 0 ? u - u_minus : u_plus - u),
+//     zero when u_k = 0, the sum scaled by dt/h once.
+//  3. r replaces u in LDS; rows are transformed two per complex pencil and
+//     modes kx = 0 .. n/2 written to spec[c][kx][z][y] (runs of YB complex
+//     values along y).
+// r never goes to HBM.
+template <typename T, int R1, int R2, int YB, bool CONV>
+__global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf_rhs(
+    const T *__restrict__ u, const T *__restrict__ Fg, const int32_t *__restrict__ tile_touch, int fmode,
+    T dt_inv_h, T f_scale, const cplx<T> *__restrict__ tw, cplx<T> *__restrict__ spec) {
   using F4 = Fft4<T, R1, R2, false, false>;
-  using SM = XfSmem<T, R1, R2>;
-  constexpr int N = R1 * R2, P = F4::P, E = F4::E, YB = XfCfg<T>::YB, NP = 3 * YB / 2;
-  constexpr int NH = N / 2 + 1, mask = N - 1, NT = NP * P, US = SM::US, OS = SM::OS;
-  constexpr int64_t G = (int64_t)N * N * N;
+  using SM = XfSmem<T, R1, R2, YB>;
+  using V = Vec16<T>;
+  constexpr int N = R1 * R2, P = F4::P, E = F4::E, NP = 3 * YB / 2;
+  constexpr int NH = N / 2 + 1, mask = N - 1, NT = NP * P, US = SM::US, OS = SM::OS, HR = SM::HR;
+  constexpr int EPC = 16 / sizeof(T), CPR = N / EPC;
+  constexpr int64_t G = (int64_t)N * N * N, NN = (int64_t)N * N;
+  constexpr int RUNS = 3 * YB * CPR / NT;              // r runs per thread
+  static_assert(RUNS * NT == 3 * YB * CPR, "runs must divide among the threads");
+  constexpr int GMAX = sizeof(T) == 4 ? 8 : 4;
+  constexpr int GR = RUNS < GMAX ? RUNS : GMAX;        // runs whose global loads are issued together
+  static_assert(RUNS % GR == 0, "whole groups");
   __shared__ __attribute__((aligned(16))) unsigned char smem[SM::BYTES];
-  T *us = (T *)smem;                                   // [3][YB][US]
+  T *us = (T *)smem;                                   // [3][HR][US] u, row y0 - 1 + lr
   const int nyb = N / YB;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int y0 = (b % nyb) * YB, z = b / nyb;
   const int tid = threadIdx.x;
-  // 1. stage the block's rows: all 16-byte loads issued before the LDS stores
+  constexpr uint32_t TB = sizeof(T);
+  const __amdgpu_buffer_rsrc_t urs = spec_rsrc(u, (uint32_t)(3 * G * TB));
+  const uint32_t fbytes = fmode ? (uint32_t)(3 * G * TB) : 0u;
+  const __amdgpu_buffer_rsrc_t frs = spec_rsrc(Fg, fbytes);
+  const int nt = N >> 3;
+  // run k of this thread: staged row `row` (component row / YB, y = y0 + row % YB),
+  // 16 bytes at x4; returns the run's byte offset in plane z = 0
+  auto run_at = [&](int k, int &row, int &x4) {
+    const int e = tid + k * NT;
+    row = e / CPR;
+    x4 = e % CPR;
+    const int c = row / YB, y = y0 + row % YB;
+    return (uint32_t)((c * G + (int64_t)y * N + x4 * EPC) * TB);
+  };
+  auto has_force = [&](int k) {
+    if (fmode != 1) return fmode == 2;
+    int row, x4;
+    run_at(k, row, x4);
+    const int y = y0 + row % YB;
+    return tile_touch[((z >> 3) * nt + (y >> 3)) * nt + ((x4 * EPC) >> 3)] != 0;
+  };
+  V vzm[GR], vzp[GR], fv[GR];
+  bool has[RUNS];
+  auto issue = [&](int g0) {
+#pragma unroll
+    for (int k = 0; k < GR; k++) {
+      int row, x4;
+      const uint32_t at = run_at(g0 + k, row, x4);
+      if (CONV) {
+        vzm[k] = bload16<T>(urs, at + (uint32_t)(((z - 1) & mask) * NN * TB));
+        vzp[k] = bload16<T>(urs, at + (uint32_t)(((z + 1) & mask) * NN * TB));
+      }
+      fv[k] = bload16<T>(frs, has[g0 + k] ? at + (uint32_t)(z * NN * TB) : fbytes);
+    }
+  };
+  // 1. stage u: all 16-byte loads issued before the LDS stores
   {
-    using V = Vec16<T>;
-    constexpr int EPC = 16 / sizeof(T), CPR = N / EPC, TOT = 3 * YB * CPR, IT = (TOT + NT - 1) / NT;
+#pragma unroll
+    for (int k = 0; k < RUNS; k++) has[k] = has_force(k);
+    constexpr int RS = CONV ? HR : YB, TOT = 3 * RS * CPR, IT = (TOT + NT - 1) / NT;
     V tmp[IT];
-    auto src = [&](int e) {
-      const int row = e / CPR, x4 = e % CPR, c = row / YB, rr = row % YB;
-      return (const V *)(rin + c * G + ((int64_t)z * N + y0 + rr) * N + x4 * EPC);
+    auto split = [&](int e, int &c, int &lr, int &x4) {
+      const int row = e / CPR;
+      x4 = e % CPR;
+      c = row / RS;
+      lr = row % RS + (CONV ? 0 : 1);
     };
-    auto dst = [&](int e) { return (V *)(us + (e / CPR) * US + (e % CPR) * EPC); };
-    if constexpr (TOT % NT == 0) {
 #pragma unroll
-      for (int k = 0; k < IT; k++) tmp[k] = *src(tid + k * NT);
+    for (int k = 0; k < IT; k++) {
+      const int e = tid + k * NT;
+      if (TOT % NT == 0 || e < TOT) {
+        int c, lr, x4;
+        split(e, c, lr, x4);
+        const int y = (y0 + lr - 1) & mask;
+        tmp[k] = bload16<T>(urs, (uint32_t)((c * G + ((int64_t)z * N + y) * N + x4 * EPC) * TB));
+      }
+    }
+    issue(0);
 #pragma unroll
-      for (int k = 0; k < IT; k++) *dst(tid + k * NT) = tmp[k];
-    } else {
-#pragma unroll
-      for (int k = 0; k < IT; k++)
-        if (tid + k * NT < TOT) tmp[k] = *src(tid + k * NT);
-#pragma unroll
-      for (int k = 0; k < IT; k++)
-        if (tid + k * NT < TOT) *dst(tid + k * NT) = tmp[k];
+    for (int k = 0; k < IT; k++) {
+      const int e = tid + k * NT;
+      if (TOT % NT == 0 || e < TOT) {
+        int c, lr, x4;
+        split(e, c, lr, x4);
+        *(V *)(us + (c * HR + lr) * US + x4 * EPC) = tmp[k];
+      }
     }
   }
   __syncthreads();
-  // 2. this thread's values of its pencil (rows 2rp, 2rp+1 of component c)
+  // 2. r of this thread's runs
+  V out[RUNS];
+#pragma unroll
+  for (int g0 = 0; g0 < RUNS; g0 += GR) {
+    if (g0 > 0) issue(g0);
+#pragma unroll
+    for (int k = 0; k < GR; k++) {
+      int row, x4;
+      run_at(g0 + k, row, x4);
+      const int c = row / YB, lr = row % YB + 1;
+      const T *urow = us + (c * HR + lr) * US;
+      const V uc = *(const V *)(urow + x4 * EPC);
+      V r = uc;
+      if (CONV) {
+        V uk[3], vym, vyp;
+#pragma unroll
+        for (int cc = 0; cc < 3; cc++) uk[cc] = *(const V *)(us + (cc * HR + lr) * US + x4 * EPC);
+        vym = *(const V *)(urow - US + x4 * EPC);
+        vyp = *(const V *)(urow + US + x4 * EPC);
+        const T xl = urow[(x4 * EPC - 1) & mask], xr = urow[(x4 * EPC + EPC) & mask];
+#pragma unroll
+        for (int i = 0; i < EPC; i++) {
+          const T ucc = uc[i];
+          const T left = i == 0 ? xl : uc[i - 1];
+          const T right = i == EPC - 1 ? xr : uc[i + 1];
+          const T dx = uk[0][i] > T(0) ? ucc - left : right - ucc;
+          const T dy = uk[1][i] > T(0) ? ucc - vym[i] : vyp[i] - ucc;
+          const T dz = uk[2][i] > T(0) ? ucc - vzm[k][i] : vzp[k][i] - ucc;
+          const T acc = uk[0][i] * dx + uk[1][i] * dy + uk[2][i] * dz;
+          r[i] = ucc - dt_inv_h * acc;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < EPC; i++) {
+        T ri = r[i] + f_scale * fv[k][i];
+        asm volatile("" : "+v"(ri));   // materialise r here, so this group's loads die before the next
+        out[g0 + k][i] = ri;
+      }
+    }
+  }
+  __syncthreads();   // every staged u value has been read
+#pragma unroll
+  for (int k = 0; k < RUNS; k++) {
+    int row, x4;
+    run_at(k, row, x4);
+    *(V *)(us + row * US + x4 * EPC) = out[k];         // [3][YB][US] r
+  }
+  __syncthreads();
+  // 3. this thread's values of its pencil (rows 2rp, 2rp+1 of component c)
   const int p = tid / P, t = tid % P;
   const int c = p / (YB / 2), rp = p % (YB / 2);
   cplx<T> v[E];
@@ -333,7 +395,7 @@ __global__ __launch_bounds__(3 * XfCfg<T>::YB / 2 * (R1 < R2 ? R1 : R2)) void k_
   __syncthreads();   // the staged rows are dead; the buffer becomes pencil exchange space
   cplx<T> *xch = (cplx<T> *)smem + p * R1 * (R2 + 1);
   F4::run(v, t, xch, tw);
-  // 3. spectra of the two real rows: A = (Z[k] + conj Z[-k]) / 2, B = (Z[k] - conj Z[-k]) / 2i
+  // spectra of the two real rows: A = (Z[k] + conj Z[-k]) / 2, B = (Z[k] - conj Z[-k]) / 2i
   wave_sync();
 #pragma unroll
   for (int i = 0; i < R1 / P; i++)
@@ -352,19 +414,19 @@ __global__ __launch_bounds__(3 * XfCfg<T>::YB / 2 * (R1 < R2 ? R1 : R2)) void k_
     }
   }
   __syncthreads();
-  cplx<T> *out = (cplx<T> *)smem;                      // [3][NH][OS]
+  cplx<T> *outs = (cplx<T> *)smem;                     // [3][NH][OS]
 #pragma unroll
   for (int m = 0; m < KM; m++) {
     const int k = t + P * m;
     if (k < NH) {
-      out[(c * NH + k) * OS + 2 * rp] = A[m];
-      out[(c * NH + k) * OS + 2 * rp + 1] = B[m];
+      outs[(c * NH + k) * OS + 2 * rp] = A[m];
+      outs[(c * NH + k) * OS + 2 * rp + 1] = B[m];
     }
   }
   __syncthreads();
   for (int e = tid; e < 3 * NH * YB; e += NT) {
     const int yy = e % YB, ck = e / YB, k = ck % NH, cc = ck / NH;
-    spec[(((int64_t)cc * NH + k) * N + z) * N + y0 + yy] = out[ck * OS + yy];
+    spec[(((int64_t)cc * NH + k) * N + z) * N + y0 + yy] = outs[ck * OS + yy];
   }
 }
 
@@ -389,27 +451,6 @@ __global__ __launch_bounds__(256) void k_y(cplx<T> *__restrict__ spec, int64_t n
   for (int i = 0; i < R1 / P; i++)
 #pragma unroll
     for (int k2 = 0; k2 < R2; k2++) g[(t + P * i) + R1 * k2] = v[i * R2 + k2];
-}
-
-// Raw buffer access to the spectrum: a per-thread byte offset plus a uniform
-// one, so that no per-value 64-bit address stays live in registers.  Offsets
-// past num_records read 0 and drop stores.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t spec_rsrc(const void *p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
-}
-__device__ __forceinline__ cplx<float> bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float) {
-  return __builtin_bit_cast(cplx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-}
-__device__ __forceinline__ cplx<double> bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double) {
-  return __builtin_bit_cast(cplx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
-}
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, cplx<float> v) {
-  using B = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, v), r, (int)voff, (int)soff, 0);
-}
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, cplx<double> v) {
-  using B = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(B, v), r, (int)voff, (int)soff, 0);
 }
 
 // ------------------------------------------------- pass z with the solve ----
@@ -489,7 +530,7 @@ __global__ __launch_bounds__(3 * XfCfg<T>::YB / 2 * (R1 < R2 ? R1 : R2)) void k_
   constexpr int N = R1 * R2, P = F4::P, E = F4::E, YB = XfCfg<T>::YB, NP = 3 * YB / 2;
   constexpr int NH = N / 2 + 1, mask = N - 1, NT = NP * P;
   constexpr int64_t G = (int64_t)N * N * N;
-  __shared__ __attribute__((aligned(16))) unsigned char smem[XfSmem<T, R1, R2>::BYTES];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[XfSmem<T, R1, R2>::BYTES_INV];
   constexpr int OS = XfSmem<T, R1, R2>::OS;
   cplx<T> *stage = (cplx<T> *)smem;                   // [3][NH][OS]
   const int nyb = N / YB;
@@ -558,16 +599,16 @@ hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect
   cplx<T> *spec = (cplx<T> *)c->ws.spec;
   const cplx<T> *tw = (const cplx<T> *)c->ws.tw;
   {
-    PhaseScope ps(c, PH_RHS);
-    constexpr int V = 16 / sizeof(T);
-    hipLaunchKernelGGL(k_rhs_v<T>, dim3((unsigned)((c->G / V + 255) / 256)), dim3(256), 0, c->stream, u_in, Fg,
-                       c->ws.tile_touch, N, c->log2n, Fg ? fmode : 0, convect, (T)c->p.dt, (T)f_scale,
-                       (T)(1.0 / c->h), (T *)c->ws.r);
-  }
-  {
-    PhaseScope ps(c, PH_FFT_X);
-    hipLaunchKernelGGL((k_xf<T, R1, R2>), dim3(N * (N / YB)), dim3(3 * YB / 2 * P), 0, c->stream,
-                       (const T *)c->ws.r, tw, spec);
+    PhaseScope ps(c, PH_RHS_FFT_X);
+    const int fm = Fg ? fmode : 0;
+    const T dtih = (T)c->p.dt * (T)(1.0 / c->h);
+    constexpr int YR = XrCfg<T>::YB;
+    if (convect)
+      hipLaunchKernelGGL((k_xf_rhs<T, R1, R2, YR, true>), dim3(N * (N / YR)), dim3(3 * YR / 2 * P), 0, c->stream,
+                         u_in, Fg, c->ws.tile_touch, fm, dtih, (T)f_scale, tw, spec);
+    else
+      hipLaunchKernelGGL((k_xf_rhs<T, R1, R2, YR, false>), dim3(N * (N / YR)), dim3(3 * YR / 2 * P), 0, c->stream,
+                         u_in, Fg, c->ws.tile_touch, fm, dtih, (T)f_scale, tw, spec);
   }
   const int64_t npen = (int64_t)3 * NH * N;
   const unsigned ny = (unsigned)((npen + 256 / P - 1) / (256 / P));

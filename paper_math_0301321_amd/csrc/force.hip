@@ -5,8 +5,9 @@
 // CSR adjacency, its tether), so no two threads write the same output and the
 // result does not depend on scheduling.  Each edge / triple is evaluated once
 // per marker it touches; the window drive is added through a per-marker slot
-// of the drive list.  In the time step the same pass also writes the marker's
-// sorted record for the spreading.  Force laws: see include/ib.h.
+// of the drive list.  Lattice rest lengths and bend scales come from the
+// reference shape and weights, computed once when those are set.  In the time
+// step the same pass also writes the marker's sorted record for the spreading.  Force laws: see include/ib.h.
 #include "dev_common.h"
 #include "ib_internal.h"
 
@@ -21,34 +22,79 @@ __device__ __forceinline__ V3 ld3(const double *__restrict__ A, int64_t M, int64
 }
 __device__ __forceinline__ double nrm(const V3 &a) { return sqrt(a.x * a.x + a.y * a.y + a.z * a.z); }
 
-// Force on marker q from the stretch edge (q, o).
+// Reference-shape constants of a lattice marker q = (i1, i2), [6][M]:
+//   0, 1: rest length Le of the edge (q, q + 1 along index 1) and Ks w / Le^2
+//         (w the mean of the two endpoint weights);
+//   2, 3: the same for the edge to the next row (index 2, wrapping when periodic);
+//   4, 5: Kb w_q / Lc^4 of the bend triples centred at q along index 1 and 2
+//         (Lc the mean rest length of the triple's two edges);
+// zero where the edge or triple does not exist.  They depend only on X_ref and
+// w, so they are computed when those are set; the stiffness multipliers k are
+// applied at run time.
+__global__ __launch_bounds__(256) void k_lattice_pre(Material m, double *__restrict__ pre) {
+  const int64_t q = gtid();
+  const int64_t M = m.M;
+  if (q >= M) return;
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int l = 0; l < m.lat.n; l++) {
+    const LatticeDev &L = m.lat.l[l];
+    if (q < L.first || q >= L.first + (int64_t)L.n1 * L.n2) continue;
+    const int64_t rel = q - L.first, n1 = L.n1, n2 = L.n2;
+    const int64_t i1 = rel % n1, i2 = rel / n1;
+    const bool per = L.periodic2 != 0;
+    auto idx = [&](int64_t a1, int64_t a2) { return L.first + a2 * n1 + a1; };
+    auto w2 = [&](int64_t a2) { return per ? (a2 + n2) % n2 : a2; };
+    const V3 yq = ld3(m.X_ref, M, q);
+    auto edge = [&](int64_t o, double &le, double &ke) {
+      const V3 yo = ld3(m.X_ref, M, o);
+      const V3 dy{yo.x - yq.x, yo.y - yq.y, yo.z - yq.z};
+      le = nrm(dy);
+      ke = L.Ks * (0.5 * (m.w[q] + m.w[o])) / (le * le);
+    };
+    auto bend = [&](int64_t a, int64_t b) {
+      const V3 ya = ld3(m.X_ref, M, a), yb = ld3(m.X_ref, M, b);
+      const V3 e1{yq.x - ya.x, yq.y - ya.y, yq.z - ya.z}, e2{yb.x - yq.x, yb.y - yq.y, yb.z - yq.z};
+      const double Lc = 0.5 * (nrm(e1) + nrm(e2));
+      return L.Kb * m.w[q] / (Lc * Lc * Lc * Lc);
+    };
+    if (L.Ks != 0.0) {
+      if (i1 < n1 - 1) edge(idx(i1 + 1, i2), v[0], v[1]);
+      if (per || i2 < n2 - 1) edge(idx(i1, w2(i2 + 1)), v[2], v[3]);
+    }
+    if (L.Kb != 0.0) {
+      if (i1 >= 1 && i1 <= n1 - 2) v[4] = bend(idx(i1 - 1, i2), idx(i1 + 1, i2));
+      if (per || (i2 >= 1 && i2 <= n2 - 2)) v[5] = bend(idx(i1, w2(i2 - 1)), idx(i1, w2(i2 + 1)));
+    }
+    break;
+  }
+  for (int j = 0; j < 6; j++) pre[j * M + q] = v[j];
+}
+
+// Force on marker q from the stretch edge (q, o) with rest length le and
+// ke = Ks w / le^2 (of the edge's lower endpoint).
 __device__ __forceinline__ void stretch_on(const Material &m, const double *__restrict__ X, int64_t q,
-                                           int64_t o, const V3 &xq, double Ks, V3 &f) {
+                                           int64_t o, const V3 &xq, double le, double ke, V3 &f) {
   const int64_t M = m.M;
   const V3 xo = ld3(X, M, o);
-  const V3 yq = ld3(m.X_ref, M, q), yo = ld3(m.X_ref, M, o);
   const V3 d{xo.x - xq.x, xo.y - xq.y, xo.z - xq.z};
-  const V3 dy{yo.x - yq.x, yo.y - yq.y, yo.z - yq.z};
-  const double len = nrm(d), Le = nrm(dy);
-  const double K = Ks * (0.5 * (m.k[q] + m.k[o])) * (0.5 * (m.w[q] + m.w[o]));
-  const double s = K * (len - Le) / (Le * Le) / len;
+  const double len = nrm(d);
+  const double s = ke * (0.5 * (m.k[q] + m.k[o])) * (len - le) / len;
   f.x += s * d.x;
   f.y += s * d.y;
   f.z += s * d.z;
 }
 
-// Force on marker q from the bend triple (a, c, b); role: 0 = end, 1 = centre.
+// Force on marker q from the bend triple (a, c, b) with cb = Kb w_c / Lc^4;
+// role: 0 = end, 1 = centre.
 __device__ __forceinline__ void bend_on(const Material &m, const double *__restrict__ X, int64_t a,
-                                        int64_t c, int64_t b, int role, double Kb, V3 &f) {
+                                        int64_t c, int64_t b, int role, double cb, V3 &f) {
   const int64_t M = m.M;
   const V3 xa = ld3(X, M, a), xb = ld3(X, M, b), xc = ld3(X, M, c);
   const V3 ya = ld3(m.X_ref, M, a), yb = ld3(m.X_ref, M, b), yc = ld3(m.X_ref, M, c);
   const V3 v{(xa.x - 2.0 * xc.x + xb.x) - (ya.x - 2.0 * yc.x + yb.x),
              (xa.y - 2.0 * xc.y + xb.y) - (ya.y - 2.0 * yc.y + yb.y),
              (xa.z - 2.0 * xc.z + xb.z) - (ya.z - 2.0 * yc.z + yb.z)};
-  const V3 e1{yc.x - ya.x, yc.y - ya.y, yc.z - ya.z}, e2{yb.x - yc.x, yb.y - yc.y, yb.z - yc.z};
-  const double Lc = 0.5 * (nrm(e1) + nrm(e2));
-  const double K = Kb * m.k[c] * m.w[c] / (Lc * Lc * Lc * Lc);
+  const double K = cb * m.k[c];
   const double s = role ? 2.0 * K : -K;
   f.x += s * v.x;
   f.y += s * v.y;
@@ -57,6 +103,8 @@ __device__ __forceinline__ void bend_on(const Material &m, const double *__restr
 
 __device__ void lattice_force(const Material &m, const LatticeDev &L, const double *__restrict__ X,
                               int64_t q, const V3 &xq, V3 &f) {
+  const int64_t M = m.M;
+  const double *P = m.lat_pre;
   const int64_t rel = q - L.first;
   const int64_t n1 = L.n1, n2 = L.n2;
   const int64_t i1 = rel % n1, i2 = rel / n1;
@@ -65,23 +113,40 @@ __device__ void lattice_force(const Material &m, const LatticeDev &L, const doub
   auto w2 = [&](int64_t a2) { return per ? (a2 + n2) % n2 : a2; };
   const bool has_dn = per || i2 > 0, has_up = per || i2 < n2 - 1;
   if (L.Ks != 0.0) {
-    if (i1 > 0) stretch_on(m, X, q, idx(i1 - 1, i2), xq, L.Ks, f);
-    if (i1 < n1 - 1) stretch_on(m, X, q, idx(i1 + 1, i2), xq, L.Ks, f);
-    if (has_dn) stretch_on(m, X, q, idx(i1, w2(i2 - 1)), xq, L.Ks, f);
-    if (has_up) stretch_on(m, X, q, idx(i1, w2(i2 + 1)), xq, L.Ks, f);
+    if (i1 > 0) {
+      const int64_t o = idx(i1 - 1, i2);
+      stretch_on(m, X, q, o, xq, P[o], P[M + o], f);
+    }
+    if (i1 < n1 - 1) stretch_on(m, X, q, idx(i1 + 1, i2), xq, P[q], P[M + q], f);
+    if (has_dn) {
+      const int64_t o = idx(i1, w2(i2 - 1));
+      stretch_on(m, X, q, o, xq, P[2 * M + o], P[3 * M + o], f);
+    }
+    if (has_up) stretch_on(m, X, q, idx(i1, w2(i2 + 1)), xq, P[2 * M + q], P[3 * M + q], f);
   }
   if (L.Kb != 0.0) {
+    const double *C1 = P + 4 * M, *C2 = P + 5 * M;
     // direction 1: centres 1 .. n1-2
-    if (i1 >= 1 && i1 <= n1 - 2) bend_on(m, X, idx(i1 - 1, i2), q, idx(i1 + 1, i2), 1, L.Kb, f);
-    if (i1 + 1 <= n1 - 2) bend_on(m, X, q, idx(i1 + 1, i2), idx(i1 + 2, i2), 0, L.Kb, f);
-    if (i1 - 1 >= 1) bend_on(m, X, idx(i1 - 2, i2), idx(i1 - 1, i2), q, 0, L.Kb, f);
+    if (i1 >= 1 && i1 <= n1 - 2) bend_on(m, X, idx(i1 - 1, i2), q, idx(i1 + 1, i2), 1, C1[q], f);
+    if (i1 + 1 <= n1 - 2) {
+      const int64_t c = idx(i1 + 1, i2);
+      bend_on(m, X, q, c, idx(i1 + 2, i2), 0, C1[c], f);
+    }
+    if (i1 - 1 >= 1) {
+      const int64_t c = idx(i1 - 1, i2);
+      bend_on(m, X, idx(i1 - 2, i2), c, q, 0, C1[c], f);
+    }
     // direction 2: centres 1 .. n2-2, or every row when periodic
     auto centre_ok = [&](int64_t c2) { return per || (c2 >= 1 && c2 <= n2 - 2); };
-    if (centre_ok(i2)) bend_on(m, X, idx(i1, w2(i2 - 1)), q, idx(i1, w2(i2 + 1)), 1, L.Kb, f);
-    if ((per || i2 + 1 < n2) && centre_ok(i2 + 1))
-      bend_on(m, X, q, idx(i1, w2(i2 + 1)), idx(i1, w2(i2 + 2)), 0, L.Kb, f);
-    if ((per || i2 - 1 >= 0) && centre_ok(i2 - 1))
-      bend_on(m, X, idx(i1, w2(i2 - 2)), idx(i1, w2(i2 - 1)), q, 0, L.Kb, f);
+    if (centre_ok(i2)) bend_on(m, X, idx(i1, w2(i2 - 1)), q, idx(i1, w2(i2 + 1)), 1, C2[q], f);
+    if ((per || i2 + 1 < n2) && centre_ok(i2 + 1)) {
+      const int64_t c = idx(i1, w2(i2 + 1));
+      bend_on(m, X, q, c, idx(i1, w2(i2 + 2)), 0, C2[c], f);
+    }
+    if ((per || i2 - 1 >= 0) && centre_ok(i2 - 1)) {
+      const int64_t c = idx(i1, w2(i2 - 1));
+      bend_on(m, X, idx(i1, w2(i2 - 2)), c, q, 0, C2[c], f);
+    }
   }
 }
 
@@ -184,6 +249,13 @@ __global__ __launch_bounds__(256) void k_force_rec(Material m, const double *__r
   r.F[2] = (T)f.z;
   r.key = cell_key(cc[0], cc[1], cc[2], log2nt);
   recs[inv[q]] = r;
+}
+
+hipError_t launch_lattice_pre(ib_ctx *c) {
+  if (c->M == 0 || !c->ws.lat_pre) return hipSuccess;
+  hipLaunchKernelGGL(k_lattice_pre, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream, c->mat,
+                     c->ws.lat_pre);
+  return hipGetLastError();
 }
 
 hipError_t launch_force(ib_ctx *c, const double *X, double amp, double *F) {

@@ -84,6 +84,8 @@ struct Material {
   const double *sp_rest;      // [2S]
   double K_spring;
   int64_t M;
+  // reference-shape constants of the lattices, [6][M] (see k_lattice_pre), or null
+  const double *lat_pre;
 };
 
 struct Workspace {
@@ -125,12 +127,13 @@ struct Workspace {
   // spring adjacency
   int32_t *sp_rowptr, *sp_col;
   double *sp_rest;
+  double *lat_pre;             // [6][M] lattice reference constants (null without lattice moduli)
 };
 
 // Phases timed by the optional HIP-event instrumentation.
 enum Phase {
   PH_BIN = 0, PH_FORCE, PH_PREP, PH_SPREAD, PH_SPLIT, PH_GATHER, PH_RHS, PH_FFT_X, PH_FFT_Y, PH_FFT_Z_SOLVE,
-  PH_FFT_Y_INV, PH_FFT_X_INV, PH_INTERP, PH_ADJ_INTERP, PH_ADJ_SPREAD, PH_HESSVEC, PH_COUNT
+  PH_FFT_Y_INV, PH_FFT_X_INV, PH_INTERP, PH_ADJ_INTERP, PH_ADJ_SPREAD, PH_HESSVEC, PH_RHS_FFT_X, PH_COUNT
 };
 
 struct TimerRec {
@@ -207,6 +210,8 @@ hipError_t launch_adj_interp(ib_ctx *c, const T *u_np1, double *Xbar);   // stag
 template <typename T>
 hipError_t launch_adj_spread(ib_ctx *c, const T *ubar_n, const double *F, double *Xbar, double *fbar);
 hipError_t launch_hessvec(ib_ctx *c, const double *X, const double *v, double *Xbar, double *kbar);
+// reference-shape constants of the lattices from X_ref and w (at creation and when they are set)
+hipError_t launch_lattice_pre(ib_ctx *c);
 
 // instrumentation: event pair around a phase when timing is on
 void timer_begin(ib_ctx *c, int phase);

@@ -55,7 +55,7 @@ class ib_elastic(C.Structure):
 EXPORTS = ["ib_create", "ib_destroy", "ib_set_material", "ib_set_stream", "ib_step", "ib_force",
            "ib_spread", "ib_interp", "ib_fluid", "ib_bin", "ib_adjoint_step", "ib_last_error",
            "ib_workspace_bytes", "ib_timers_enable", "ib_timers_select", "ib_timers_read", "ib_timer_name"]
-IB_N_TIMERS = 16
+IB_N_TIMERS = 32
 
 _lib = None
 
