@@ -42,7 +42,8 @@ def worklist_sizes(wl, ncu=256):
     """Sizes of the spreading work list for the markers at X0: 8^3-cell tiles, the sorted
     markers cut into chunks of max(256, ceil(M / (6 ncu))) markers (one per spreading wave),
     an item per (tile, chunk) part.  Returns items, tiles with markers, tiles the spread
-    force reaches, and the tiles cut into several items with their items."""
+    force reaches, the tiles cut into several items with their items, and the markers of
+    lattices with stretch or bend moduli."""
     import numpy as np
     n, nt = wl.N, wl.N // 8
     c = np.floor(wl.X0 / wl.h).astype(np.int64) & (n - 1)
@@ -61,8 +62,10 @@ def worklist_sizes(wl, ncu=256):
         for dy in (-1, 0, 1):
             for dx in (-1, 0, 1):
                 touched |= np.roll(occ, (dz, dy, dx), axis=(0, 1, 2))
+    lat = sum(L.n1 * L.n2 for L in wl.lattices if L.Ks != 0.0 or L.Kb != 0.0)
     return {"items": items, "tiles_with_markers": int(occ.sum()), "tiles_touched": int(touched.sum()),
-            "split_items": split_items, "split_tiles": int((nit > 1).sum()), "chunk": chunk}
+            "split_items": split_items, "split_tiles": int((nit > 1).sum()), "chunk": chunk,
+            "lattice_markers": int(lat)}
 
 
 def phase_bytes(phase, N, M, b, wls):
@@ -75,7 +78,8 @@ def phase_bytes(phase, N, M, b, wls):
     halo = 3 * 11 ** 3 * b                        # one work item's spread halo
     items, touched = wls["items"], wls["tiles_touched"]
     return {
-        "force": M * (24 + 8 + 8 + 24 + 8 + 4 + 4 + rec),     # X, w, k, X_ref, kappa, inv, drive slot; record
+        # X, w, k, X_ref, kappa, inv, drive slot; record; 6 lattice constants of each lattice marker
+        "force": M * (24 + 8 + 8 + 24 + 8 + 4 + 4 + rec) + 48 * wls.get("lattice_markers", 0),
         "spread": M * rec + items * halo,                       # records in, item halos out
         "split": wls["split_items"] * halo + wls["split_tiles"] * halo,   # split tiles' halos in, sums out
         "gather": items * halo + touched * 512 * 3 * b,         # halos in, touched tiles out

@@ -299,7 +299,7 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
     chk_alloc(dalloc(c, &w.scan_tmp, 3 * ((ntiles + 1023) / 1024)));
     chk_alloc(dalloc_bytes(c, &w.partials, c->item_cap * kPartStride * (int64_t)ts));
   }
-  chk_alloc(dalloc_bytes(c, &w.r, 3 * c->G * (int64_t)ts));
+  if (!fluid_reg_supported(n)) chk_alloc(dalloc_bytes(c, &w.r, 3 * c->G * (int64_t)ts));   // the fused path keeps r in LDS
   chk_alloc(dalloc_bytes(c, &w.spec, 3 * nh * (int64_t)n * n * 2 * (int64_t)ts));
   chk_alloc(dalloc(c, &w.nonfinite, 1));
   chk_alloc(dalloc_bytes(c, &w.tw, 2 * (int64_t)n * (int64_t)ts));

@@ -113,7 +113,7 @@ struct Workspace {
   int32_t *touch_list;         // [ntiles] tiles the spread force reaches
   int32_t *scan_tmp;           // [3 ceil(ntiles / 1024)] per-block scan totals
   void *partials;              // [item_cap][kPartStride] each item's spread halo, [3][11^3] + pad
-  void *r;                     // [3][G] right-hand side
+  void *r;                     // [3][G] right-hand side (radix-2 path only; null for n = 32 .. 256)
   void *spec;                  // [3][n/2+1][n][n] complex spectrum
   int32_t *nonfinite;          // [1] flag for checked mode
   // tables (fluid precision)
