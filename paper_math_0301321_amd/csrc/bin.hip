@@ -15,7 +15,7 @@
 namespace ib {
 
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortItems = 8;    // 2048 keys per block: several blocks per CU hide the scatter's latency
 constexpr int kSortChunk = kSortThreads * kSortItems;
 
 __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ X, int64_t M, double h,

@@ -51,4 +51,12 @@ __device__ __forceinline__ int64_t gtid() {
   return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 }
 
+// Block index remapped so that each XCD (8 per device; the dispatcher deals
+// blocks to them round-robin) runs one contiguous range of logical blocks and
+// neighbouring blocks share its L2.  A bijection of [0, nblk) for any nblk.
+__device__ __forceinline__ int xcd_block(int b, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7, x = b & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 }  // namespace ib

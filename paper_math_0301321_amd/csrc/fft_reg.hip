@@ -165,12 +165,9 @@ struct Fft4 {
   }
 };
 
-// Block index remapped so consecutive work lands on one XCD (8 per device,
-// blocks dealt round-robin): neighbouring z-planes then share that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int b, int nblk) {
-  if (nblk % 8) return b;
-  return (b % 8) * (nblk / 8) + b / 8;
-}
+// Blocks go to XCDs in contiguous ranges (xcd_block): neighbouring z-planes
+// then share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nblk) { return xcd_block(b, nblk); }
 
 // --------------------------------------------- pass x, block shapes ----
 template <typename T>
@@ -344,12 +341,14 @@ __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf_rhs(
       run_at(g0 + k, row, x4);
       const int c = row / YB, lr = row % YB + 1;
       const T *urow = us + (c * HR + lr) * US;
-      const V uc = *(const V *)(urow + x4 * EPC);
-      V r = uc;
+      V r;
+      if (!CONV) r = *(const V *)(urow + x4 * EPC);
       if (CONV) {
-        V uk[3], vym, vyp;
+        V uk[3], vym, vyp, uc;
 #pragma unroll
         for (int cc = 0; cc < 3; cc++) uk[cc] = *(const V *)(us + (cc * HR + lr) * US + x4 * EPC);
+#pragma unroll
+        for (int i = 0; i < EPC; i++) uc[i] = c == 0 ? uk[0][i] : (c == 1 ? uk[1][i] : uk[2][i]);
         vym = *(const V *)(urow - US + x4 * EPC);
         vyp = *(const V *)(urow + US + x4 * EPC);
         const T xl = urow[(x4 * EPC - 1) & mask], xr = urow[(x4 * EPC + EPC) & mask];
