@@ -174,6 +174,12 @@ template <typename T>
 struct XfCfg {
   static constexpr int YB = sizeof(T) == 4 ? 16 : 8;   // rows per block: 128-byte runs of complex
 };
+// rows per block of the inverse x pass (16 in FP32: reads of 128-byte runs
+// outweigh the occupancy that fewer rows would give)
+template <typename T>
+struct XiCfg {
+  static constexpr int YB = XfCfg<T>::YB;
+};
 // rows per block of the forward x pass with the right-hand side: 8 keeps the
 // staged rows and their y halo within a third of the LDS, so that several
 // blocks share a CU and hide each other's load latency
@@ -522,15 +528,15 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ?
 }
 
 // ------------------------------------------------------ pass x, inverse ----
-template <typename T, int R1, int R2>
-__global__ __launch_bounds__(3 * XfCfg<T>::YB / 2 * (R1 < R2 ? R1 : R2)) void k_xi(
+template <typename T, int R1, int R2, int YB>
+__global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xi(
     const cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ tw, T scale, T *__restrict__ u) {
   using F4 = Fft4<T, R1, R2, true, false>;
-  constexpr int N = R1 * R2, P = F4::P, E = F4::E, YB = XfCfg<T>::YB, NP = 3 * YB / 2;
+  constexpr int N = R1 * R2, P = F4::P, E = F4::E, NP = 3 * YB / 2;
   constexpr int NH = N / 2 + 1, mask = N - 1, NT = NP * P;
   constexpr int64_t G = (int64_t)N * N * N;
-  __shared__ __attribute__((aligned(16))) unsigned char smem[XfSmem<T, R1, R2>::BYTES_INV];
-  constexpr int OS = XfSmem<T, R1, R2>::OS;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[XfSmem<T, R1, R2, YB>::BYTES_INV];
+  constexpr int OS = XfSmem<T, R1, R2, YB>::OS;
   cplx<T> *stage = (cplx<T> *)smem;                   // [3][NH][OS]
   const int nyb = N / YB;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -626,7 +632,8 @@ hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect
   }
   {
     PhaseScope ps(c, PH_FFT_X_INV);
-    hipLaunchKernelGGL((k_xi<T, R1, R2>), dim3(N * (N / YB)), dim3(3 * YB / 2 * P), 0, c->stream, spec, tw,
+    constexpr int YI = XiCfg<T>::YB;
+    hipLaunchKernelGGL((k_xi<T, R1, R2, YI>), dim3(N * (N / YI)), dim3(3 * YI / 2 * P), 0, c->stream, spec, tw,
                        (T)(1.0 / (double)c->G), u_out);
   }
   return hipGetLastError();
