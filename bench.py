@@ -169,7 +169,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--fp64-steps", type=int, default=None, help="steps of the FP64 comparison run (default: --steps)")
     ap.add_argument("--grid", type=int, default=256)
-    ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    ap.add_argument("--cpu-sample-steps", type=int, default=8,
+                    help="oracle steps timed on the host (one step of the default workload takes ~2 s on 16 cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
