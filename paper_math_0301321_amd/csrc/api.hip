@@ -278,7 +278,7 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
       if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
         c->ncu = prop.multiProcessorCount;
     }
-    c->item_grid = c->ncu * (c->fp32 ? 6 : 3);
+    c->item_grid = c->ncu * (c->fp32 ? 8 : 4);   // spreading waves: as many as fit in LDS at once
     c->chunk = (int)std::max<int64_t>(256, (M + c->item_grid - 1) / std::max(1, c->item_grid));
     c->nchunks = (int)((M + c->chunk - 1) / c->chunk);
     c->item_cap = std::min<int64_t>(ntiles, M) + c->nchunks + 1;

@@ -79,11 +79,15 @@ struct alignas(16) SpreadG {
   uint32_t key;
 };
 
+// Markers are staged kStage at a time: half a record batch, so that the
+// staging and the accumulator fit eight waves per CU (FP32).
+constexpr int kStage = 32;
+
 template <typename T>
 struct SpreadSmem {
   T acc[kPartStride];             // the wave's halo accumulator, [3][11^3] + pad
-  SpreadG<T> g[64][4];            // staging: force times x-weights, [marker][a]
-  T wyz[64][16];                  // staging: y-weight times z-weight, [marker][b * 4 + c]
+  SpreadG<T> g[kStage][4];        // staging: force times x-weights, [marker][a]
+  T wyz[kStage][16];              // staging: y-weight times z-weight, [marker][b * 4 + c]
 };
 
 constexpr int kSpreadRing = 4;    // 64-marker batches of records in flight per wave
@@ -152,56 +156,64 @@ __global__ __launch_bounds__(64) void k_spread(const int32_t *__restrict__ chunk
   // batch kSpreadRing batches ahead (the slots are never moved: a register
   // move would wait for the load in flight)
   auto batch = [&](Rec<T> &r, int64_t jb) {
-    const int cnt = (int)max((int64_t)0, min((int64_t)64, ce - jb));
-    wave_sync_lds();   // the previous batch's staging has been consumed
-    if (lane < cnt) {
-      T wx[4], wy[4], wz[4];
-      phi4<T>(r.f[0], wx);
-      phi4<T>(r.f[1], wy);
-      phi4<T>(r.f[2], wz);
-#pragma unroll
-      for (int a = 0; a < 4; a++) {
-        SpreadG<T> g;
-        g.g[0] = r.F[0] * wx[a];
-        g.g[1] = r.F[1] * wx[a];
-        g.g[2] = r.F[2] * wx[a];
-        g.key = r.key;
-        sm.g[lane][a] = g;
-      }
-#pragma unroll
-      for (int b = 0; b < 4; b++)
-#pragma unroll
-        for (int c = 0; c < 4; c++) sm.wyz[lane][b * 4 + c] = wy[b] * wz[c];
-    }
+    const int cnt64 = (int)max((int64_t)0, min((int64_t)64, ce - jb));
+    // the lanes' weights, computed once for the whole batch
+    T wx[4], wy[4], wz[4];
+    phi4<T>(r.f[0], wx);
+    phi4<T>(r.f[1], wy);
+    phi4<T>(r.f[2], wz);
+    const Rec<T> rr = r;
     r = recs[min(jb + 64 * kSpreadRing + lane, ce - 1)];
-    wave_sync_lds();
-    int m = 0;
-    // eight markers at a time: their LDS reads issue together
-    for (; m + 8 <= cnt; m += 8) {
-      SpreadG<T> g[8];
-      T w[8];
 #pragma unroll
-      for (int u = 0; u < 8; u++) {
-        g[u] = sm.g[m + u][oa];
-        w[u] = sm.wyz[m + u][ob * 4 + oc];
+    for (int half = 0; half < 64 / kStage; half++) {
+      const int cnt = min(kStage, cnt64 - half * kStage);
+      if (cnt <= 0) break;
+      wave_sync_lds();   // the previous staging has been consumed
+      if (lane >= half * kStage && lane < half * kStage + cnt) {
+        const int sl = lane - half * kStage;
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+          SpreadG<T> g;
+          g.g[0] = rr.F[0] * wx[a];
+          g.g[1] = rr.F[1] * wx[a];
+          g.g[2] = rr.F[2] * wx[a];
+          g.key = rr.key;
+          sm.g[sl][a] = g;
+        }
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+#pragma unroll
+          for (int c = 0; c < 4; c++) sm.wyz[sl][b * 4 + c] = wy[b] * wz[c];
       }
+      wave_sync_lds();
+      int m = 0;
+      // eight markers at a time: their LDS reads issue together
+      for (; m + 8 <= cnt; m += 8) {
+        SpreadG<T> g[8];
+        T w[8];
 #pragma unroll
-      for (int u = 0; u < 8; u++) {
-        const uint32_t k = __builtin_amdgcn_readfirstlane(g[u].key);
+        for (int u = 0; u < 8; u++) {
+          g[u] = sm.g[m + u][oa];
+          w[u] = sm.wyz[m + u][ob * 4 + oc];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          const uint32_t k = __builtin_amdgcn_readfirstlane(g[u].key);
+          if (k != cur) switch_cell(k);
+          a0 += g[u].g[0] * w[u];
+          a1 += g[u].g[1] * w[u];
+          a2 += g[u].g[2] * w[u];
+        }
+      }
+      for (; m < cnt; m++) {
+        const SpreadG<T> g = sm.g[m][oa];
+        const T w = sm.wyz[m][ob * 4 + oc];
+        const uint32_t k = __builtin_amdgcn_readfirstlane(g.key);
         if (k != cur) switch_cell(k);
-        a0 += g[u].g[0] * w[u];
-        a1 += g[u].g[1] * w[u];
-        a2 += g[u].g[2] * w[u];
+        a0 += g.g[0] * w;
+        a1 += g.g[1] * w;
+        a2 += g.g[2] * w;
       }
-    }
-    for (; m < cnt; m++) {
-      const SpreadG<T> g = sm.g[m][oa];
-      const T w = sm.wyz[m][ob * 4 + oc];
-      const uint32_t k = __builtin_amdgcn_readfirstlane(g.key);
-      if (k != cur) switch_cell(k);
-      a0 += g.g[0] * w;
-      a1 += g.g[1] * w;
-      a2 += g.g[2] * w;
     }
   };
   static_assert(kSpreadRing == 4, "the batch loop below is unrolled for four ring slots");
