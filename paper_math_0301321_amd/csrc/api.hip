@@ -93,7 +93,7 @@ void free_ws(ib_ctx *c) {
   void *ptrs[] = {w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.hist, w.tile_start, w.recs, w.Flag, w.fb,
                   w.Fgrid, w.tile_nit, w.tile_item0, w.tile_touch, w.item_tile, w.chunk_item0, w.nitems, w.split_list, w.touch_list, w.scan_tmp, w.partials,
                   w.r, w.spec, w.nonfinite, w.tw, w.lam, w.sgrad, w.drive_idx, w.drive_dir, w.sp_rowptr, w.sp_col,
-                  w.sp_rest, w.inv, w.drive_slot, w.lat_pre};
+                  w.sp_rest, w.inv, w.drive_slot, w.lat_pre, w.touch_bits};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->ws = Workspace{};
@@ -291,6 +291,7 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
     chk_alloc(dalloc(c, &w.tile_nit, ntiles));
     chk_alloc(dalloc(c, &w.tile_item0, ntiles));
     chk_alloc(dalloc(c, &w.tile_touch, ntiles));
+    chk_alloc(dalloc(c, &w.touch_bits, (ntiles + 31) / 32));
     chk_alloc(dalloc(c, &w.item_tile, c->item_cap));
     chk_alloc(dalloc(c, &w.chunk_item0, c->nchunks + 1));
     chk_alloc(dalloc(c, &w.nitems, 3));

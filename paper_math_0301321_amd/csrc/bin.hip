@@ -266,13 +266,21 @@ __device__ __forceinline__ int3 scan1024(int3 v, int3 *wsum, int3 *total) {
 __global__ __launch_bounds__(1024) void k_item_scan_blocks(const int32_t *__restrict__ tile_start, int64_t ntiles,
                                                            int log2nt, int chunk, int3 *__restrict__ block_tot,
                                                            int32_t *__restrict__ tile_nit,
-                                                           int32_t *__restrict__ tile_touch) {
+                                                           int32_t *__restrict__ tile_touch,
+                                                           uint32_t *__restrict__ touch_bits) {
   __shared__ int3 wsum[16];
   const int64_t t = (int64_t)blockIdx.x * 1024 + threadIdx.x;
   const int3 v = tile_items(tile_start, t, ntiles, log2nt, chunk);
   if (t < ntiles) {
     tile_nit[t] = v.x;
     tile_touch[t] = v.z;
+  }
+  // the same flags as bits: a wave's 64 consecutive tiles are two words
+  const uint64_t bits = __ballot(t < ntiles && v.z != 0);
+  if ((threadIdx.x & 63) == 0) {
+    const int64_t w0 = t >> 5, nw = (ntiles + 31) >> 5;
+    if (w0 < nw) touch_bits[w0] = (uint32_t)bits;
+    if (w0 + 1 < nw) touch_bits[w0 + 1] = (uint32_t)(bits >> 32);
   }
   int3 tot;
   (void)scan1024(v, wsum, &tot);
@@ -368,7 +376,7 @@ hipError_t launch_bin(ib_ctx *c, const double *X) {
   const int nsb = (int)((nt + 1023) / 1024);
   int3 *tmp = (int3 *)ws.scan_tmp;
   hipLaunchKernelGGL(k_item_scan_blocks, dim3(nsb), dim3(1024), 0, c->stream, ws.tile_start, nt, c->log2nt,
-                     c->chunk, tmp, ws.tile_nit, ws.tile_touch);
+                     c->chunk, tmp, ws.tile_nit, ws.tile_touch, ws.touch_bits);
   hipLaunchKernelGGL(k_item_scan_top, dim3(1), dim3(1024), 0, c->stream, tmp, nsb, ws.nitems, c->nchunks,
                      ws.chunk_item0);
   hipLaunchKernelGGL(k_item_scan_write, dim3(nsb), dim3(1024), 0, c->stream, ws.tile_nit, nt, ws.tile_touch,

@@ -247,7 +247,7 @@ __device__ __forceinline__ Vec16<T> bload16(__amdgpu_buffer_rsrc_t r, uint32_t v
 // r never goes to HBM.
 template <typename T, int R1, int R2, int YB, bool CONV>
 __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf_rhs(
-    const T *__restrict__ u, const T *__restrict__ Fg, const int32_t *__restrict__ tile_touch, int fmode,
+    const T *__restrict__ u, const T *__restrict__ Fg, const uint32_t *__restrict__ touch_bits, int fmode,
     T dt_inv_h, T f_scale, const cplx<T> *__restrict__ tw, cplx<T> *__restrict__ spec) {
   using F4 = Fft4<T, R1, R2, false, false>;
   using SM = XfSmem<T, R1, R2, YB>;
@@ -281,12 +281,16 @@ __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf_rhs(
     const int c = row / YB, y = y0 + row % YB;
     return (uint32_t)((c * G + (int64_t)y * N + x4 * EPC) * TB);
   };
+  // the touched flags of the block's row of tiles (one word: the rows y0 .. y0+7
+  // are one tile row, and a tile row of n <= 256 lies within one 32-bit word)
+  static_assert(YB == 8 && N <= 256, "one tile row per block");
+  const int trow = ((z >> 3) * nt + (y0 >> 3)) * nt;
+  const uint32_t tbits = fmode == 1 ? touch_bits[trow >> 5] >> (trow & 31) : 0u;
   auto has_force = [&](int k) {
     if (fmode != 1) return fmode == 2;
     int row, x4;
     run_at(k, row, x4);
-    const int y = y0 + row % YB;
-    return tile_touch[((z >> 3) * nt + (y >> 3)) * nt + ((x4 * EPC) >> 3)] != 0;
+    return ((tbits >> ((x4 * EPC) >> 3)) & 1u) != 0;
   };
   V vzm[GR], vzp[GR], fv[GR];
   bool has[RUNS];
@@ -610,10 +614,10 @@ hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect
     constexpr int YR = XrCfg<T>::YB;
     if (convect)
       hipLaunchKernelGGL((k_xf_rhs<T, R1, R2, YR, true>), dim3(N * (N / YR)), dim3(3 * YR / 2 * P), 0, c->stream,
-                         u_in, Fg, c->ws.tile_touch, fm, dtih, (T)f_scale, tw, spec);
+                         u_in, Fg, c->ws.touch_bits, fm, dtih, (T)f_scale, tw, spec);
     else
       hipLaunchKernelGGL((k_xf_rhs<T, R1, R2, YR, false>), dim3(N * (N / YR)), dim3(3 * YR / 2 * P), 0, c->stream,
-                         u_in, Fg, c->ws.tile_touch, fm, dtih, (T)f_scale, tw, spec);
+                         u_in, Fg, c->ws.touch_bits, fm, dtih, (T)f_scale, tw, spec);
   }
   const int64_t npen = (int64_t)3 * NH * N;
   const unsigned ny = (unsigned)((npen + 256 / P - 1) / (256 / P));

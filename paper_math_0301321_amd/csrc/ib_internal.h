@@ -106,6 +106,7 @@ struct Workspace {
   int32_t *tile_nit;           // [ntiles] work items of the tile
   int32_t *tile_item0;         // [ntiles] first work item of the tile
   int32_t *tile_touch;         // [ntiles] 1 if the spread force reaches the tile (dense in Fgrid), else 0
+  uint32_t *touch_bits;        // [ceil(ntiles / 32)] the same flags, bit t & 31 of word t >> 5
   int32_t *item_tile;          // [item_cap] tile of each work item
   int32_t *chunk_item0;        // [nchunks + 1] first item of each chunk; the last entry = items
   int32_t *nitems;             // [3] work items, split tiles, touched tiles
