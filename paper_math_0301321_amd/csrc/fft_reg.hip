@@ -351,23 +351,25 @@ __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf_rhs(
       run_at(g0 + k, row, x4);
       const int c = row / YB, lr = row % YB + 1;
       const T *urow = us + (c * HR + lr) * US;
-      V r;
-      if (!CONV) r = *(const V *)(urow + x4 * EPC);
+      const V uc = *(const V *)(urow + x4 * EPC);
+      V r = uc;
       if (CONV) {
-        V uk[3], vym, vyp, uc;
+        V uk[3], vym, vyp;
 #pragma unroll
         for (int cc = 0; cc < 3; cc++) uk[cc] = *(const V *)(us + (cc * HR + lr) * US + x4 * EPC);
-#pragma unroll
-        for (int i = 0; i < EPC; i++) uc[i] = c == 0 ? uk[0][i] : (c == 1 ? uk[1][i] : uk[2][i]);
         vym = *(const V *)(urow - US + x4 * EPC);
         vyp = *(const V *)(urow + US + x4 * EPC);
         const T xl = urow[(x4 * EPC - 1) & mask], xr = urow[(x4 * EPC + EPC) & mask];
+        // backward x differences d[i] = u[i] - u[i-1]; the forward one of i is d[i+1]
+        T dm[EPC + 1];
+        dm[0] = uc[0] - xl;
+#pragma unroll
+        for (int i = 1; i < EPC; i++) dm[i] = uc[i] - uc[i - 1];
+        dm[EPC] = xr - uc[EPC - 1];
 #pragma unroll
         for (int i = 0; i < EPC; i++) {
           const T ucc = uc[i];
-          const T left = i == 0 ? xl : uc[i - 1];
-          const T right = i == EPC - 1 ? xr : uc[i + 1];
-          const T dx = uk[0][i] > T(0) ? ucc - left : right - ucc;
+          const T dx = uk[0][i] > T(0) ? dm[i] : dm[i + 1];
           const T dy = uk[1][i] > T(0) ? ucc - vym[i] : vyp[i] - ucc;
           const T dz = uk[2][i] > T(0) ? ucc - vzm[k][i] : vzp[k][i] - ucc;
           const T acc = uk[0][i] * dx + uk[1][i] * dy + uk[2][i] * dz;
