@@ -18,25 +18,40 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;    // 2048 keys per block: several blocks per CU hide the scatter's latency
 constexpr int kSortChunk = kSortThreads * kSortItems;
 
-__global__ __launch_bounds__(256) void k_keys(const double *__restrict__ X, int64_t M, double h,
-                                              int n, int log2nt, uint32_t *__restrict__ keys,
-                                              int32_t *__restrict__ vals) {
-  const int64_t q = gtid();
-  if (q >= M) return;
-  int c[3];
-  for (int d = 0; d < 3; d++) {
-    const double s = X[d * M + q] / h;
-    int64_t cd = isfinite(s) ? (int64_t)floor(s) : 0;
-    c[d] = (int)(cd & (int64_t)(n - 1));   // periodic wrap (n is a power of two)
-  }
-  keys[q] = cell_key(c[0], c[1], c[2], log2nt);
-  vals[q] = (int32_t)q;
-}
-
 // A block owns a contiguous chunk of kSortChunk keys; within it each wave owns
-// a contiguous quarter (16 rounds of 64).  Digit counts per block, layout
-// hist[digit * nblk + block].
+// a contiguous quarter (kSortItems rounds of 64).  Digit counts per block,
+// layout hist[digit * nblk + block].
 constexpr int kWaveKeys = 64 * kSortItems;
+
+// Keys of the sort blocks' markers, with the first pass's digit counts of
+// each block (the counts of the later passes depend on the order the earlier
+// passes produce).
+__global__ __launch_bounds__(256) void k_keys_hist(const double *__restrict__ X, int64_t M, double h, int n,
+                                                   int log2nt, int radix, uint32_t *__restrict__ keys,
+                                                   int32_t *__restrict__ vals, uint32_t *__restrict__ hist,
+                                                   int nblk) {
+  __shared__ uint32_t cnt[256];
+  for (int i = threadIdx.x; i < 256; i += kSortThreads) cnt[i] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+  for (int it = 0; it < kSortItems; it++) {
+    const int64_t q = base + (int64_t)it * kSortThreads + threadIdx.x;
+    if (q < M) {
+      int c[3];
+      for (int d = 0; d < 3; d++) {
+        const double s = X[d * M + q] / h;
+        int64_t cd = isfinite(s) ? (int64_t)floor(s) : 0;
+        c[d] = (int)(cd & (int64_t)(n - 1));   // periodic wrap (n is a power of two)
+      }
+      const uint32_t k = cell_key(c[0], c[1], c[2], log2nt);
+      keys[q] = k;
+      vals[q] = (int32_t)q;
+      atomicAdd(&cnt[k & (uint32_t)(radix - 1)], 1u);
+    }
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < radix; d += kSortThreads) hist[(int64_t)d * nblk + blockIdx.x] = cnt[d];
+}
 
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t M,
                                                     int shift, int radix, uint32_t *__restrict__ hist, int nblk) {
@@ -349,16 +364,16 @@ hipError_t launch_bin(ib_ctx *c, const double *X) {
   const int64_t M = c->M;
   Workspace &ws = c->ws;
   if (M > 0) {
-    const int gb = (int)((M + 255) / 256);
-    hipLaunchKernelGGL(k_keys, dim3(gb), dim3(256), 0, c->stream, X, M, c->h, c->n, c->log2nt,
-                       ws.keys[0], ws.vals[0]);
     int cur = 0;
     const int bits = c->digit_bits, R = 1 << bits;
     const int nblk = (int)((M + kSortChunk - 1) / kSortChunk);
+    hipLaunchKernelGGL(k_keys_hist, dim3(nblk), dim3(kSortThreads), 0, c->stream, X, M, c->h, c->n, c->log2nt, R,
+                       ws.keys[0], ws.vals[0], ws.hist, nblk);
     for (int pass = 0; pass < c->sort_passes; pass++) {
       const int shift = pass * bits;
-      hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, c->stream, ws.keys[cur], M,
-                         shift, R, ws.hist, nblk);
+      if (pass > 0)
+        hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, c->stream, ws.keys[cur], M,
+                           shift, R, ws.hist, nblk);
       hipLaunchKernelGGL(k_radix_scan_digit, dim3(R), dim3(kSortThreads), 0, c->stream, ws.hist, nblk,
                          ws.hist + (int64_t)R * nblk);
       hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kSortThreads), 0, c->stream, ws.keys[cur],
