@@ -90,6 +90,16 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
     const int tile = item_tile[item];
     int j0, j1;
     item_range(item, tile_start, tile_item0, item_tile, chunk, &j0, &j1);
+    {
+      // a tile that fits one round is taken whole by its first item's block:
+      // its halo is staged once rather than once per chunk it meets
+      const int ts = tile_start[tile], te = tile_start[tile + 1];
+      if (te - ts <= kInterpThreads * kInterpPer) {
+        if (item != tile_item0[tile]) continue;
+        j0 = ts;
+        j1 = te;
+      }
+    }
     const int x0 = 8 * (tile & tmask) - 1, y0 = 8 * ((tile >> log2nt) & tmask) - 1, z0 = 8 * (tile >> (2 * log2nt)) - 1;
     // every load below is issued unconditionally (indices clamped), so that
     // the waits for them are exact
