@@ -59,4 +59,16 @@ __device__ __forceinline__ int xcd_block(int b, int nblk) {
   return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// Block index remapped so that each XCD runs groups of R consecutive logical
+// blocks, the groups dealt to the XCDs in turn: neighbouring blocks share an
+// L2 while every XCD still sees every part of the index range.  Blocks past
+// the last whole round of 8 R keep their index.  A bijection of [0, nblk).
+template <int R>
+__device__ __forceinline__ int xcd_runs(int b, int nblk) {
+  const int full = nblk / (8 * R) * (8 * R);
+  if (b >= full) return b;
+  const int x = b & 7, j = b >> 3;
+  return (j / R) * (8 * R) + x * R + (j % R);
+}
+
 }  // namespace ib

@@ -203,7 +203,7 @@ __device__ __forceinline__ void add_drive(const Material &m, const int32_t *__re
 __global__ __launch_bounds__(256) void k_force(Material m, const double *__restrict__ X,
                                                const int32_t *__restrict__ slot, const double *__restrict__ dir,
                                                int64_t D, double amp, double *__restrict__ F) {
-  const int64_t q = gtid();
+  const int64_t q = (int64_t)xcd_runs<16>(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;   // lattice neighbours on one L2
   const int64_t M = m.M;
   if (q >= M) return;
   const V3 xq = ld3(X, M, q);
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void k_force_rec(Material m, const double *__r
                                                    const int32_t *__restrict__ slot, const double *__restrict__ dir,
                                                    int64_t D, double amp, const int32_t *__restrict__ inv, double h,
                                                    int n, int log2nt, double *__restrict__ F, Rec<T> *__restrict__ recs) {
-  const int64_t q = gtid();
+  const int64_t q = (int64_t)xcd_runs<16>(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;   // lattice neighbours on one L2
   const int64_t M = m.M;
   if (q >= M) return;
   const V3 xq = ld3(X, M, q);
