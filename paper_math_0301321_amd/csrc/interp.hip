@@ -86,7 +86,8 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
   const int mask = n - 1, tmask = (1 << log2nt) - 1;
   const int64_t G = (int64_t)n * n * n;
   constexpr int kPer = (kHalo3 + kInterpThreads - 1) / kInterpThreads;
-  for (int item = blockIdx.x; item < W; item += gridDim.x) {
+  // blocks in runs of 16 per XCD: neighbouring items (tiles) share halo rows in its L2
+  for (int item = xcd_runs<16>(blockIdx.x, gridDim.x); item < W; item += gridDim.x) {
     const int tile = item_tile[item];
     int j0, j1;
     item_range(item, tile_start, tile_item0, item_tile, chunk, &j0, &j1);

@@ -317,7 +317,8 @@ __global__ __launch_bounds__(256) void k_spread_gather(const int32_t *__restrict
   const int y0 = py <= 1 ? py : py + 2, y1 = py <= 1 ? py + 2 : 10;
   const bool hx1 = px <= 1 || px == 7, hy1 = py <= 1 || py == 7;
   T *Vw = Vs[w];
-  for (int li = blockIdx.x * 4 + w; li < ntouch; li += gridDim.x * 4) {
+  // blocks in runs of 16 per XCD: neighbouring tiles read neighbouring parts of the same halos
+  for (int li = xcd_runs<16>(blockIdx.x, gridDim.x) * 4 + w; li < ntouch; li += gridDim.x * 4) {
     const int tile = touch_list[li];
     const int T1 = tile & tmask, T2 = (tile >> log2nt) & tmask, T3 = tile >> (2 * log2nt);
     int nb_base = -1;                     // first halo value of neighbour `lane`, -1 without markers
