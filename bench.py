@@ -40,7 +40,7 @@ SINGLE_KERNEL = {"force": "k_force_rec", "spread": "k_spread", "split": "k_split
 
 def worklist_sizes(wl, ncu=256):
     """Sizes of the spreading work list for the markers at X0: 8^3-cell tiles, the sorted
-    markers cut into chunks of max(256, ceil(M / (6 ncu))) markers (one per spreading wave),
+    markers cut into chunks of max(256, ceil(M / (8 ncu))) markers (one per spreading wave),
     an item per (tile, chunk) part.  Returns items, tiles with markers, tiles the spread
     force reaches, the tiles cut into several items with their items, and the markers of
     lattices with stretch or bend moduli."""
@@ -52,7 +52,7 @@ def worklist_sizes(wl, ncu=256):
     K = np.bincount(tile, minlength=nt ** 3)
     te = np.cumsum(K)
     ts = te - K
-    chunk = max(256, -(-wl.M // (6 * ncu)))
+    chunk = max(256, -(-wl.M // (8 * ncu)))
     nit = np.where(K > 0, (te - 1) // chunk - ts // chunk + 1, 0)
     items = int(nit.sum())
     split_items = int(nit[nit > 1].sum())

@@ -255,3 +255,20 @@ def test_adjoint_rejects_convect(ibm):
         ctx.adjoint_step(X, u, 0.0, torch.zeros_like(X), ctx.new_grid(),
                          torch.zeros(wl.M, dtype=torch.float64, device="cuda"))
     assert ei.value.code == ibm.IB_ENOTSUP
+
+
+def test_mixed_velocity_error_after_100_steps(ibm, oracle_mod):
+    """The stated per-field bound: 100 steps of the plain IB step (advection on) on the
+    64^3 replica of the 256^3 workload (same 1.5M-marker layout); the mixed step's velocity
+    and marker displacement within 1e-5 of the FP64 oracle, the FP64 step within 1e-9."""
+    wl = W.config3(64)
+    n = 100
+    announce("100-step error", wl.N, wl.M)
+    Xo, uo = oracle_mod.run(wl, n)
+    errs = {}
+    for prec, tol in (("fp64", 1e-9), ("fp32", 1e-5)):
+        Xg, ug = _run_gpu(ibm, wl, prec, n)
+        eX, eu = rel_max(Xg - wl.X0, Xo - wl.X0), rel_max(ug, uo)
+        errs[prec] = (eu, eX)
+        print(f"[gpu-case] 100 steps {prec}: rel u {eu:.3e}, rel dX {eX:.3e}", flush=True)
+        assert eu <= tol and eX <= tol, (prec, eu, eX)
