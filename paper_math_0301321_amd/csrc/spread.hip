@@ -243,19 +243,29 @@ __global__ __launch_bounds__(256) void k_split_reduce(const int32_t *__restrict_
     const int tile = split_list[si];
     const int nit = tile_nit[tile];
     V *p0 = (V *)(partials + (int64_t)tile_item0[tile] * kPartStride);
-    for (int e = threadIdx.x; e < kNV; e += 256) {
-      V acc = p0[e];
-      int j = 1;
-      for (; j + 4 <= nit; j += 4) {
-        V x[4];
+    // every vector of this thread at once (kNV / 256 of them), four items ahead
+    constexpr int NE = kNV / 256;
+    static_assert(NE * 256 == kNV, "whole vectors per thread");
+    V acc[NE];
 #pragma unroll
-        for (int u = 0; u < 4; u++) x[u] = p0[(int64_t)(j + u) * kNV + e];
+    for (int q = 0; q < NE; q++) acc[q] = p0[threadIdx.x + 256 * q];
+    int j = 1;
+    for (; j + 4 <= nit; j += 4) {
+      V x[4][NE];
 #pragma unroll
-        for (int u = 0; u < 4; u++) acc += x[u];
-      }
-      for (; j < nit; j++) acc += p0[(int64_t)j * kNV + e];
-      p0[e] = acc;
+      for (int u = 0; u < 4; u++)
+#pragma unroll
+        for (int q = 0; q < NE; q++) x[u][q] = p0[(int64_t)(j + u) * kNV + threadIdx.x + 256 * q];
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+#pragma unroll
+        for (int q = 0; q < NE; q++) acc[q] += x[u][q];
     }
+    for (; j < nit; j++)
+#pragma unroll
+      for (int q = 0; q < NE; q++) acc[q] += p0[(int64_t)j * kNV + threadIdx.x + 256 * q];
+#pragma unroll
+    for (int q = 0; q < NE; q++) p0[threadIdx.x + 256 * q] = acc[q];
   }
 }
 
