@@ -156,6 +156,15 @@ def advect(N, L, u):
     return A
 
 
+def advect_adjoint(N, L, u, r):
+    """(dA/du)^T r for the upwind advection A of `advect`, linearised at u with
+    every branch frozen (the transpose the adjoint step needs when convect = 1)."""
+    u, r = _f64(u), _f64(r)
+    out = np.zeros_like(u)
+    lib().ibo_advect_adjoint(C.c_int(N), C.c_double(L), _ptr(u), _ptr(r), _ptr(out))
+    return out
+
+
 def fft3(x, sign=-1):
     """Complex 3-D DFT of an (N, N, N) array (no normalisation)."""
     x = np.asarray(x)
@@ -203,16 +212,21 @@ def run(wl, n_steps, X=None, u=None, N=None, k=None, convect=None, t0_step=0, ca
     return X, u
 
 
-def adjoint_step(model: Model, wl, X_n, u_np1, t, Xbar, ubar, kbar, N=None):
-    """Adjoint of one convect=0 step: returns (Xbar_n, ubar_n, kbar + contribution)."""
+def adjoint_step(model: Model, wl, X_n, u_np1, t, Xbar, ubar, kbar, N=None, convect=0, u_n=None):
+    """Adjoint of one step: returns (Xbar_n, ubar_n, kbar + contribution).  With
+    convect = 1 the step's starting velocity u_n is required (the upwind branches
+    are frozen at its signs)."""
     N = wl.N if N is None else N
     X_n, u_np1 = _f64(X_n), _f64(u_np1)
     Xb = _f64(Xbar).copy()
     ub = _f64(ubar).copy()
     kb = _f64(kbar).copy()
-    lib().ibo_adjoint_step(model.ref(), C.c_int(N), C.c_double(wl.L), C.c_double(wl.rho),
-                           C.c_double(wl.mu), C.c_double(wl.dt), C.c_double(t), _ptr(X_n), _ptr(u_np1),
-                           _ptr(Xb), _ptr(ub), _ptr(kb))
+    if convect and u_n is None:
+        raise ValueError("adjoint_step: convect = 1 needs u_n")
+    un = _f64(u_n) if convect else None
+    lib().ibo_adjoint_step_u(model.ref(), C.c_int(N), C.c_double(wl.L), C.c_double(wl.rho),
+                             C.c_double(wl.mu), C.c_double(wl.dt), C.c_double(t), C.c_int(1 if convect else 0),
+                             _ptr(X_n), _ptr(un) if convect else None, _ptr(u_np1), _ptr(Xb), _ptr(ub), _ptr(kb))
     return Xb, ub, kb
 
 

@@ -298,6 +298,51 @@ void ibo_advect(int N, double L, const double *u, double *A) {
       }
 }
 
+/* Transpose of the upwind advection linearised at u with each branch frozen
+ * (the side taken by u_k(x) > 0, u_k(x) < 0 or neither is kept; R8):
+ * the advection of ibo_advect is A_c(x) = sum_k u_k(x) D_k u_c(x), D_k the
+ * backward difference where u_k(x) > 0 and the forward one where u_k(x) < 0,
+ * so for a perturbation d,
+ *   dA_c(x) = sum_k [ d_k(x) D_k u_c(x) + u_k(x) D_k d_c(x) ].
+ * Written out for a cotangent r, out = (dA/du)^T r is, at each point y,
+ *   out_k(y) = sum_c r_c(y) D_k u_c(y)                      (first term)
+ *   out_c(y) += sum_k [ b_k(y) - b_k(y + e_k) - f_k(y) + f_k(y - e_k) ]
+ * with b_k(x) = u_k(x) r_c(x) / h where u_k(x) > 0 (else 0) and
+ * f_k(x) = u_k(x) r_c(x) / h where u_k(x) < 0 (else 0)    (second term). */
+void ibo_advect_adjoint(int N, double L, const double *u, const double *r, double *out) {
+  int64_t G = (int64_t)N * N * N;
+  double h = L / N;
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < N; k++)
+    for (int64_t j = 0; j < N; j++)
+      for (int64_t i = 0; i < N; i++) {
+        int64_t p = gidx(N, i, j, k);
+        int64_t pm[3] = {gidx(N, i - 1, j, k), gidx(N, i, j - 1, k), gidx(N, i, j, k - 1)};
+        int64_t pp[3] = {gidx(N, i + 1, j, k), gidx(N, i, j + 1, k), gidx(N, i, j, k + 1)};
+        for (int c = 0; c < 3; c++) {
+          const double *rc = r + c * G;
+          double acc = 0.0;
+          /* first term: component c receives sum_c' r_c'(y) D_c u_c'(y) */
+          double uk = u[c * G + p];
+          for (int cp = 0; cp < 3; cp++) {
+            const double *ucp = u + cp * G;
+            if (uk > 0.0) acc += r[cp * G + p] * ((ucp[p] - ucp[pm[c]]) / h);
+            else if (uk < 0.0) acc += r[cp * G + p] * ((ucp[pp[c]] - ucp[p]) / h);
+          }
+          /* second term: the difference stencils of every direction k, transposed */
+          for (int kk = 0; kk < 3; kk++) {
+            const double *uk_ = u + kk * G;
+            double at = uk_[p], up = uk_[pp[kk]], dn = uk_[pm[kk]];
+            if (at > 0.0) acc += at * rc[p] / h;          /* b_k(y)        */
+            if (up > 0.0) acc -= up * rc[pp[kk]] / h;     /* - b_k(y + e_k) */
+            if (at < 0.0) acc -= at * rc[p] / h;          /* - f_k(y)      */
+            if (dn < 0.0) acc += dn * rc[pm[kk]] / h;     /* f_k(y - e_k)  */
+          }
+          out[c * G + p] = acc;
+        }
+      }
+}
+
 /* ------------------------------------------------------------------------
  * FFT (named, not specified, in Sec. 3.2): an iterative radix-2
  * decimation-in-time transform of length n applied along each axis.
@@ -576,6 +621,12 @@ static void elastic_hvp_and_kbar(const ibo_model *m, const double *X, const doub
 void ibo_adjoint_step(const ibo_model *m, int N, double L, double rho, double mu, double dt,
                       double t, const double *X_n, const double *u_np1,
                       double *Xbar, double *ubar, double *kbar) {
+  ibo_adjoint_step_u(m, N, L, rho, mu, dt, t, 0, X_n, NULL, u_np1, Xbar, ubar, kbar);
+}
+
+void ibo_adjoint_step_u(const ibo_model *m, int N, double L, double rho, double mu, double dt,
+                        double t, int convect, const double *X_n, const double *u_n, const double *u_np1,
+                        double *Xbar, double *ubar, double *kbar) {
   int64_t M = m->M, G = (int64_t)N * N * N;
   double h = L / N, inv_h3 = 1.0 / (h * h * h);
   size_t mb = sizeof(double) * 3 * (size_t)(M > 0 ? M : 1);
@@ -642,6 +693,13 @@ void ibo_adjoint_step(const ibo_model *m, int N, double L, double rho, double mu
   /* force: Xbar += (df/dX)^T fbar = -H fbar ; kbar += (df/dk)^T fbar */
   elastic_hvp_and_kbar(m, X_n, fb, Hv, kbar);
   for (int64_t p = 0; p < 3 * M; p++) Xbar[p] -= Hv[p];
+
+  /* ubar is the cotangent of r = u - dt A(u) + (dt / rho) F; with advection
+   * the velocity's own adjoint loses dt (dA/du)^T rbar */
+  if (convect) {
+    ibo_advect_adjoint(N, L, u_n, ubar, utot);
+    for (int64_t p = 0; p < 3 * G; p++) ubar[p] -= dt * utot[p];
+  }
 
   free(f); free(Ub); free(fb); free(Hv); free(utot);
 }

@@ -68,6 +68,9 @@ void ibo_spread(int N, double L, int64_t M, const double *X, const double *Fq, d
 void ibo_interp(int N, double L, int64_t M, const double *X, const double *u, double *U);
 /* Upwind advection sum_k u_k D_k^{+-} u (eq. discreteNS1), [3][N^3] -> [3][N^3]. */
 void ibo_advect(int N, double L, const double *u, double *A);
+/* out = (dA/du)^T r: the transpose of ibo_advect linearised at u, each
+ * upwind branch frozen at the sign u_k(x) takes. */
+void ibo_advect_adjoint(int N, double L, const double *u, const double *r, double *out);
 /* In-place complex 3-D DFT of an N^3 array (x fastest): sign -1 forward,
  * +1 inverse; no normalisation. */
 void ibo_fft3(int N, double *re, double *im, int sign);
@@ -84,6 +87,11 @@ void ibo_step(const ibo_model *m, int N, double L, double rho, double mu, double
 void ibo_adjoint_step(const ibo_model *m, int N, double L, double rho, double mu, double dt,
                       double t, const double *X_n, const double *u_np1,
                       double *Xbar, double *ubar, double *kbar);
+/* The same for either convect setting; u_n (the step's starting velocity,
+ * where the upwind branches are frozen) is read when convect = 1. */
+void ibo_adjoint_step_u(const ibo_model *m, int N, double L, double rho, double mu, double dt,
+                        double t, int convect, const double *X_n, const double *u_n, const double *u_np1,
+                        double *Xbar, double *ubar, double *kbar);
 
 int ibo_num_threads(void);
 

@@ -1,13 +1,14 @@
 """Pins of the oracle's adjoint step against the (pinned) forward step, on the CPU.
 
-The adjoint of one Stokes step (convect = 0) must be the transpose of its
-linearisation: for any tangent (dX, du, dk) and cotangent (Xbar', ubar'),
+The adjoint of one step (Stokes, or with the upwind advection linearised with
+its branches frozen) must be the transpose of its linearisation: for any tangent (dX, du, dk) and cotangent (Xbar', ubar'),
 <J (dX, du, dk), (Xbar', ubar')> = <(dX, du, dk), J^T (Xbar', ubar')>.
 J is taken by central differences of the forward oracle.  A multi-step
 gradient of a membrane-displacement loss is checked against finite
 differences of the same loss.
 """
 import numpy as np
+import pytest
 
 from paper_math_0301321_amd import workloads as W
 
@@ -21,8 +22,34 @@ def _setup(N=16):
     return wl, X, u, rng
 
 
-def test_adjoint_step_is_transpose_of_linearised_step(oracle_mod):
+def test_advect_adjoint_is_transpose_of_linearised_advection(oracle_mod):
+    """The upwind advection is quadratic in u on each frozen branch, so its central
+    difference is exact up to rounding: <A'(u) d, r> = <d, A'(u)^T r>, for a field
+    with both signs of every component and no zeros (no branch changes within eps)."""
+    N, L = 8, 1.0
+    rng = np.random.default_rng(40)
+    u = rng.standard_normal((3, N, N, N))
+    u += np.sign(u) * 0.05                                    # keep |u_k| away from 0
+    d = rng.standard_normal(u.shape)
+    r = rng.standard_normal(u.shape)
+    eps = 1e-6
+    Jd = (oracle_mod.advect(N, L, u + eps * d) - oracle_mod.advect(N, L, u - eps * d)) / (2 * eps)
+    lhs = (Jd * r).sum()
+    rhs = (d * oracle_mod.advect_adjoint(N, L, u, r)).sum()
+    assert abs(lhs - rhs) <= 1e-9 * abs(rhs), (lhs, rhs)
+    # each component of the perturbation separately, so no error can cancel
+    for c in range(3):
+        dc = np.zeros_like(d)
+        dc[c] = d[c]
+        Jc = (oracle_mod.advect(N, L, u + eps * dc) - oracle_mod.advect(N, L, u - eps * dc)) / (2 * eps)
+        l2, r2 = (Jc * r).sum(), (dc * oracle_mod.advect_adjoint(N, L, u, r)).sum()
+        assert abs(l2 - r2) <= 1e-9 * max(abs(r2), 1.0), (c, l2, r2)
+
+
+@pytest.mark.parametrize("convect", [0, 1])
+def test_adjoint_step_is_transpose_of_linearised_step(oracle_mod, convect):
     wl, X, u, rng = _setup()
+    wl.convect = convect
     t = 3e-4
     dX = rng.standard_normal(X.shape)
     du = rng.standard_normal(u.shape)
@@ -32,7 +59,7 @@ def test_adjoint_step_is_transpose_of_linearised_step(oracle_mod):
 
     def fwd(e):
         m = oracle_mod.Model(wl, wl.k + e * dk)
-        return oracle_mod.step(m, wl, X + e * dX, u + e * du, t, convect=0)
+        return oracle_mod.step(m, wl, X + e * dX, u + e * du, t, convect=convect)
 
     eps = 1e-6
     Xp, up = fwd(eps)
@@ -41,8 +68,8 @@ def test_adjoint_step_is_transpose_of_linearised_step(oracle_mod):
     lhs = (jX * Xb1).sum() + (ju * ub1).sum()
 
     m = oracle_mod.Model(wl)
-    _, u1 = oracle_mod.step(m, wl, X, u, t, convect=0)
-    Xb, ub, kb = oracle_mod.adjoint_step(m, wl, X, u1, t, Xb1, ub1, np.zeros(wl.M))
+    _, u1 = oracle_mod.step(m, wl, X, u, t, convect=convect)
+    Xb, ub, kb = oracle_mod.adjoint_step(m, wl, X, u1, t, Xb1, ub1, np.zeros(wl.M), convect=convect, u_n=u)
     rhs = (dX * Xb).sum() + (du * ub).sum() + (dk * kb).sum()
     assert abs(lhs - rhs) <= 1e-6 * abs(rhs), (lhs, rhs)
 
@@ -54,7 +81,7 @@ def test_adjoint_step_is_transpose_of_linearised_step(oracle_mod):
 
         def f2(e):
             mm = oracle_mod.Model(wl, wl.k + e * sk)
-            return oracle_mod.step(mm, wl, X + e * sX, u + e * su, t, convect=0)
+            return oracle_mod.step(mm, wl, X + e * sX, u + e * su, t, convect=convect)
 
         a, b = f2(eps), f2(-eps)
         l2 = (((a[0] - b[0]) * Xb1).sum() + ((a[1] - b[1]) * ub1).sum()) / (2 * eps)
