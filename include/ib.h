@@ -149,6 +149,14 @@ int ib_bin(ib_ctx *c, const double *X, uint32_t *keys_sorted, int32_t *perm);
  * kbar [M] double has (df/dk)^T fbar added to it. */
 int ib_adjoint_step(ib_ctx *c, const double *X_n, const void *u_np1, double t,
                     double *Xbar, void *ubar, double *kbar);
+/* The same for either convect setting.  With convect = 1 the upwind advection
+ * of eq. discreteNS1 is differentiated with each branch frozen at the side
+ * u^n selects (the derivative away from u_k = 0; no term where u_k = 0), so
+ * u_n [3][n^3] (fluid precision, the velocity the step started from) is
+ * required; with convect = 0 it is not read and may be NULL.  IB_EINVAL when
+ * it is missing for convect = 1. */
+int ib_adjoint_step_u(ib_ctx *c, const double *X_n, const void *u_n, const void *u_np1, double t,
+                      double *Xbar, void *ubar, double *kbar);
 
 /* Text of the last error on this context ("" if none); c may be NULL for the
  * last ib_create failure. */

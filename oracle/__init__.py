@@ -230,18 +230,18 @@ def adjoint_step(model: Model, wl, X_n, u_np1, t, Xbar, ubar, kbar, N=None, conv
     return Xb, ub, kb
 
 
-def gradient_k(wl, n_steps, loss_idx, N=None, k=None, X0=None):
-    """Loss L = (1/|W|) sum_{q in W} |X_q^T - X_q^0|^2 after n_steps Stokes steps
-    (convect = 0) from (X0, u = 0), and its gradient with respect to the
-    per-marker stiffness k, by the adjoint step run backwards over stored states.
-    Returns (L, kbar, Xbar0, ubar0)."""
+def gradient_k(wl, n_steps, loss_idx, N=None, k=None, X0=None, convect=0):
+    """Loss L = (1/|W|) sum_{q in W} |X_q^T - X_q^0|^2 after n_steps steps (Stokes,
+    or with the upwind advection when convect = 1) from (X0, u = 0), and its
+    gradient with respect to the per-marker stiffness k, by the adjoint step run
+    backwards over stored states.  Returns (L, kbar, Xbar0, ubar0)."""
     N = wl.N if N is None else N
     model = Model(wl, k)
     X0 = _f64(wl.X0 if X0 is None else X0)
     idx = np.asarray(loss_idx, dtype=np.int64)
     Xs, us = [X0.copy()], [np.zeros((3, N, N, N))]
     for n in range(n_steps):
-        Xn, un = step(model, wl, Xs[-1], us[-1], n * wl.dt, N=N, convect=0)
+        Xn, un = step(model, wl, Xs[-1], us[-1], n * wl.dt, N=N, convect=convect)
         Xs.append(Xn)
         us.append(un)
     d = Xs[-1][:, idx] - X0[:, idx]
@@ -251,5 +251,6 @@ def gradient_k(wl, n_steps, loss_idx, N=None, k=None, X0=None):
     ub = np.zeros_like(us[0])
     kb = np.zeros(wl.M)
     for n in reversed(range(n_steps)):
-        Xb, ub, kb = adjoint_step(model, wl, Xs[n], us[n + 1], n * wl.dt, Xb, ub, kb, N=N)
+        Xb, ub, kb = adjoint_step(model, wl, Xs[n], us[n + 1], n * wl.dt, Xb, ub, kb, N=N, convect=convect,
+                                  u_n=us[n])
     return L, kb, Xb, ub

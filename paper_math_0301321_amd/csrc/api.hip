@@ -387,7 +387,7 @@ extern "C" void ib_destroy(ib_ctx *c) {
 // ------------------------------------------------------ instrumentation ----
 static const char *kPhaseNames[PH_COUNT] = {"bin", "force", "prep", "spread", "split", "gather", "rhs", "fft_x", "fft_y",
                                             "fft_z_solve", "fft_y_inv", "fft_x_inv", "interp", "adj_interp",
-                                            "adj_spread", "hessvec", "rhs_fft_x"};
+                                            "adj_spread", "hessvec", "rhs_fft_x", "adj_advect"};
 
 static void timers_fold(ib_ctx *c) {
   if (c->tused == 0) return;
@@ -563,8 +563,8 @@ extern "C" int ib_bin(ib_ctx *c, const double *X, uint32_t *keys_sorted, int32_t
 }
 
 template <typename T>
-static int adjoint_impl(ib_ctx *c, const double *X_n, const T *u_np1, double t, double *Xbar, T *ubar,
-                        double *kbar) {
+static int adjoint_impl(ib_ctx *c, const double *X_n, const T *u_n, const T *u_np1, double t, double *Xbar,
+                        T *ubar, double *kbar) {
   // forward quantities at X^n: binning, weights, force f^n
   IB_TRY(launch_bin(c, X_n));
   IB_TRY(launch_force_rec<T>(c, X_n, drive_amp(c, t), c->ws.Flag));
@@ -577,16 +577,27 @@ static int adjoint_impl(ib_ctx *c, const double *X_n, const T *u_np1, double t, 
   // transpose of spreading (fbar) and its phi' term, then the force Jacobian
   IB_TRY(launch_adj_spread<T>(c, ubar, c->ws.Flag, Xbar, c->ws.fb));
   IB_TRY(launch_hessvec(c, X_n, c->ws.fb, Xbar, kbar));
+  // with advection, r = u - dt A(u) + ...: ubar^n = rbar - dt (dA/du)^T rbar at u^n
+  if (c->p.convect) IB_TRY(launch_adv_adjoint<T>(c, u_n, ubar, (T *)c->ws.Fgrid));
   return checked(c, ubar, c->fp32, Xbar);
+}
+
+extern "C" int ib_adjoint_step_u(ib_ctx *c, const double *X_n, const void *u_n, const void *u_np1, double t,
+                                 double *Xbar, void *ubar, double *kbar) {
+  if (!c) return IB_EINVAL;
+  if (!u_np1 || !ubar || (c->M > 0 && (!X_n || !Xbar || !kbar)))
+    return fail(c, IB_EINVAL, "ib_adjoint_step: X_n, u_np1, Xbar, ubar, kbar required");
+  if (c->p.convect && !u_n) return fail(c, IB_EINVAL, "ib_adjoint_step_u: convect = 1 needs u_n");
+  c->err.clear();
+  return c->fp32 ? adjoint_impl<float>(c, X_n, (const float *)u_n, (const float *)u_np1, t, Xbar, (float *)ubar, kbar)
+                 : adjoint_impl<double>(c, X_n, (const double *)u_n, (const double *)u_np1, t, Xbar, (double *)ubar,
+                                        kbar);
 }
 
 extern "C" int ib_adjoint_step(ib_ctx *c, const double *X_n, const void *u_np1, double t, double *Xbar,
                                void *ubar, double *kbar) {
   if (!c) return IB_EINVAL;
-  if (c->p.convect != 0) return fail(c, IB_ENOTSUP, "ib_adjoint_step: only convect = 0 is differentiated");
-  if (!u_np1 || !ubar || (c->M > 0 && (!X_n || !Xbar || !kbar)))
-    return fail(c, IB_EINVAL, "ib_adjoint_step: X_n, u_np1, Xbar, ubar, kbar required");
-  c->err.clear();
-  return c->fp32 ? adjoint_impl<float>(c, X_n, (const float *)u_np1, t, Xbar, (float *)ubar, kbar)
-                 : adjoint_impl<double>(c, X_n, (const double *)u_np1, t, Xbar, (double *)ubar, kbar);
+  if (c->p.convect != 0)
+    return fail(c, IB_ENOTSUP, "ib_adjoint_step: convect = 1 needs u^n: use ib_adjoint_step_u");
+  return ib_adjoint_step_u(c, X_n, nullptr, u_np1, t, Xbar, ubar, kbar);
 }

@@ -296,4 +296,68 @@ template hipError_t launch_rhs<double>(ib_ctx *, const double *, const double *,
 template hipError_t launch_fluid_solve<float>(ib_ctx *, const float *, float *);
 template hipError_t launch_fluid_solve<double>(ib_ctx *, const double *, double *);
 
+// Adjoint of the upwind advection for the time step's adjoint (convect = 1),
+// linearised at u^n with every branch frozen at the side u_k(x) selects (no
+// term where u_k(x) = 0).  With the advection A_c(x) = sum_k u_k(x) D_k u_c(x),
+// a perturbation d changes it by sum_k [d_k D_k u_c + u_k D_k d_c]; the
+// transpose applied to a cotangent r, gathered at each point y, is
+//   out_c(y) = sum_c' r_c'(y) D_c u_c'(y)
+//            + sum_k [b_k(y) - b_k(y + e_k) - f_k(y) + f_k(y - e_k)],
+// b_k(x) = u_k(x) r_c(x) / h where u_k(x) > 0, f_k(x) the same where
+// u_k(x) < 0.  One thread per grid point; the result, times dt, goes to tmp.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adv_adjoint(const T *__restrict__ u, const T *__restrict__ r, int n,
+                                                     int log2n, T inv_h, T dt, T *__restrict__ tmp) {
+  const int64_t G = (int64_t)n << (2 * log2n);
+  const int64_t p = gtid();
+  if (p >= G) return;
+  const int mask = n - 1;
+  const int x = (int)(p & mask), y = (int)((p >> log2n) & mask), z = (int)(p >> (2 * log2n));
+  const int64_t zo = (int64_t)z << (2 * log2n), yo = (int64_t)y << log2n;
+  const int64_t pm[3] = {zo + yo + ((x - 1) & mask), zo + ((int64_t)((y - 1) & mask) << log2n) + x,
+                         ((int64_t)((z - 1) & mask) << (2 * log2n)) + yo + x};
+  const int64_t pp[3] = {zo + yo + ((x + 1) & mask), zo + ((int64_t)((y + 1) & mask) << log2n) + x,
+                         ((int64_t)((z + 1) & mask) << (2 * log2n)) + yo + x};
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    T acc = T(0);
+    const T uc = u[c * G + p];
+#pragma unroll
+    for (int cp = 0; cp < 3; cp++) {
+      const T *v = u + cp * G;
+      const T D = uc > T(0) ? (v[p] - v[pm[c]]) * inv_h : (uc < T(0) ? (v[pp[c]] - v[p]) * inv_h : T(0));
+      acc += r[cp * G + p] * D;
+    }
+    const T *rc = r + c * G;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      const T at = u[k * G + p], up = u[k * G + pp[k]], dn = u[k * G + pm[k]];
+      if (at > T(0)) acc += at * rc[p] * inv_h;
+      if (up > T(0)) acc -= up * rc[pp[k]] * inv_h;
+      if (at < T(0)) acc -= at * rc[p] * inv_h;
+      if (dn < T(0)) acc += dn * rc[pm[k]] * inv_h;
+    }
+    tmp[c * G + p] = dt * acc;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sub_inplace(T *__restrict__ a, const T *__restrict__ b, int64_t count) {
+  const int64_t i = gtid();
+  if (i < count) a[i] -= b[i];
+}
+
+template <typename T>
+hipError_t launch_adv_adjoint(ib_ctx *c, const T *u_n, T *ubar, T *tmp) {
+  PhaseScope ps(c, PH_ADJ_ADVECT);
+  const unsigned g1 = (unsigned)((c->G + 255) / 256), g3 = (unsigned)((3 * c->G + 255) / 256);
+  hipLaunchKernelGGL(k_adv_adjoint<T>, dim3(g1), dim3(256), 0, c->stream, u_n, (const T *)ubar, c->n, c->log2n,
+                     (T)(1.0 / c->h), (T)c->p.dt, tmp);
+  hipLaunchKernelGGL(k_sub_inplace<T>, dim3(g3), dim3(256), 0, c->stream, ubar, (const T *)tmp, 3 * c->G);
+  return hipGetLastError();
+}
+
+template hipError_t launch_adv_adjoint<float>(ib_ctx *, const float *, float *, float *);
+template hipError_t launch_adv_adjoint<double>(ib_ctx *, const double *, double *, double *);
+
 }  // namespace ib

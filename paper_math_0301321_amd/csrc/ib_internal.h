@@ -134,7 +134,7 @@ struct Workspace {
 // Phases timed by the optional HIP-event instrumentation.
 enum Phase {
   PH_BIN = 0, PH_FORCE, PH_PREP, PH_SPREAD, PH_SPLIT, PH_GATHER, PH_RHS, PH_FFT_X, PH_FFT_Y, PH_FFT_Z_SOLVE,
-  PH_FFT_Y_INV, PH_FFT_X_INV, PH_INTERP, PH_ADJ_INTERP, PH_ADJ_SPREAD, PH_HESSVEC, PH_RHS_FFT_X, PH_COUNT
+  PH_FFT_Y_INV, PH_FFT_X_INV, PH_INTERP, PH_ADJ_INTERP, PH_ADJ_SPREAD, PH_HESSVEC, PH_RHS_FFT_X, PH_ADJ_ADVECT, PH_COUNT
 };
 
 struct TimerRec {
@@ -213,6 +213,9 @@ hipError_t launch_adj_spread(ib_ctx *c, const T *ubar_n, const double *F, double
 hipError_t launch_hessvec(ib_ctx *c, const double *X, const double *v, double *Xbar, double *kbar);
 // reference-shape constants of the lattices from X_ref and w (at creation and when they are set)
 hipError_t launch_lattice_pre(ib_ctx *c);
+// adjoint step with advection: ubar -= dt (dA/du)^T ubar at u^n (tmp: [3][G] scratch)
+template <typename T>
+hipError_t launch_adv_adjoint(ib_ctx *c, const T *u_n, T *ubar, T *tmp);
 
 // instrumentation: event pair around a phase when timing is on
 void timer_begin(ib_ctx *c, int phase);

@@ -53,7 +53,7 @@ class ib_elastic(C.Structure):
 
 
 EXPORTS = ["ib_create", "ib_destroy", "ib_set_material", "ib_set_stream", "ib_step", "ib_force",
-           "ib_spread", "ib_interp", "ib_fluid", "ib_bin", "ib_adjoint_step", "ib_last_error",
+           "ib_spread", "ib_interp", "ib_fluid", "ib_bin", "ib_adjoint_step", "ib_adjoint_step_u", "ib_last_error",
            "ib_workspace_bytes", "ib_timers_enable", "ib_timers_select", "ib_timers_read", "ib_timer_name"]
 IB_N_TIMERS = 32
 
@@ -82,6 +82,7 @@ def load_library():
     lib.ib_fluid.argtypes = [vp, vp, vp]
     lib.ib_bin.argtypes = [vp, vp, vp, vp]
     lib.ib_adjoint_step.argtypes = [vp, vp, vp, dp, vp, vp, vp]
+    lib.ib_adjoint_step_u.argtypes = [vp, vp, vp, vp, dp, vp, vp, vp]
     lib.ib_last_error.argtypes = [vp]
     lib.ib_last_error.restype = C.c_char_p
     lib.ib_workspace_bytes.argtypes = [vp]
@@ -264,10 +265,12 @@ class Context:
         self._check(self.lib.ib_bin(self._h, self._markers(X, "X"), _ptr(keys), _ptr(perm)))
         return keys, perm
 
-    def adjoint_step(self, X_n, u_np1, t: float, Xbar, ubar, kbar):
-        """Adjoint of one convect=0 step: Xbar, ubar (n+1 -> n) in place, kbar accumulated."""
+    def adjoint_step(self, X_n, u_np1, t: float, Xbar, ubar, kbar, u_n=None):
+        """Adjoint of one step: Xbar, ubar (n+1 -> n) in place, kbar accumulated.  With
+        convect = 1, u_n (the velocity the step started from) is required."""
         if kbar.device.type != "cuda" or kbar.dtype != torch.float64 or kbar.numel() != self.M:
             raise ValueError("kbar must be a cuda float64 tensor with M entries")
-        self._check(self.lib.ib_adjoint_step(self._h, self._markers(X_n, "X_n"), self._grid(u_np1, "u_np1"),
-                                             float(t), self._markers(Xbar, "Xbar"), self._grid(ubar, "ubar"),
-                                             _ptr(kbar)))
+        un = None if u_n is None else self._grid(u_n, "u_n")
+        self._check(self.lib.ib_adjoint_step_u(self._h, self._markers(X_n, "X_n"), un,
+                                               self._grid(u_np1, "u_np1"), float(t), self._markers(Xbar, "Xbar"),
+                                               self._grid(ubar, "ubar"), _ptr(kbar)))

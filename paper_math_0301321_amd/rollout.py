@@ -9,8 +9,9 @@ checkpoint, keeping that segment's states, and then walks the segment
 backwards.  Gradients flow to ``k`` (the stiffness multipliers of the
 material force), ``X0`` and ``u0``.
 
-The adjoint differentiates the Stokes step (``convect = 0``); the context must
-be created with ``convect=0``.
+With ``convect = 1`` the upwind advection is differentiated with each branch
+frozen at the side the step's starting velocity selects; the segment replay
+keeps that velocity for the adjoint.
 """
 from __future__ import annotations
 
@@ -20,8 +21,6 @@ import torch
 class IBRollout(torch.autograd.Function):
     @staticmethod
     def forward(fctx, k, X0, u0, ibctx, n_steps: int, ckpt_every: int, t0: float = 0.0):
-        if ibctx.convect != 0:
-            raise ValueError("IBRollout differentiates the Stokes step: create the context with convect=0")
         if n_steps < 0 or ckpt_every < 1:
             raise ValueError("need n_steps >= 0 and ckpt_every >= 1")
         dt = float(ibctx.wl.dt)
@@ -54,13 +53,15 @@ class IBRollout(torch.autograd.Function):
             end = min(start + fctx.ckpt_every, fctx.n_steps)
             X, u = Xc.clone(), uc.clone()
             seg = []
+            conv = ibctx.convect != 0
             for n in range(start, end):
                 Xn = X.clone()
+                un = u.clone() if conv else None
                 ibctx.step(X, u, t0 + n * dt)
-                seg.append((Xn, u.clone()))          # X^n and u^{n+1}
+                seg.append((Xn, un, u.clone()))      # X^n, u^n (with advection), u^{n+1}
             for n in reversed(range(start, end)):
-                Xn, unp1 = seg[n - start]
-                ibctx.adjoint_step(Xn, unp1, t0 + n * dt, Xbar, ubar, kbar)
+                Xn, un, unp1 = seg[n - start]
+                ibctx.adjoint_step(Xn, unp1, t0 + n * dt, Xbar, ubar, kbar, u_n=un)
         return kbar, Xbar, ubar, None, None, None, None
 
 

@@ -217,10 +217,11 @@ def test_full_size_one_step(ibm, oracle_mod):
 # --------------------------------------------------------------------------
 # adjoint step
 # --------------------------------------------------------------------------
+@pytest.mark.parametrize("convect", [0, 1])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-4)])
-def test_adjoint_step_parity(ibm, oracle_mod, prec, tol):
+def test_adjoint_step_parity(ibm, oracle_mod, prec, tol, convect):
     wl = W.tiny_helix(N=16)
-    wl.convect = 0
+    wl.convect = convect
     rng = np.random.default_rng(50)
     X = wl.X0 + 2e-3 * rng.standard_normal(wl.X0.shape)
     u = 0.05 * W.random_field(16, seed=51)
@@ -228,33 +229,40 @@ def test_adjoint_step_parity(ibm, oracle_mod, prec, tol):
         u = u.astype(np.float32).astype(np.float64)
     t = 3e-4
     m = oracle_mod.Model(wl)
-    _, u1 = oracle_mod.step(m, wl, X, u, t, convect=0)
+    _, u1 = oracle_mod.step(m, wl, X, u, t, convect=convect)
     Xb1 = rng.standard_normal(X.shape)
     ub1 = rng.standard_normal(u.shape)
     if prec == "fp32":
         u1 = u1.astype(np.float32).astype(np.float64)
         ub1 = ub1.astype(np.float32).astype(np.float64)
-    Xbo, ubo, kbo = oracle_mod.adjoint_step(m, wl, X, u1, t, Xb1, ub1, np.zeros(wl.M))
-    announce("adjoint", prec)
-    ctx = ibm.Context(wl, prec, convect=0)
+    Xbo, ubo, kbo = oracle_mod.adjoint_step(m, wl, X, u1, t, Xb1, ub1, np.zeros(wl.M), convect=convect, u_n=u)
+    announce("adjoint", prec, "convect", convect)
+    ctx = ibm.Context(wl, prec, convect=convect)
     fd = _fluid_dtype(prec)
     Xb, ub, kb = dev(Xb1), dev(ub1, fd), torch.zeros(wl.M, dtype=torch.float64, device="cuda")
-    ctx.adjoint_step(dev(X), dev(u1, fd), t, Xb, ub, kb)
+    ctx.adjoint_step(dev(X), dev(u1, fd), t, Xb, ub, kb, u_n=dev(u, fd) if convect else None)
     torch.cuda.synchronize()
     assert rel_max(host(Xb) - Xb1, Xbo - Xb1) < tol
     assert rel_max(host(ub), ubo) < tol
     assert rel_max(host(kb), kbo) < tol
 
 
-def test_adjoint_rejects_convect(ibm):
+def test_adjoint_with_advection_needs_u_n(ibm):
+    """convect = 1: ib_adjoint_step_u without u^n is IB_EINVAL; the Stokes-only
+    ib_adjoint_step refuses with IB_ENOTSUP."""
     wl = W.tiny_helix(N=16)
     ctx = ibm.Context(wl, "fp64", convect=1)
     X = dev(wl.X0)
     u = ctx.new_grid()
+    kb = torch.zeros(wl.M, dtype=torch.float64, device="cuda")
     with pytest.raises(ibm.IBError) as ei:
-        ctx.adjoint_step(X, u, 0.0, torch.zeros_like(X), ctx.new_grid(),
-                         torch.zeros(wl.M, dtype=torch.float64, device="cuda"))
-    assert ei.value.code == ibm.IB_ENOTSUP
+        ctx.adjoint_step(X, u, 0.0, torch.zeros_like(X), ctx.new_grid(), kb)
+    assert ei.value.code == ibm.IB_EINVAL
+    Xb, ub = torch.zeros_like(X), ctx.new_grid()
+    rc = ctx.lib.ib_adjoint_step(ctx._h, X.data_ptr(), u.data_ptr(), 0.0, Xb.data_ptr(), ub.data_ptr(),
+                                 kb.data_ptr())
+    torch.cuda.synchronize()
+    assert rc == ibm.IB_ENOTSUP
 
 
 def test_mixed_velocity_error_after_100_steps(ibm, oracle_mod):

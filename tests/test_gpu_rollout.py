@@ -30,8 +30,8 @@ def mods():
     return ib, rollout
 
 
-def _gpu_grad(ib, rollout, wl, prec, n_steps, ckpt, idx, k=None):
-    ctx = ib.Context(wl, prec, convect=0)
+def _gpu_grad(ib, rollout, wl, prec, n_steps, ckpt, idx, k=None, convect=0):
+    ctx = ib.Context(wl, prec, convect=convect)
     kt = dev(wl.k if k is None else k).requires_grad_(True)
     X0 = dev(wl.X0)
     u0 = ctx.new_grid()
@@ -59,6 +59,22 @@ def test_rollout_gradient_matches_oracle_small(mods, oracle_mod, prec, tol):
     Lo, kbo, _, _ = oracle_mod.gradient_k(wl, 7, idx)
     L, kb = _gpu_grad(ib, rollout, wl, prec, 7, 3, idx)       # segments 3, 3, 1
     # the loss is quadratic in the displacement: twice the displacement bound
+    assert abs(L - Lo) <= (2e-5 if prec == "fp32" else 1e-12) * Lo, (L, Lo)
+    assert _rel_l2(kb, kbo) < tol, _rel_l2(kb, kbo)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_rollout_gradient_with_advection_matches_oracle(mods, oracle_mod, prec, tol):
+    """The same with the upwind advection on (branches frozen at u^n in the adjoint)."""
+    ib, rollout = mods
+    wl = W.tiny_helix(N=16)
+    wl.convect = 1
+    rng = np.random.default_rng(31)
+    wl.X0 = wl.X0 + 2e-3 * rng.standard_normal(wl.X0.shape)
+    idx = W.bm_index(wl, np.arange(30), 3)
+    announce("rollout small, advection", prec)
+    Lo, kbo, _, _ = oracle_mod.gradient_k(wl, 7, idx, convect=1)
+    L, kb = _gpu_grad(ib, rollout, wl, prec, 7, 3, idx, convect=1)
     assert abs(L - Lo) <= (2e-5 if prec == "fp32" else 1e-12) * Lo, (L, Lo)
     assert _rel_l2(kb, kbo) < tol, _rel_l2(kb, kbo)
 
@@ -151,3 +167,34 @@ def test_rollout_config4_vs_oracle_gradient(mods, oracle_mod):
         L, kb = _gpu_grad(ib, rollout, wl, prec, wl.n_steps, wl.meta["ckpt"], idx)
         assert abs(L - Lo) <= 1e-5 * Lo, (prec, L, Lo)
         assert _rel_l2(kb, kbo) < tol, (prec, _rel_l2(kb, kbo))
+
+
+def test_rollout_advection_vs_finite_differences(mods):
+    """Advection on, FP64: the adjoint gradient along a random direction of the stiffness
+    against central differences of the loss (large strains: well conditioned)."""
+    ib, rollout = mods
+    wl = W.tiny_helix(N=16)
+    wl.convect = 1
+    rng = np.random.default_rng(33)
+    wl.X0 = wl.X0 + 2e-3 * rng.standard_normal(wl.X0.shape)
+    idx = W.bm_index(wl, np.arange(30), 3)
+    n, ck = 7, 3
+    announce("rollout advection FD")
+    L, g = _gpu_grad(ib, rollout, wl, "fp64", n, ck, idx, convect=1)
+    v = rng.standard_normal(wl.M) * wl.k
+
+    def loss(k):
+        ctx = ib.Context(wl, "fp64", convect=1)
+        ctx.set_stiffness(dev(k))
+        X = dev(wl.X0)
+        u = ctx.new_grid()
+        for s in range(n):
+            ctx.step(X, u, s * wl.dt)
+        torch.cuda.synchronize()
+        d = host(X)[:, idx] - wl.X0[:, idx]
+        return (d ** 2).sum() / len(idx)
+
+    gv = g @ v
+    for eps in (1e-4, 1e-3):
+        dfd = (loss(wl.k + eps * v) - loss(wl.k - eps * v)) / (2 * eps)
+        assert abs(gv - dfd) <= 1e-4 * abs(gv), (eps, gv, dfd)
