@@ -151,6 +151,48 @@ def run_gpu(wl, precision, steps, warmup, timed_phases=(), every=1):
     return dict(ctx=ctx, X=X, u=u, wall=wall, ev_ms=ev_ms, phases=ph)
 
 
+def extras(wl, n=10):
+    """Rates beside the headline (not part of it): the adjoint step with the upwind
+    advection on the same workload (mixed precision), and the 128^3 window-model
+    workload stepping with the membrane's centre line recorded every 10th step."""
+    import torch
+    from paper_math_0301321_amd import ib, workloads as W, diagnostics as D
+    out = {}
+    ctx = ib.Context(wl, "fp32", convect=1)
+    X = torch.as_tensor(wl.X0, dtype=torch.float64, device="cuda").contiguous()
+    u = ctx.new_grid()
+    ctx.step(X, u, 0.0)
+    un = u.clone()
+    Xn = X.clone()
+    ctx.step(X, u, wl.dt)
+    Xb = torch.zeros_like(X)
+    ub = ctx.new_grid()
+    kb = torch.zeros(wl.M, dtype=torch.float64, device="cuda")
+    ctx.adjoint_step(Xn, u, wl.dt, Xb, ub, kb, u_n=un)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(n):
+        ctx.adjoint_step(Xn, u, wl.dt, Xb, ub, kb, u_n=un)
+    e1.record()
+    torch.cuda.synchronize()
+    out["adjoint_steps_per_s"] = round(n / (e0.elapsed_time(e1) / 1e3), 2)
+    del ctx, u, un, ub
+    wlw = W.window128()
+    cw = ib.Context(wlw, "fp32")
+    Xw = torch.as_tensor(wlw.X0, dtype=torch.float64, device="cuda").contiguous()
+    uw = cw.new_grid()
+    D.run_with_output(cw, wlw, Xw, uw, 10, every=10)
+    torch.cuda.synchronize()
+    e0.record()
+    D.run_with_output(cw, wlw, Xw, uw, 50, every=10, t0_step=10)
+    e1.record()
+    torch.cuda.synchronize()
+    out["window128_steps_per_s"] = round(50 / (e0.elapsed_time(e1) / 1e3), 2)
+    out["window128_markers"] = wlw.M
+    return out
+
+
 def cpu_baseline(wl, sample_steps: int):
     import numpy as np
     import oracle
@@ -177,6 +219,8 @@ def main():
                     help="oracle steps timed on the host (one step of the default workload takes ~2 s on 16 cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the adjoint-step and window-model rates reported beside the headline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB device copy (reference kernel for traffic counters)")
     args = ap.parse_args()
@@ -242,6 +286,9 @@ def main():
             dXm = mixed["X"] - torch.as_tensor(wl.X0, device="cuda")
             extra["mixed_vs_fp64_rel_dX"] = float((dXm - dX64).abs().max() / dX64.abs().max())
         print(f"[bench] fp64: {v64:.1f} steps/s", file=sys.stderr, flush=True)
+
+    if not args.no_extras:
+        extra.update(extras(wl))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -158,6 +158,17 @@ int ib_adjoint_step(ib_ctx *c, const double *X_n, const void *u_np1, double t,
 int ib_adjoint_step_u(ib_ctx *c, const double *X_n, const void *u_n, const void *u_np1, double t,
                       double *Xbar, void *ubar, double *kbar);
 
+/* Diagnostics of Sec. 5 (the membrane's displacement along its length and
+ * its envelope over time): for i < count, the displacement of marker idx[i]
+ * from X0 along the unit direction dir[:, i],
+ *   disp[i] = sum_c (X[c][idx[i]] - X0[c][idx[i]]) dir[c][i],
+ * and env[i] = max(env[i], |disp[i]|).  X, X0 [3][M] and dir [3][count]
+ * double, idx [count] int32, disp and env [count] double (either NULL): all
+ * DEVICE arrays.  An index outside [0, M) gives disp[i] = NaN and leaves
+ * env[i].  IB_EINVAL for count < 0 or a missing X, X0, idx, dir. */
+int ib_probe(ib_ctx *c, const double *X, const double *X0, const int32_t *idx, const double *dir,
+             int64_t count, double *disp, double *env);
+
 /* Text of the last error on this context ("" if none); c may be NULL for the
  * last ib_create failure. */
 const char *ib_last_error(const ib_ctx *c);

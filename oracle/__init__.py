@@ -156,6 +156,18 @@ def advect(N, L, u):
     return A
 
 
+def probe(X, X0, idx, dirs):
+    """Displacement of markers idx along unit directions dirs (Sec. 5 diagnostics):
+    d[i] = sum_c (X[c, idx[i]] - X0[c, idx[i]]) dirs[c, i], written out term by term."""
+    X, X0, dirs = _f64(X), _f64(X0), _f64(dirs)
+    idx = np.asarray(idx, dtype=np.int64)
+    d = np.zeros(len(idx))
+    for i, q in enumerate(idx):
+        for c in range(3):
+            d[i] += (X[c, q] - X0[c, q]) * dirs[c, i]
+    return d
+
+
 def advect_adjoint(N, L, u, r):
     """(dA/du)^T r for the upwind advection A of `advect`, linearised at u with
     every branch frozen (the transpose the adjoint step needs when convect = 1)."""

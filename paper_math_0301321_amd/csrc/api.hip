@@ -594,6 +594,17 @@ extern "C" int ib_adjoint_step_u(ib_ctx *c, const double *X_n, const void *u_n, 
                                         kbar);
 }
 
+extern "C" int ib_probe(ib_ctx *c, const double *X, const double *X0, const int32_t *idx, const double *dir,
+                        int64_t count, double *disp, double *env) {
+  if (!c) return IB_EINVAL;
+  if (count < 0 || (count > 0 && (!X || !X0 || !idx || !dir)))
+    return fail(c, IB_EINVAL, "ib_probe: count >= 0 and X, X0, idx, dir are required");
+  c->err.clear();
+  IB_TRY(launch_probe(c, X, X0, idx, dir, count, disp, env));
+  if (c->check) IB_TRY(hipStreamSynchronize(c->stream));
+  return IB_OK;
+}
+
 extern "C" int ib_adjoint_step(ib_ctx *c, const double *X_n, const void *u_np1, double t, double *Xbar,
                                void *ubar, double *kbar) {
   if (!c) return IB_EINVAL;

@@ -213,6 +213,8 @@ hipError_t launch_adj_spread(ib_ctx *c, const T *ubar_n, const double *F, double
 hipError_t launch_hessvec(ib_ctx *c, const double *X, const double *v, double *Xbar, double *kbar);
 // reference-shape constants of the lattices from X_ref and w (at creation and when they are set)
 hipError_t launch_lattice_pre(ib_ctx *c);
+hipError_t launch_probe(ib_ctx *c, const double *X, const double *X0, const int32_t *idx, const double *dir,
+                        int64_t count, double *disp, double *env);
 // adjoint step with advection: ubar -= dt (dA/du)^T ubar at u^n (tmp: [3][G] scratch)
 template <typename T>
 hipError_t launch_adv_adjoint(ib_ctx *c, const T *u_n, T *ubar, T *tmp);

@@ -319,4 +319,32 @@ template hipError_t launch_adj_interp<double>(ib_ctx *, const double *, double *
 template hipError_t launch_adj_spread<float>(ib_ctx *, const float *, const double *, double *, double *);
 template hipError_t launch_adj_spread<double>(ib_ctx *, const double *, const double *, double *, double *);
 
+// Diagnostics (Sec. 5): displacement of chosen markers along given unit
+// directions, disp[i] = (X[idx[i]] - X0[idx[i]]) . dir[i], and its running
+// maximum magnitude env[i].  Indices outside [0, M) give NaN and leave env.
+__global__ __launch_bounds__(256) void k_probe(const double *__restrict__ X, const double *__restrict__ X0,
+                                               int64_t M, const int32_t *__restrict__ idx,
+                                               const double *__restrict__ dir, int64_t count,
+                                               double *__restrict__ disp, double *__restrict__ env) {
+  const int64_t i = gtid();
+  if (i >= count) return;
+  const int64_t q = idx[i];
+  if (q < 0 || q >= M) {
+    if (disp) disp[i] = __builtin_nan("");
+    return;
+  }
+  double d = 0.0;
+  for (int c = 0; c < 3; c++) d += (X[c * M + q] - X0[c * M + q]) * dir[c * count + i];
+  if (disp) disp[i] = d;
+  if (env) env[i] = fmax(env[i], fabs(d));
+}
+
+hipError_t launch_probe(ib_ctx *c, const double *X, const double *X0, const int32_t *idx, const double *dir,
+                        int64_t count, double *disp, double *env) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_probe, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, c->stream, X, X0, c->M, idx, dir,
+                     count, disp, env);
+  return hipGetLastError();
+}
+
 }  // namespace ib

@@ -53,7 +53,7 @@ class ib_elastic(C.Structure):
 
 
 EXPORTS = ["ib_create", "ib_destroy", "ib_set_material", "ib_set_stream", "ib_step", "ib_force",
-           "ib_spread", "ib_interp", "ib_fluid", "ib_bin", "ib_adjoint_step", "ib_adjoint_step_u", "ib_last_error",
+           "ib_spread", "ib_interp", "ib_fluid", "ib_bin", "ib_adjoint_step", "ib_adjoint_step_u", "ib_probe", "ib_last_error",
            "ib_workspace_bytes", "ib_timers_enable", "ib_timers_select", "ib_timers_read", "ib_timer_name"]
 IB_N_TIMERS = 32
 
@@ -83,6 +83,7 @@ def load_library():
     lib.ib_bin.argtypes = [vp, vp, vp, vp]
     lib.ib_adjoint_step.argtypes = [vp, vp, vp, dp, vp, vp, vp]
     lib.ib_adjoint_step_u.argtypes = [vp, vp, vp, vp, dp, vp, vp, vp]
+    lib.ib_probe.argtypes = [vp, vp, vp, vp, vp, C.c_int64, vp, vp]
     lib.ib_last_error.argtypes = [vp]
     lib.ib_last_error.restype = C.c_char_p
     lib.ib_workspace_bytes.argtypes = [vp]
@@ -264,6 +265,24 @@ class Context:
         perm = torch.empty(self.M, dtype=torch.int32, device=X.device)
         self._check(self.lib.ib_bin(self._h, self._markers(X, "X"), _ptr(keys), _ptr(perm)))
         return keys, perm
+
+    def probe(self, X, X0, idx, dirs, disp=None, env=None):
+        """disp[i] = (X[:, idx[i]] - X0[:, idx[i]]) . dirs[:, i] (returned; written into
+        `disp` when given) and env[i] = max(env[i], |disp[i]|) when `env` is given."""
+        n = int(idx.numel())
+        if idx.device.type != "cuda" or idx.dtype != torch.int32 or not idx.is_contiguous():
+            raise ValueError("idx must be a contiguous cuda int32 tensor")
+        if (dirs.device.type != "cuda" or dirs.dtype != torch.float64 or not dirs.is_contiguous()
+                or tuple(dirs.shape) != (3, n)):
+            raise ValueError(f"dirs must be a contiguous cuda float64 tensor of shape (3, {n})")
+        d = torch.empty(n, dtype=torch.float64, device=idx.device) if disp is None else disp
+        for t_, nm in ((d, "disp"), (env, "env")):
+            if t_ is not None and (t_.device.type != "cuda" or t_.dtype != torch.float64
+                                   or not t_.is_contiguous() or t_.numel() != n):
+                raise ValueError(f"{nm} must be a contiguous cuda float64 tensor with {n} entries")
+        self._check(self.lib.ib_probe(self._h, self._markers(X, "X"), self._markers(X0, "X0"), _ptr(idx),
+                                      _ptr(dirs), n, _ptr(d), None if env is None else _ptr(env)))
+        return d
 
     def adjoint_step(self, X_n, u_np1, t: float, Xbar, ubar, kbar, u_n=None):
         """Adjoint of one step: Xbar, ubar (n+1 -> n) in place, kbar accumulated.  With

@@ -171,7 +171,7 @@ def _centre(s):
 
 def helicoid_in_tube(nb1, nb2, nw1, nw2, win1, win2, *, N, dt, n_steps, freq,
                      Ks=50.0, Kb=3e-4, kappa=1e5, drive_A=1e2, jitter_seed=None,
-                     convect=1, name="helix") -> Workload:
+                     convect=1, name="helix", window=None) -> Workload:
     """Tapered helicoidal strip ('BM', nb1 x nb2) inside a coiled tube wall (nw1 x nw2).
 
     BM centre line C(s) = (1/2 + R cos th, 1/2 + R sin th, 0.2 + 0.6 s), th = 5 pi s
@@ -181,6 +181,13 @@ def helicoid_in_tube(nb1, nb2, nw1, nw2, win1, win2, *, N, dt, n_steps, freq,
     long edges are tethered.  The wall is a tube of radius a = 0.10 - 0.04 s
     around C(s), every marker tethered to its initial position.  The window
     patch (wall i1 < win1, i2 < win2) is driven along the outward normal.
+
+    ``window = nw`` replaces the driven wall patch by the window model of
+    Sec. 4: a flat square lattice of nw x nw markers (spacing h/2) in the
+    plane tangent to the wall at s = 0.03, whose markers outside the inscribed
+    circle are held by tethers and whose markers inside move freely, with
+    stretch and bend moduli Ks, Kb, under the sinusoidal force along the
+    outward normal.
     """
     # ---- basilar membrane lattice, fibre by fibre (the membrane's fibres run
     # across its width): index = i1 * nb2 + i2 for station i1 < nb1 along the
@@ -225,13 +232,39 @@ def helicoid_in_tube(nb1, nb2, nw1, nw2, win1, win2, *, N, dt, n_steps, freq,
     k = np.concatenate([k_bm.reshape(-1), np.ones(M_w)])
     kap = np.concatenate([kap_bm.reshape(-1), np.full(M_w, kappa)])
 
-    i2w, i1w = np.meshgrid(np.arange(win2), np.arange(win1), indexing="ij")
-    didx = (M_bm + i2w * nw1 + i1w).reshape(-1).astype(np.int32)
-    ddir = nrm[i2w.reshape(-1), i1w.reshape(-1), :].T.copy()
-
     lattices = [Lattice(0, nb2, nb1, False, Ks, Kb), Lattice(M_bm, nw1, nw2, True, 0.0, 0.0)]
     meta = {"bm_first": 0, "bm_along": nb1, "bm_across": nb2, "wall_first": M_bm,
             "wall_n1": nw1, "wall_n2": nw2, "s_bm": s_bm.reshape(-1).copy()}
+    if window is None:
+        i2w, i1w = np.meshgrid(np.arange(win2), np.arange(win1), indexing="ij")
+        didx = (M_bm + i2w * nw1 + i1w).reshape(-1).astype(np.int32)
+        ddir = nrm[i2w.reshape(-1), i1w.reshape(-1), :].T.copy()
+    else:
+        # window lattice: index = M_bm + M_w + j * nw + i, i along the tube, j around it
+        nwin = int(window)
+        s0 = np.array([0.03])
+        C0, dC0, er0 = _centre(s0)
+        t0 = (dC0 / np.linalg.norm(dC0, axis=0))[:, 0]
+        m1 = er0[:, 0] - (er0[:, 0] @ t0) * t0
+        m1 /= np.linalg.norm(m1)                      # outward normal of the wall at phase 0
+        m2 = np.cross(t0, m1)
+        centre = C0[:, 0] + (0.10 - 0.04 * s0[0]) * m1
+        d = 0.5 / N                                   # spacing h/2
+        off = (np.arange(nwin) - 0.5 * (nwin - 1)) * d
+        oj, oi = np.meshgrid(off, off, indexing="ij")
+        WIN = centre[:, None, None] + oi[None] * t0[:, None, None] + oj[None] * m2[:, None, None]
+        inside = (oi ** 2 + oj ** 2 <= (0.5 * (nwin - 1) * d) ** 2).reshape(-1)
+        M_win = nwin * nwin
+        X0 = np.ascontiguousarray(np.concatenate([X0, WIN.reshape(3, M_win)], axis=1))
+        w = np.concatenate([w, np.full(M_win, d * d)])
+        k = np.concatenate([k, np.ones(M_win)])
+        kap = np.concatenate([kap, np.where(inside, 0.0, kappa)])
+        first = M_bm + M_w
+        lattices.append(Lattice(first, nwin, nwin, False, Ks, Kb))
+        didx = (first + np.flatnonzero(inside)).astype(np.int32)
+        ddir = np.ascontiguousarray(np.repeat(m1[:, None], len(didx), axis=1))
+        meta.update({"window_first": first, "window_n": nwin, "window_inside": np.flatnonzero(inside),
+                     "window_normal": m1.copy()})
     return Workload(
         name=name, N=N, L=1.0, rho=1.0, mu=0.01, dt=dt, n_steps=n_steps, convect=convect,
         X0=X0, w=np.ascontiguousarray(w), k=np.ascontiguousarray(k), X_ref=X0.copy(),
@@ -294,10 +327,17 @@ def config5(N: int = 256) -> Workload:
     return wl
 
 
-def tiny_helix(N: int = 32, nb=(60, 12), nw=(80, 24), dt=2e-4, n_steps=10) -> Workload:
+def tiny_helix(N: int = 32, nb=(60, 12), nw=(80, 24), dt=2e-4, n_steps=10, window=None) -> Workload:
     """A scaled-down helix for fast parity tests (same structure, few markers)."""
     return helicoid_in_tube(nb[0], nb[1], nw[0], nw[1], 4, 6, N=N, dt=dt, n_steps=n_steps,
-                            freq=1000.0, jitter_seed=0, name=f"helix_tiny{N}")
+                            freq=1000.0, jitter_seed=0, name=f"helix_tiny{N}", window=window)
+
+
+def window128(N: int = 128) -> Workload:
+    """The 128^3 helix with the window model of Sec. 4 (a 48 x 48 lattice, free
+    inside its inscribed circle, fixed outside) in place of the driven wall patch."""
+    return helicoid_in_tube(800, 250, 1000, 300, 20, 100, N=N, dt=5e-5, n_steps=200,
+                            freq=1000.0, name="window128", window=48)
 
 
 def random_markers(M: int, seed: int = 2, lo: float = 0.0, hi: float = 1.0):

@@ -1,0 +1,116 @@
+"""The window model of Sec. 4 and the membrane diagnostics of Sec. 5.
+
+CPU: the generated window (free and driven inside its inscribed circle, held
+by tethers outside), the oracle's probe against displacements built along
+known directions, and the centre line's normals.  GPU: a few steps of a
+helix with the window model against the oracle, the probe kernel against the
+oracle's probe (with its envelope and an out-of-range index), and the
+every-tenth-step output driver.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_math_0301321_amd import workloads as W
+from paper_math_0301321_amd import diagnostics as D
+from tests.gpu_util import announce, dev, host, rel_max
+
+
+def test_window_model_structure():
+    wl = W.tiny_helix(window=12)
+    first, nw = wl.meta["window_first"], wl.meta["window_n"]
+    ins = wl.meta["window_inside"]
+    assert wl.M == first + nw * nw
+    assert np.array_equal(np.sort(wl.drive_idx - first), ins)          # exactly the inside markers are driven
+    assert np.all(wl.kappa[first + ins] == 0.0)
+    out = np.setdiff1d(np.arange(nw * nw), ins)
+    assert np.all(wl.kappa[first + out] > 0.0)
+    # the inside markers form the inscribed disc of the square lattice
+    i, j = ins % nw, ins // nw
+    r = np.hypot(i - 0.5 * (nw - 1), j - 0.5 * (nw - 1))
+    assert r.max() <= 0.5 * (nw - 1) + 1e-12
+    # flat, spacing h/2, drive along the lattice's normal
+    Y = wl.X0[:, first:]
+    n = wl.meta["window_normal"]
+    assert np.ptp(n @ Y) < 1e-12
+    assert abs(np.linalg.norm(Y[:, 1] - Y[:, 0]) - 0.5 * wl.h) < 1e-12
+    assert np.allclose(wl.drive_dir, n[:, None])
+
+
+def test_oracle_probe_and_centre_line(oracle_mod):
+    rng = np.random.default_rng(7)
+    M, n = 500, 40
+    X0 = rng.standard_normal((3, M))
+    idx = rng.choice(M, n, replace=False)
+    dirs = rng.standard_normal((3, n))
+    dirs /= np.linalg.norm(dirs, axis=0)
+    a = rng.standard_normal(n)
+    X = X0.copy()
+    X[:, idx] += a * dirs                                               # displacement a along dirs
+    perp = np.cross(dirs.T, rng.standard_normal((n, 3))).T               # plus one orthogonal to it
+    X[:, idx] += perp
+    assert np.allclose(oracle_mod.probe(X, X0, idx, dirs), a, atol=1e-12)
+    wl = W.tiny_helix()
+    cidx, nrm = D.bm_centre_line(wl)
+    assert len(cidx) == wl.meta["bm_along"]
+    assert np.allclose(np.linalg.norm(nrm, axis=0), 1.0)
+    along = np.gradient(wl.X_ref[:, cidx], axis=1)
+    assert np.abs((along * nrm).sum(0)).max() < 1e-9 * np.abs(along).max() + 1e-15
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_window_steps_match_oracle(oracle_mod, prec, tol):
+    from paper_math_0301321_amd import ib
+    ib.load_library()
+    wl = W.tiny_helix(window=12, n_steps=6)
+    announce("window steps", prec)
+    Xo, uo = oracle_mod.run(wl, wl.n_steps)
+    ctx = ib.Context(wl, prec)
+    X = dev(wl.X0)
+    u = ctx.new_grid()
+    for s in range(wl.n_steps):
+        ctx.step(X, u, s * wl.dt)
+    torch.cuda.synchronize()
+    Xg, ug = host(X), host(u)
+    assert rel_max(Xg - wl.X0, Xo - wl.X0) < tol and rel_max(ug, uo) < tol
+    first, ins = wl.meta["window_first"], wl.meta["window_inside"]
+    out = np.setdiff1d(np.arange(wl.meta["window_n"] ** 2), ins)
+    dmove = np.abs(Xg - wl.X0)
+    assert dmove[:, first + ins].max() > 2 * dmove[:, first + out].max()    # the free disc moves more than the held rim
+
+
+@pytest.mark.gpu
+def test_probe_kernel_and_output_driver(oracle_mod, tmp_path):
+    from paper_math_0301321_amd import ib
+    ib.load_library()
+    wl = W.tiny_helix(window=12)
+    ctx = ib.Context(wl, "fp64")
+    rng = np.random.default_rng(8)
+    X0 = dev(wl.X0)
+    idx_h = rng.choice(wl.M, 64, replace=False).astype(np.int32)
+    dirs_h = rng.standard_normal((3, 64))
+    dirs_h /= np.linalg.norm(dirs_h, axis=0)
+    env = torch.zeros(64, dtype=torch.float64, device="cuda")
+    want_env = np.zeros(64)
+    announce("probe")
+    for r in range(3):
+        Xh = wl.X0 + 1e-3 * rng.standard_normal(wl.X0.shape)
+        d = host(ctx.probe(dev(Xh), X0, dev(idx_h, torch.int32), dev(dirs_h), env=env))
+        want = oracle_mod.probe(Xh, wl.X0, idx_h, dirs_h)
+        want_env = np.maximum(want_env, np.abs(want))
+        assert np.abs(d - want).max() <= 1e-15 * np.abs(want).max() + 1e-18
+    assert np.abs(host(env) - want_env).max() <= 1e-15 * want_env.max()   # running max of the same values
+    bad = dev(np.array([0, wl.M, -1], dtype=np.int32), torch.int32)
+    d = host(ctx.probe(X0, X0, bad, dev(np.ones((3, 3)) / np.sqrt(3.0))))
+    assert d[0] == 0.0 and np.isnan(d[1]) and np.isnan(d[2])
+    # every tenth step of 30: three records, the envelope bounds every record
+    X = dev(wl.X0)
+    u = ctx.new_grid()
+    out = D.run_with_output(ctx, wl, X, u, 30, every=10, path=tmp_path / "bm.npz")
+    assert list(out["step"]) == [10, 20, 30]
+    assert out["disp"].shape == (3, wl.meta["bm_along"])
+    assert np.all(out["envelope"] >= np.abs(out["disp"]).max(axis=0) - 1e-18)
+    assert np.all(np.isfinite(out["disp"])) and out["envelope"].max() > 0.0
+    saved = np.load(tmp_path / "bm.npz")
+    assert np.array_equal(saved["envelope"], out["envelope"])
