@@ -38,8 +38,9 @@ static inline int64_t wrap(int64_t i, int64_t n) {
   return r < 0 ? r + n : r;
 }
 
-static inline int64_t gidx(int64_t N, int64_t i, int64_t j, int64_t k) {
-  return (wrap(k, N) * N + wrap(j, N)) * N + wrap(i, N);
+/* node (i, j, k) of the N x N x Nz grid, wrapped periodically */
+static inline int64_t gidx(int64_t N, int64_t Nz, int64_t i, int64_t j, int64_t k) {
+  return (wrap(k, Nz) * N + wrap(j, N)) * N + wrap(i, N);
 }
 
 /* ------------------------------------------------------------------------
@@ -68,12 +69,12 @@ static int kv_cmp(const void *a, const void *b) {
   return (x->id > y->id) - (x->id < y->id);
 }
 
-void ibo_bin(int N, double L, int64_t M, const double *X, uint32_t *keys_sorted, int32_t *perm) {
+void ibo_bin(int N, int Nz, double L, int64_t M, const double *X, uint32_t *keys_sorted, int32_t *perm) {
   double h = L / N;
   kv_t *kv = (kv_t *)malloc(sizeof(kv_t) * (size_t)(M > 0 ? M : 1));
   for (int64_t q = 0; q < M; q++) {
     int64_t c[3];
-    for (int d = 0; d < 3; d++) c[d] = wrap((int64_t)floor(X[d * M + q] / h), N);
+    for (int d = 0; d < 3; d++) c[d] = wrap((int64_t)floor(X[d * M + q] / h), d == 2 ? Nz : N);
     int64_t nb = N / 8;
     int64_t blk = ((c[2] / 8) * nb + c[1] / 8) * nb + c[0] / 8;
     kv[q].key = (uint32_t)(((blk * 8 + c[2] % 8) * 8 + c[1] % 8) * 8 + c[0] % 8);
@@ -229,8 +230,8 @@ double ibo_energy(const ibo_model *m, const double *X) {
  * nodes floor(X/h)-1 .. floor(X/h)+2 are visited; node indices wrap
  * periodically.  Plain scatter in marker order.
  * ---------------------------------------------------------------------- */
-void ibo_spread(int N, double L, int64_t M, const double *X, const double *Fq, double *Fg) {
-  int64_t G = (int64_t)N * N * N;
+void ibo_spread(int N, int Nz, double L, int64_t M, const double *X, const double *Fq, double *Fg) {
+  int64_t G = (int64_t)N * N * Nz;
   double h = L / N, inv_h3 = 1.0 / (h * h * h);
   memset(Fg, 0, sizeof(double) * 3 * (size_t)G);
   for (int64_t q = 0; q < M; q++) {
@@ -241,7 +242,7 @@ void ibo_spread(int N, double L, int64_t M, const double *X, const double *Fq, d
       for (int64_t j = c[1] - 1; j <= c[1] + 2; j++)
         for (int64_t i = c[0] - 1; i <= c[0] + 2; i++) {
           double dlt = ibo_phi(s[0] - (double)i) * ibo_phi(s[1] - (double)j) * ibo_phi(s[2] - (double)k) * inv_h3;
-          int64_t p = gidx(N, i, j, k);
+          int64_t p = gidx(N, Nz, i, j, k);
           for (int cc = 0; cc < 3; cc++) Fg[cc * G + p] += Fq[cc * M + q] * dlt;
         }
   }
@@ -251,8 +252,8 @@ void ibo_spread(int N, double L, int64_t M, const double *X, const double *Fq, d
  * Interpolation, eq. discreteX (sub-step 4): U_q = sum_x u(x) delta_h(x - X_q) h^3
  * = sum over the same 4^3 nodes of u(x) phi phi phi.
  * ---------------------------------------------------------------------- */
-void ibo_interp(int N, double L, int64_t M, const double *X, const double *u, double *U) {
-  int64_t G = (int64_t)N * N * N;
+void ibo_interp(int N, int Nz, double L, int64_t M, const double *X, const double *u, double *U) {
+  int64_t G = (int64_t)N * N * Nz;
   double h = L / N;
 #pragma omp parallel for schedule(static)
   for (int64_t q = 0; q < M; q++) {
@@ -263,7 +264,7 @@ void ibo_interp(int N, double L, int64_t M, const double *X, const double *u, do
       for (int64_t j = c[1] - 1; j <= c[1] + 2; j++)
         for (int64_t i = c[0] - 1; i <= c[0] + 2; i++) {
           double wgt = ibo_phi(s[0] - (double)i) * ibo_phi(s[1] - (double)j) * ibo_phi(s[2] - (double)k);
-          int64_t p = gidx(N, i, j, k);
+          int64_t p = gidx(N, Nz, i, j, k);
           for (int cc = 0; cc < 3; cc++) acc[cc] += u[cc * G + p] * wgt;
         }
     for (int cc = 0; cc < 3; cc++) U[cc * M + q] = acc[cc];
@@ -275,16 +276,16 @@ void ibo_interp(int N, double L, int64_t M, const double *X, const double *u, do
  *   A_c = sum_k u_k D_k^- u_c  (u_k > 0),  u_k D_k^+ u_c  (u_k < 0),  0 (u_k = 0),
  * with D^+ / D^- the one-sided differences of eqs. differenceOpsFirst-Last.
  * ---------------------------------------------------------------------- */
-void ibo_advect(int N, double L, const double *u, double *A) {
-  int64_t G = (int64_t)N * N * N;
+void ibo_advect(int N, int Nz, double L, const double *u, double *A) {
+  int64_t G = (int64_t)N * N * Nz;
   double h = L / N;
 #pragma omp parallel for schedule(static)
-  for (int64_t k = 0; k < N; k++)
+  for (int64_t k = 0; k < Nz; k++)
     for (int64_t j = 0; j < N; j++)
       for (int64_t i = 0; i < N; i++) {
-        int64_t p = gidx(N, i, j, k);
-        int64_t pm[3] = {gidx(N, i - 1, j, k), gidx(N, i, j - 1, k), gidx(N, i, j, k - 1)};
-        int64_t pp[3] = {gidx(N, i + 1, j, k), gidx(N, i, j + 1, k), gidx(N, i, j, k + 1)};
+        int64_t p = gidx(N, Nz, i, j, k);
+        int64_t pm[3] = {gidx(N, Nz, i - 1, j, k), gidx(N, Nz, i, j - 1, k), gidx(N, Nz, i, j, k - 1)};
+        int64_t pp[3] = {gidx(N, Nz, i + 1, j, k), gidx(N, Nz, i, j + 1, k), gidx(N, Nz, i, j, k + 1)};
         for (int c = 0; c < 3; c++) {
           const double *uc = u + c * G;
           double acc = 0.0;
@@ -309,16 +310,16 @@ void ibo_advect(int N, double L, const double *u, double *A) {
  *   out_c(y) += sum_k [ b_k(y) - b_k(y + e_k) - f_k(y) + f_k(y - e_k) ]
  * with b_k(x) = u_k(x) r_c(x) / h where u_k(x) > 0 (else 0) and
  * f_k(x) = u_k(x) r_c(x) / h where u_k(x) < 0 (else 0)    (second term). */
-void ibo_advect_adjoint(int N, double L, const double *u, const double *r, double *out) {
-  int64_t G = (int64_t)N * N * N;
+void ibo_advect_adjoint(int N, int Nz, double L, const double *u, const double *r, double *out) {
+  int64_t G = (int64_t)N * N * Nz;
   double h = L / N;
 #pragma omp parallel for schedule(static)
-  for (int64_t k = 0; k < N; k++)
+  for (int64_t k = 0; k < Nz; k++)
     for (int64_t j = 0; j < N; j++)
       for (int64_t i = 0; i < N; i++) {
-        int64_t p = gidx(N, i, j, k);
-        int64_t pm[3] = {gidx(N, i - 1, j, k), gidx(N, i, j - 1, k), gidx(N, i, j, k - 1)};
-        int64_t pp[3] = {gidx(N, i + 1, j, k), gidx(N, i, j + 1, k), gidx(N, i, j, k + 1)};
+        int64_t p = gidx(N, Nz, i, j, k);
+        int64_t pm[3] = {gidx(N, Nz, i - 1, j, k), gidx(N, Nz, i, j - 1, k), gidx(N, Nz, i, j, k - 1)};
+        int64_t pp[3] = {gidx(N, Nz, i + 1, j, k), gidx(N, Nz, i, j + 1, k), gidx(N, Nz, i, j, k + 1)};
         for (int c = 0; c < 3; c++) {
           const double *rc = r + c * G;
           double acc = 0.0;
@@ -372,30 +373,32 @@ static void fft1(int n, double *re, double *im, const double *cs, const double *
   }
 }
 
-void ibo_fft3(int N, double *re, double *im, int sign) {
-  double *cs = (double *)malloc(sizeof(double) * N), *sn = (double *)malloc(sizeof(double) * N);
-  for (int j = 0; j < N; j++) { cs[j] = cos(2.0 * PI * j / N); sn[j] = sin(2.0 * PI * j / N); }
-  int64_t NN = (int64_t)N * N;
+void ibo_fft3(int N, int Nz, double *re, double *im, int sign) {
+  int64_t NN = (int64_t)N * N, G = NN * Nz;
   for (int axis = 0; axis < 3; axis++) {
+    int n = axis == 2 ? Nz : N;                    /* transform length along this axis */
     int64_t stride = axis == 0 ? 1 : (axis == 1 ? N : NN);
+    int64_t npen = G / n;
+    double *cs = (double *)malloc(sizeof(double) * n), *sn = (double *)malloc(sizeof(double) * n);
+    for (int j = 0; j < n; j++) { cs[j] = cos(2.0 * PI * j / n); sn[j] = sin(2.0 * PI * j / n); }
 #pragma omp parallel
     {
-      double *br = (double *)malloc(sizeof(double) * N), *bi = (double *)malloc(sizeof(double) * N);
+      double *br = (double *)malloc(sizeof(double) * n), *bi = (double *)malloc(sizeof(double) * n);
 #pragma omp for schedule(static)
-      for (int64_t pencil = 0; pencil < NN; pencil++) {
+      for (int64_t pencil = 0; pencil < npen; pencil++) {
         /* pencil enumerates the two other axes */
         int64_t a = pencil % N, b = pencil / N, base;
         if (axis == 0) base = b * NN + a * N;          /* (j=a, k=b) */
         else if (axis == 1) base = b * NN + a;         /* (i=a, k=b) */
         else base = b * N + a;                         /* (i=a, j=b) */
-        for (int t = 0; t < N; t++) { br[t] = re[base + t * stride]; bi[t] = im[base + t * stride]; }
-        fft1(N, br, bi, cs, sn, sign);
-        for (int t = 0; t < N; t++) { re[base + t * stride] = br[t]; im[base + t * stride] = bi[t]; }
+        for (int t = 0; t < n; t++) { br[t] = re[base + t * stride]; bi[t] = im[base + t * stride]; }
+        fft1(n, br, bi, cs, sn, sign);
+        for (int t = 0; t < n; t++) { re[base + t * stride] = br[t]; im[base + t * stride] = bi[t]; }
       }
       free(br); free(bi);
     }
+    free(cs); free(sn);
   }
-  free(cs); free(sn);
 }
 
 /* ------------------------------------------------------------------------
@@ -403,10 +406,11 @@ void ibo_fft3(int N, double *re, double *im, int sign) {
  *   r = u^n - dt sum_k u_k D_k^{+-} u^n + (dt/rho) F^n,
  * the system reads (I - (mu dt/rho) sum_k D+_k D-_k) u' + (dt/rho) D0 p = r,
  * D0 . u' = 0.  In Fourier mode m the symbols are
- *   sum_k D+_k D-_k -> -lambda,  lambda = sum_d (4/h^2) sin^2(pi m_d / N),
- *   D0_d            -> i s_d,    s_d    = sin(2 pi m_d / N) / h,
- * so w = r^/(1 + (mu dt/rho) lambda) and u'^ = w - s (s.w)/|s|^2, or u'^ = w
- * when s = 0 (every m_d in {0, N/2}: D0 annihilates the mode, no pressure).
+ *   sum_k D+_k D-_k -> -lambda,  lambda = sum_d (4/h^2) sin^2(pi m_d / N_d),
+ *   D0_d            -> i s_d,    s_d    = sin(2 pi m_d / N_d) / h,
+ * (N_d the nodes along axis d: N, N, Nz), so w = r^/(1 + (mu dt/rho) lambda)
+ * and u'^ = w - s (s.w)/|s|^2, or u'^ = w when s = 0 (every m_d in
+ * {0, N_d/2}: D0 annihilates the mode, no pressure).
  * ---------------------------------------------------------------------- */
 static double sin_mode(int m, int N) {
   /* sin(2 pi m / N), exactly 0 at m = 0 and m = N/2 where the true value is 0 */
@@ -414,16 +418,16 @@ static double sin_mode(int m, int N) {
   return sin(2.0 * PI * (double)m / (double)N);
 }
 
-double ibo_fluid(int N, double L, double rho, double mu, double dt, int convect,
+double ibo_fluid(int N, int Nz, double L, double rho, double mu, double dt, int convect,
                  const double *u, const double *Fg, double *u_new) {
-  int64_t G = (int64_t)N * N * N;
+  int64_t G = (int64_t)N * N * Nz;
   double h = L / N;
   double *re = (double *)malloc(sizeof(double) * 3 * (size_t)G);
   double *im = (double *)calloc(3 * (size_t)G, sizeof(double));
   double *A = NULL;
   if (convect) {
     A = (double *)malloc(sizeof(double) * 3 * (size_t)G);
-    ibo_advect(N, L, u, A);
+    ibo_advect(N, Nz, L, u, A);
   }
   for (int64_t p = 0; p < 3 * G; p++) {
     double r = u[p];
@@ -432,20 +436,21 @@ double ibo_fluid(int N, double L, double rho, double mu, double dt, int convect,
     re[p] = r;
   }
   free(A);
-  for (int c = 0; c < 3; c++) ibo_fft3(N, re + c * G, im + c * G, -1);
+  for (int c = 0; c < 3; c++) ibo_fft3(N, Nz, re + c * G, im + c * G, -1);
 
   double nu_dt = mu * dt / rho;
 #pragma omp parallel for schedule(static)
-  for (int64_t m3 = 0; m3 < N; m3++)
+  for (int64_t m3 = 0; m3 < Nz; m3++)
     for (int64_t m2 = 0; m2 < N; m2++)
       for (int64_t m1 = 0; m1 < N; m1++) {
         int64_t p = (m3 * N + m2) * N + m1;
         int64_t mm[3] = {m1, m2, m3};
         double lam = 0.0, s[3];
         for (int d = 0; d < 3; d++) {
-          double sh = sin(PI * (double)mm[d] / (double)N);
+          int nd = d == 2 ? Nz : N;       /* modes along z are those of period Nz */
+          double sh = sin(PI * (double)mm[d] / (double)nd);
           lam += (4.0 / (h * h)) * sh * sh;
-          s[d] = sin_mode((int)mm[d], N) / h;
+          s[d] = sin_mode((int)mm[d], nd) / h;
         }
         double den = 1.0 + nu_dt * lam;
         double wr[3], wi[3];
@@ -459,7 +464,7 @@ double ibo_fluid(int N, double L, double rho, double mu, double dt, int convect,
         for (int c = 0; c < 3; c++) { re[c * G + p] = wr[c]; im[c * G + p] = wi[c]; }
       }
 
-  for (int c = 0; c < 3; c++) ibo_fft3(N, re + c * G, im + c * G, +1);
+  for (int c = 0; c < 3; c++) ibo_fft3(N, Nz, re + c * G, im + c * G, +1);
   double inv = 1.0 / (double)G, maxre = 0.0, maxim = 0.0;
   for (int64_t p = 0; p < 3 * G; p++) {
     u_new[p] = re[p] * inv;
@@ -475,18 +480,18 @@ double ibo_fluid(int N, double L, double rho, double mu, double dt, int convect,
  * force f^n, spread to F^n, NS update to u^{n+1}, move markers with u^{n+1}
  * interpolated at X^n (eq. discreteX).
  * ---------------------------------------------------------------------- */
-void ibo_step(const ibo_model *m, int N, double L, double rho, double mu, double dt,
+void ibo_step(const ibo_model *m, int N, int Nz, double L, double rho, double mu, double dt,
               int convect, double t, double *X, double *u, double *F_lag_out) {
-  int64_t M = m->M, G = (int64_t)N * N * N;
+  int64_t M = m->M, G = (int64_t)N * N * Nz;
   double *F = (double *)malloc(sizeof(double) * 3 * (size_t)(M > 0 ? M : 1));
   double *Fg = (double *)malloc(sizeof(double) * 3 * (size_t)G);
   double *un = (double *)malloc(sizeof(double) * 3 * (size_t)G);
   double *U = (double *)malloc(sizeof(double) * 3 * (size_t)(M > 0 ? M : 1));
   ibo_force(m, X, t, F);
   if (F_lag_out) memcpy(F_lag_out, F, sizeof(double) * 3 * (size_t)M);
-  ibo_spread(N, L, M, X, F, Fg);
-  ibo_fluid(N, L, rho, mu, dt, convect, u, Fg, un);
-  ibo_interp(N, L, M, X, un, U);
+  ibo_spread(N, Nz, L, M, X, F, Fg);
+  ibo_fluid(N, Nz, L, rho, mu, dt, convect, u, Fg, un);
+  ibo_interp(N, Nz, L, M, X, un, U);
   for (int64_t p = 0; p < 3 * M; p++) X[p] = X[p] + dt * U[p];
   memcpy(u, un, sizeof(double) * 3 * (size_t)G);
   free(F); free(Fg); free(un); free(U);
@@ -618,16 +623,16 @@ static void elastic_hvp_and_kbar(const ibo_model *m, const double *X, const doub
     }
 }
 
-void ibo_adjoint_step(const ibo_model *m, int N, double L, double rho, double mu, double dt,
+void ibo_adjoint_step(const ibo_model *m, int N, int Nz, double L, double rho, double mu, double dt,
                       double t, const double *X_n, const double *u_np1,
                       double *Xbar, double *ubar, double *kbar) {
-  ibo_adjoint_step_u(m, N, L, rho, mu, dt, t, 0, X_n, NULL, u_np1, Xbar, ubar, kbar);
+  ibo_adjoint_step_u(m, N, Nz, L, rho, mu, dt, t, 0, X_n, NULL, u_np1, Xbar, ubar, kbar);
 }
 
-void ibo_adjoint_step_u(const ibo_model *m, int N, double L, double rho, double mu, double dt,
+void ibo_adjoint_step_u(const ibo_model *m, int N, int Nz, double L, double rho, double mu, double dt,
                         double t, int convect, const double *X_n, const double *u_n, const double *u_np1,
                         double *Xbar, double *ubar, double *kbar) {
-  int64_t M = m->M, G = (int64_t)N * N * N;
+  int64_t M = m->M, G = (int64_t)N * N * Nz;
   double h = L / N, inv_h3 = 1.0 / (h * h * h);
   size_t mb = sizeof(double) * 3 * (size_t)(M > 0 ? M : 1);
   double *f = (double *)malloc(mb), *Ub = (double *)malloc(mb), *fb = (double *)calloc(3 * (size_t)(M > 0 ? M : 1), sizeof(double));
@@ -649,7 +654,7 @@ void ibo_adjoint_step_u(const ibo_model *m, int N, double L, double rho, double 
           double r[3] = {s[0] - (double)i, s[1] - (double)j, s[2] - (double)k};
           double p0 = ibo_phi(r[0]), p1 = ibo_phi(r[1]), p2 = ibo_phi(r[2]);
           double g0 = dphi(r[0]) / h, g1 = dphi(r[1]) / h, g2 = dphi(r[2]) / h;
-          int64_t p = gidx(N, i, j, k);
+          int64_t p = gidx(N, Nz, i, j, k);
           double uU = 0.0;
           for (int cc = 0; cc < 3; cc++) uU += u_np1[cc * G + p] * Ub[cc * M + q];
           gX[0] += uU * g0 * p1 * p2;
@@ -662,7 +667,7 @@ void ibo_adjoint_step_u(const ibo_model *m, int N, double L, double rho, double 
   }
 
   /* symmetric NS operator (no force, no advection) */
-  ibo_fluid(N, L, rho, mu, dt, 0, utot, NULL, ubar);
+  ibo_fluid(N, Nz, L, rho, mu, dt, 0, utot, NULL, ubar);
 
   /* spreading: transpose (an interpolation with 1/h^3) and phi' term */
   for (int64_t q = 0; q < M; q++) {
@@ -676,7 +681,7 @@ void ibo_adjoint_step_u(const ibo_model *m, int N, double L, double rho, double 
           double r[3] = {s[0] - (double)i, s[1] - (double)j, s[2] - (double)k};
           double p0 = ibo_phi(r[0]), p1 = ibo_phi(r[1]), p2 = ibo_phi(r[2]);
           double g0 = dphi(r[0]) / h, g1 = dphi(r[1]) / h, g2 = dphi(r[2]) / h;
-          int64_t p = gidx(N, i, j, k);
+          int64_t p = gidx(N, Nz, i, j, k);
           double Ff = 0.0;
           for (int cc = 0; cc < 3; cc++) {
             double Fb = (dt / rho) * ubar[cc * G + p];
@@ -697,7 +702,7 @@ void ibo_adjoint_step_u(const ibo_model *m, int N, double L, double rho, double 
   /* ubar is the cotangent of r = u - dt A(u) + (dt / rho) F; with advection
    * the velocity's own adjoint loses dt (dA/du)^T rbar */
   if (convect) {
-    ibo_advect_adjoint(N, L, u_n, ubar, utot);
+    ibo_advect_adjoint(N, Nz, L, u_n, ubar, utot);
     for (int64_t p = 0; p < 3 * G; p++) ubar[p] -= dt * utot[p];
   }
 

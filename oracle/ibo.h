@@ -20,8 +20,10 @@
  * notes; the ones that change arithmetic are restated next to the code.
  *
  * Layouts: marker arrays are SoA [3][M] (component-major); grid arrays are
- * [3][N][N][N] with x fastest: element (c, k, j, i) at ((c*N + k)*N + j)*N + i,
- * grid node (i, j, k) at position (i h, j h, k h), h = L / N.
+ * [3][Nz][N][N] with x fastest: element (c, k, j, i) at ((c*Nz + k)*N + j)*N + i,
+ * grid node (i, j, k) at position (i h, j h, k h), h = L / N.  The box is
+ * L x L x (Nz h): Nz = N is the cube, Nz = N/2 the half-cube of Sec. 4.
+ * Every function taking (N, Nz) wraps x and y with period N, z with Nz.
  */
 #ifndef IBO_H
 #define IBO_H
@@ -35,10 +37,11 @@ extern "C" {
 double ibo_phi(double r);
 
 /* Binning: cell of marker q is c_d = floor(X_d / h) wrapped into [0, N)
- * (N a multiple of 8); with block b = ((c3/8) (N/8) + c2/8) (N/8) + c1/8,
+ * ([0, Nz) along z; N, Nz multiples of 8); with block
+ * b = ((c3/8) (N/8) + c2/8) (N/8) + c1/8,
  * key = ((b * 8 + c3%8) * 8 + c2%8) * 8 + c1%8.  perm lists marker ids ordered
  * by key, ties by marker id (a stable sort).  keys_sorted[i] = key of perm[i]. */
-void ibo_bin(int N, double L, int64_t M, const double *X,
+void ibo_bin(int N, int Nz, double L, int64_t M, const double *X,
              uint32_t *keys_sorted, int32_t *perm);
 
 /* Material force F_q = f(q) dq on every marker (sub-step 1), and its energy. */
@@ -63,33 +66,33 @@ void   ibo_force(const ibo_model *m, const double *X, double t, double *F);
 double ibo_energy(const ibo_model *m, const double *X);
 
 /* Sub-step 2, eq. discreteF: Fg = sum_q F_q delta_h(x - X_q) (overwrite). */
-void ibo_spread(int N, double L, int64_t M, const double *X, const double *Fq, double *Fg);
+void ibo_spread(int N, int Nz, double L, int64_t M, const double *X, const double *Fq, double *Fg);
 /* Sub-step 4 velocity, eq. discreteX: U_q = sum_x u(x) delta_h(x - X_q) h^3. */
-void ibo_interp(int N, double L, int64_t M, const double *X, const double *u, double *U);
-/* Upwind advection sum_k u_k D_k^{+-} u (eq. discreteNS1), [3][N^3] -> [3][N^3]. */
-void ibo_advect(int N, double L, const double *u, double *A);
+void ibo_interp(int N, int Nz, double L, int64_t M, const double *X, const double *u, double *U);
+/* Upwind advection sum_k u_k D_k^{+-} u (eq. discreteNS1), [3][G] -> [3][G], G = N^2 Nz. */
+void ibo_advect(int N, int Nz, double L, const double *u, double *A);
 /* out = (dA/du)^T r: the transpose of ibo_advect linearised at u, each
  * upwind branch frozen at the sign u_k(x) takes. */
-void ibo_advect_adjoint(int N, double L, const double *u, const double *r, double *out);
-/* In-place complex 3-D DFT of an N^3 array (x fastest): sign -1 forward,
- * +1 inverse; no normalisation. */
-void ibo_fft3(int N, double *re, double *im, int sign);
+void ibo_advect_adjoint(int N, int Nz, double L, const double *u, const double *r, double *out);
+/* In-place complex 3-D DFT of an Nz x N x N array (x fastest): sign -1
+ * forward, +1 inverse; no normalisation. */
+void ibo_fft3(int N, int Nz, double *re, double *im, int sign);
 /* Sub-step 3, eqs. discreteNS1-2: u_new from u, Fg.  Returns the largest
  * |imaginary part| of the inverse transform relative to max |u_new|. */
-double ibo_fluid(int N, double L, double rho, double mu, double dt, int convect,
+double ibo_fluid(int N, int Nz, double L, double rho, double mu, double dt, int convect,
                  const double *u, const double *Fg, double *u_new);
 /* One full time step: X, u advanced in place; F_lag_out (nullable) gets f^n dq. */
-void ibo_step(const ibo_model *m, int N, double L, double rho, double mu, double dt,
+void ibo_step(const ibo_model *m, int N, int Nz, double L, double rho, double mu, double dt,
               int convect, double t, double *X, double *u, double *F_lag_out);
 
 /* Reverse-mode (adjoint) step for convect = 0, given Xbar, ubar at n+1:
  * overwrites them with the adjoints at n and accumulates kbar += (df/dk)^T fbar. */
-void ibo_adjoint_step(const ibo_model *m, int N, double L, double rho, double mu, double dt,
+void ibo_adjoint_step(const ibo_model *m, int N, int Nz, double L, double rho, double mu, double dt,
                       double t, const double *X_n, const double *u_np1,
                       double *Xbar, double *ubar, double *kbar);
 /* The same for either convect setting; u_n (the step's starting velocity,
  * where the upwind branches are frozen) is read when convect = 1. */
-void ibo_adjoint_step_u(const ibo_model *m, int N, double L, double rho, double mu, double dt,
+void ibo_adjoint_step_u(const ibo_model *m, int N, int Nz, double L, double rho, double mu, double dt,
                         double t, int convect, const double *X_n, const double *u_n, const double *u_np1,
                         double *Xbar, double *ubar, double *kbar);
 

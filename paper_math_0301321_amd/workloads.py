@@ -43,8 +43,8 @@ class Lattice:
 @dataclass
 class Workload:
     name: str
-    N: int                 # grid points per dimension (periodic cube)
-    L: float               # box edge; h = L / N
+    N: int                 # grid points along x and y (and z, unless Nz is set)
+    L: float               # box edge along x and y; h = L / N in every direction
     rho: float
     mu: float
     dt: float
@@ -64,10 +64,20 @@ class Workload:
     drive_A: float = 0.0
     drive_freq: float = 0.0
     meta: dict = field(default_factory=dict)
+    Nz: int = 0            # grid points along z: 0 means N (the cube); N / 2 is the half-cube of Sec. 4
 
     @property
     def M(self) -> int:
         return int(self.X0.shape[1])
+
+    @property
+    def nz(self) -> int:
+        return int(self.Nz) if self.Nz else int(self.N)
+
+    @property
+    def grid_shape(self) -> tuple:
+        """Shape of one grid field, [component, z, y, x]."""
+        return (3, self.nz, self.N, self.N)
 
     @property
     def h(self) -> float:
@@ -78,7 +88,11 @@ class Workload:
         import copy
         wl = copy.copy(self)
         wl.N = int(N)
-        wl.name = f"{self.name}@{N}^3"
+        if self.Nz:
+            wl.Nz = int(N) * int(self.Nz) // int(self.N)
+            wl.name = f"{self.name}@{N}x{N}x{wl.Nz}"
+        else:
+            wl.name = f"{self.name}@{N}^3"
         return wl
 
 
@@ -169,9 +183,25 @@ def _centre(s):
     return C, dC, er
 
 
+# flat spiral of the half-cube model (Sec. 4): 1.5 turns in the plane z = 1/4
+_FLAT_TURNS = 1.5
+
+
+def _centre_flat(s):
+    th = 2.0 * math.pi * _FLAT_TURNS * s
+    R = 0.38 - 0.28 * s
+    C = np.stack([0.5 + R * np.cos(th), 0.5 + R * np.sin(th), np.full_like(s, 0.25)])
+    dth = 2.0 * math.pi * _FLAT_TURNS
+    dC = np.stack([-0.28 * np.cos(th) - R * dth * np.sin(th),
+                   -0.28 * np.sin(th) + R * dth * np.cos(th),
+                   np.zeros_like(s)])
+    er = np.stack([np.cos(th), np.sin(th), np.zeros_like(s)])
+    return C, dC, er
+
+
 def helicoid_in_tube(nb1, nb2, nw1, nw2, win1, win2, *, N, dt, n_steps, freq,
                      Ks=50.0, Kb=3e-4, kappa=1e5, drive_A=1e2, jitter_seed=None,
-                     convect=1, name="helix", window=None) -> Workload:
+                     convect=1, name="helix", window=None, flat=False) -> Workload:
     """Tapered helicoidal strip ('BM', nb1 x nb2) inside a coiled tube wall (nw1 x nw2).
 
     BM centre line C(s) = (1/2 + R cos th, 1/2 + R sin th, 0.2 + 0.6 s), th = 5 pi s
@@ -188,12 +218,21 @@ def helicoid_in_tube(nb1, nb2, nw1, nw2, win1, win2, *, N, dt, n_steps, freq,
     circle are held by tethers and whose markers inside move freely, with
     stretch and bend moduli Ks, Kb, under the sinusoidal force along the
     outward normal.
+
+    ``flat = True`` builds the half-cube model of Sec. 4 instead: the grid is
+    N x N x N/2 (box 1 x 1 x 1/2) and the membrane is flat, its centre line
+    the planar spiral (1/2 + R cos th, 1/2 + R sin th, 1/4), th = 3 pi s
+    (1.5 turns), R = 0.38 - 0.28 s, the strip spanning the radial direction
+    within that plane; the tube radius is a = 0.07 - 0.03 s so that the
+    coils stay apart and the tube stays inside 0 < z < 1/2.
     """
+    centre = _centre_flat if flat else _centre
+    tube_a = (lambda s_: 0.07 - 0.03 * s_) if flat else (lambda s_: 0.10 - 0.04 * s_)
     # ---- basilar membrane lattice, fibre by fibre (the membrane's fibres run
     # across its width): index = i1 * nb2 + i2 for station i1 < nb1 along the
     # length and position i2 < nb2 across ----
     s = np.linspace(0.0, 1.0, nb1)
-    C, dC, er = _centre(s)
+    C, dC, er = centre(s)
     b = 0.015 + 0.041 * s
     eta = np.linspace(-0.5, 0.5, nb2)
     BM = C[:, None, :] + eta[None, :, None] * (b * er)[:, None, :]      # (3, nb2, nb1)
@@ -210,12 +249,12 @@ def helicoid_in_tube(nb1, nb2, nw1, nw2, win1, win2, *, N, dt, n_steps, freq,
 
     # ---- tube wall lattice (periodic around): index = M_bm + i2 * nw1 + i1 ----
     sw = np.linspace(0.0, 1.0, nw1)
-    Cw, dCw, erw = _centre(sw)
+    Cw, dCw, erw = centre(sw)
     t = dCw / np.linalg.norm(dCw, axis=0)
     n1 = erw - (erw * t).sum(0) * t
     n1 /= np.linalg.norm(n1, axis=0)
     n2 = np.cross(t.T, n1.T).T
-    a = 0.10 - 0.04 * sw
+    a = tube_a(sw)
     ph = 2.0 * math.pi * np.arange(nw2) / nw2
     nrm = (np.cos(ph)[:, None, None] * n1.T[None, :, :]
            + np.sin(ph)[:, None, None] * n2.T[None, :, :])                 # (nw2, nw1, 3)
@@ -243,16 +282,16 @@ def helicoid_in_tube(nb1, nb2, nw1, nw2, win1, win2, *, N, dt, n_steps, freq,
         # window lattice: index = M_bm + M_w + j * nw + i, i along the tube, j around it
         nwin = int(window)
         s0 = np.array([0.03])
-        C0, dC0, er0 = _centre(s0)
+        C0, dC0, er0 = centre(s0)
         t0 = (dC0 / np.linalg.norm(dC0, axis=0))[:, 0]
         m1 = er0[:, 0] - (er0[:, 0] @ t0) * t0
         m1 /= np.linalg.norm(m1)                      # outward normal of the wall at phase 0
         m2 = np.cross(t0, m1)
-        centre = C0[:, 0] + (0.10 - 0.04 * s0[0]) * m1
+        wc = C0[:, 0] + tube_a(s0[0]) * m1
         d = 0.5 / N                                   # spacing h/2
         off = (np.arange(nwin) - 0.5 * (nwin - 1)) * d
         oj, oi = np.meshgrid(off, off, indexing="ij")
-        WIN = centre[:, None, None] + oi[None] * t0[:, None, None] + oj[None] * m2[:, None, None]
+        WIN = wc[:, None, None] + oi[None] * t0[:, None, None] + oj[None] * m2[:, None, None]
         inside = (oi ** 2 + oj ** 2 <= (0.5 * (nwin - 1) * d) ** 2).reshape(-1)
         M_win = nwin * nwin
         X0 = np.ascontiguousarray(np.concatenate([X0, WIN.reshape(3, M_win)], axis=1))
@@ -271,7 +310,7 @@ def helicoid_in_tube(nb1, nb2, nw1, nw2, win1, win2, *, N, dt, n_steps, freq,
         kappa=np.ascontiguousarray(kap), lattices=lattices,
         spring_ab=np.zeros((2, 0), np.int32), spring_rest=np.zeros(0), K_spring=0.0,
         drive_idx=didx, drive_dir=np.ascontiguousarray(ddir), drive_A=drive_A,
-        drive_freq=float(freq), meta=meta)
+        drive_freq=float(freq), meta=meta, Nz=N // 2 if flat else 0)
 
 
 def config2(N: int = 128) -> Workload:
@@ -340,6 +379,21 @@ def window128(N: int = 128) -> Workload:
                             freq=1000.0, name="window128", window=48)
 
 
+def halfcube(N: int = 256) -> Workload:
+    """The half-cube model of Sec. 4 on an N x N x N/2 grid (256 x 256 x 128:
+    the grid of the paper's reported runs): flat spiral membrane 1200 x 500 in
+    a coiled tube wall 1800 x 500, 1.5M markers, the drive and time step of
+    the 256^3 helix."""
+    return helicoid_in_tube(1200, 500, 1800, 500, 36, 167, N=N, dt=2.5e-5, n_steps=500,
+                            freq=1000.0, jitter_seed=0, name=f"halfcube{N}", flat=True)
+
+
+def tiny_halfcube(N: int = 32, nb=(60, 12), nw=(80, 24), dt=2e-4, n_steps=10) -> Workload:
+    """A scaled-down half-cube model for fast parity tests (N x N x N/2)."""
+    return helicoid_in_tube(nb[0], nb[1], nw[0], nw[1], 4, 6, N=N, dt=dt, n_steps=n_steps,
+                            freq=1000.0, jitter_seed=0, name=f"halfcube_tiny{N}", flat=True)
+
+
 def random_markers(M: int, seed: int = 2, lo: float = 0.0, hi: float = 1.0):
     """Uniform random marker positions and forces (seed 2 is used for test fields)."""
     rng = np.random.default_rng(seed)
@@ -348,9 +402,9 @@ def random_markers(M: int, seed: int = 2, lo: float = 0.0, hi: float = 1.0):
     return X, F
 
 
-def random_field(N: int, seed: int = 2, comps: int = 3):
+def random_field(N: int, seed: int = 2, comps: int = 3, Nz: int | None = None):
     rng = np.random.default_rng(seed)
-    return rng.standard_normal((comps, N, N, N))
+    return rng.standard_normal((comps, N if Nz is None else Nz, N, N))
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
