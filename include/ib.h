@@ -10,10 +10,12 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- *  - Grid: a periodic cube of n^3 nodes at positions (i h, j h, k h), h = L/n
- *    (one mesh width in all directions; n a power of two in [8, 512]).
- *  - Grid fields (u, F_grid, ubar) are DEVICE arrays [3][n][n][n], x fastest:
- *    component c of node (i, j, k) at ((c*n + k)*n + j)*n + i, in the fluid
+ *  - Grid: a periodic box of n x n x nz nodes at positions (i h, j h, k h),
+ *    h = L/n (one mesh width in all directions; n a power of two in
+ *    [8, 512]).  nz = n is the cube; nz = n/2 is the half-cube of Sec. 4
+ *    (box L x L x L/2), available for n in [32, 256].
+ *  - Grid fields (u, F_grid, ubar) are DEVICE arrays [3][nz][n][n], x fastest:
+ *    component c of node (i, j, k) at ((c*nz + k)*n + j)*n + i, in the fluid
  *    precision (double for IB_FLUID_FP64, float for IB_FLUID_FP32).
  *  - Marker arrays (X, F_lag, U, Xbar) are DEVICE double arrays [3][M]
  *    (component-major).  X is stored unwrapped; only grid indices wrap.
@@ -58,6 +60,7 @@ typedef struct {
   int32_t convect;           /* 0 or 1                                               */
   int64_t n_markers;         /* M >= 0, < 2^31                                      */
   void *stream;              /* hipStream_t (NULL: the null stream)                 */
+  int32_t nz;                /* nodes along z: 0 or n (cube), n/2 (half-cube)       */
 } ib_params;
 
 /* A rectangular material lattice Q (Sec. 3.2): markers first + i2*n1 + i1,
@@ -103,7 +106,8 @@ typedef struct {
 
 /* Validate, copy the topology, allocate the workspace.  IB_EINVAL on a bad
  * parameter or topology index, IB_ENOTSUP for n outside [8, 512] or not a
- * power of two, IB_ENOMEM on allocation failure.  *out is NULL on error. */
+ * power of two, or nz other than 0, n and n/2 (n/2 only for n in [32, 256]),
+ * IB_ENOMEM on allocation failure.  *out is NULL on error. */
 int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out);
 void ib_destroy(ib_ctx *c);
 
@@ -124,7 +128,7 @@ int ib_step(ib_ctx *c, double *X, void *u, double t, double *F_lag_out);
 int ib_force(ib_ctx *c, const double *X, double t, double *F_lag);
 
 /* Sub-step 2, eq. discreteF: F_grid = sum_q F_lag[q] delta_h(x - X_q)
- * (overwrites the whole [3][n^3] F_grid). */
+ * (overwrites the whole [3][nz][n][n] F_grid). */
 int ib_spread(ib_ctx *c, const double *X, const double *F_lag, void *F_grid);
 
 /* Velocity of eq. discreteX: U_q = sum_x u(x) delta_h(x - X_q) h^3, [3][M] double. */
@@ -135,8 +139,9 @@ int ib_interp(ib_ctx *c, const double *X, const void *u, double *U);
 int ib_fluid(ib_ctx *c, void *u, const void *F_grid);
 
 /* The binning that partitions markers among grid cells (Sec. 3.3): the cell
- * of marker q is c = floor(X_q / h) per dimension wrapped into [0, n); cells
- * are grouped in 8^3 tiles, tile = ((c3/8)*(n/8) + c2/8)*(n/8) + c1/8, and
+ * of marker q is c = floor(X_q / h) per dimension wrapped into [0, n) ([0, nz)
+ * along z); cells are grouped in 8^3 tiles,
+ * tile = ((c3/8)*(n/8) + c2/8)*(n/8) + c1/8, and
  * key = tile*512 + ((c3%8)*8 + c2%8)*8 + c1%8.  perm[i] lists marker ids by
  * key, ties by id (stable); keys_sorted[i] is the key of perm[i].  Both
  * DEVICE arrays of length M. */
@@ -144,7 +149,7 @@ int ib_bin(ib_ctx *c, const double *X, uint32_t *keys_sorted, int32_t *perm);
 
 /* Adjoint of ib_step for convect = 0 (IB_ENOTSUP otherwise).  Inputs: X_n
  * (the step's starting positions), u_np1 (the velocity it produced), t.
- * On entry Xbar [3][M] double and ubar [3][n^3] (fluid precision) hold the
+ * On entry Xbar [3][M] double and ubar [3][nz][n][n] (fluid precision) hold the
  * adjoints at step n+1; on return they hold those at step n, and
  * kbar [M] double has (df/dk)^T fbar added to it. */
 int ib_adjoint_step(ib_ctx *c, const double *X_n, const void *u_np1, double t,
@@ -152,7 +157,7 @@ int ib_adjoint_step(ib_ctx *c, const double *X_n, const void *u_np1, double t,
 /* The same for either convect setting.  With convect = 1 the upwind advection
  * of eq. discreteNS1 is differentiated with each branch frozen at the side
  * u^n selects (the derivative away from u_k = 0; no term where u_k = 0), so
- * u_n [3][n^3] (fluid precision, the velocity the step started from) is
+ * u_n [3][nz][n][n] (fluid precision, the velocity the step started from) is
  * required; with convect = 0 it is not read and may be NULL.  IB_EINVAL when
  * it is missing for convect = 1. */
 int ib_adjoint_step_u(ib_ctx *c, const double *X_n, const void *u_n, const void *u_np1, double t,

@@ -140,6 +140,11 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
     g_create_error = "ib_create: n must be a power of two in [8, 512]";
     return IB_ENOTSUP;
   }
+  const int nz = p->nz == 0 ? n : p->nz;
+  if (nz != n && !(2 * nz == n && fluid_reg_supported(n, nz))) {
+    g_create_error = "ib_create: nz must be 0, n, or n/2 with n in [32, 256]";
+    return IB_ENOTSUP;
+  }
   if (!(p->L > 0.0) || !is_fin(p->L) || !(p->rho > 0.0) || !is_fin(p->rho) || !(p->mu >= 0.0) || !is_fin(p->mu) ||
       !(p->dt > 0.0) || !is_fin(p->dt)) {
     g_create_error = "ib_create: need L > 0, rho > 0, mu >= 0, dt > 0 (finite)";
@@ -217,9 +222,12 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
 
   ib_ctx *c = new ib_ctx();
   c->p = *p;
+  c->p.nz = nz;
   c->n = n;
   while ((1 << c->log2n) < n) c->log2n++;
-  c->G = (int64_t)n * n * n;
+  c->nz = nz;
+  while ((1 << c->log2nz) < nz) c->log2nz++;
+  c->G = (int64_t)n * n * nz;
   c->M = M;
   c->h = p->L / n;
   c->fp32 = p->fluid_precision == IB_FLUID_FP32;
@@ -227,12 +235,13 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
   const char *chk = getenv("IB_CHECK");
   c->check = chk && chk[0] == '1';
   c->log2nt = c->log2n - 3;
-  c->ntiles = (int64_t)1 << (3 * c->log2nt);
+  c->log2ntz = c->log2nz - 3;
+  c->ntiles = (int64_t)1 << (2 * c->log2nt + c->log2ntz);
   c->n_springs = S;
   c->n_drive = D;
   c->drive_A = e->drive_A;
   c->drive_freq = e->drive_freq;
-  const int key_bits = 3 * c->log2n;
+  const int key_bits = 2 * c->log2n + c->log2nz;
   c->sort_passes = (key_bits + 7) / 8;
   c->digit_bits = (key_bits + c->sort_passes - 1) / c->sort_passes;
 
@@ -300,8 +309,8 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
     chk_alloc(dalloc(c, &w.scan_tmp, 3 * ((ntiles + 1023) / 1024)));
     chk_alloc(dalloc_bytes(c, &w.partials, c->item_cap * kPartStride * (int64_t)ts));
   }
-  if (!fluid_reg_supported(n)) chk_alloc(dalloc_bytes(c, &w.r, 3 * c->G * (int64_t)ts));   // the fused path keeps r in LDS
-  chk_alloc(dalloc_bytes(c, &w.spec, 3 * nh * (int64_t)n * n * 2 * (int64_t)ts));
+  if (!fluid_reg_supported(n, nz)) chk_alloc(dalloc_bytes(c, &w.r, 3 * c->G * (int64_t)ts));   // the fused path keeps r in LDS
+  chk_alloc(dalloc_bytes(c, &w.spec, 3 * nh * (int64_t)n * nz * 2 * (int64_t)ts));
   chk_alloc(dalloc(c, &w.nonfinite, 1));
   chk_alloc(dalloc_bytes(c, &w.tw, 2 * (int64_t)n * (int64_t)ts));
   chk_alloc(dalloc_bytes(c, &w.lam, (int64_t)n * (int64_t)ts));

@@ -1,5 +1,6 @@
 // Register-resident FFT passes of the Navier-Stokes update (eqs. discreteNS1-2)
-// for n = 32, 64, 128, 256.
+// for n = 32, 64, 128, 256 along x and y, and nz = n or n / 2 along z (the
+// cube, or the half-cube of Sec. 4).
 //
 // A length-n transform is split as n = R1 * R2 (four-step): each of the
 // P = min(R1, R2) threads that own a pencil holds n / P values in registers,
@@ -12,12 +13,15 @@
 //   k_xf_rhs   r = u - dt (upwind advection) + (dt/rho) F for a block of
 //              rows, kept in LDS, then transformed (two real rows packed as
 //              one complex pencil), writing modes kx = 0 .. n/2 to
-//              spec[c][kx][z][y] (runs of 128 bytes along y);
+//              spec[c][kx][z][y], z < nz (runs of 128 bytes along y);
 //   k_y        forward or inverse along y (contiguous pencils);
 //   k_z_solve  forward along z for all three components of a (kx, y-block),
 //              the diagonal viscous solve and the projection per mode in
 //              registers, inverse along z;
-//   k_xi       inverse along x, real rows, scaled by 1/n^3.
+//   k_xi       inverse along x, real rows, scaled by 1/(n^2 nz).
+// Along z of length nz = n / s the twiddles, eigenvalues and gradient
+// symbols are those of length n at stride s (exp(-2 pi i k / nz) is the
+// n-table's entry s k), so one set of tables serves both lengths.
 #include "dev_common.h"
 #include "ib_internal.h"
 
@@ -127,7 +131,8 @@ __device__ __forceinline__ void wave_sync() {
 //   out: v[i R2 + k2] = X[(t + P i) + R1 k2],  i < R1/P, k2 < R2
 // xch: R1 (R2 + 1) LDS values private to the pencil.  BLOCK: the pencil's
 // threads span several waves (block barrier) instead of one (wave barrier).
-template <typename T, int R1, int R2, bool INV, bool BLOCK>
+// tw holds exp(-2 pi i k / (TS N)); the transform reads it at stride TS.
+template <typename T, int R1, int R2, bool INV, bool BLOCK, int TS = 1>
 struct Fft4 {
   static constexpr int N = R1 * R2;
   static constexpr int P = R1 < R2 ? R1 : R2;
@@ -145,7 +150,7 @@ struct Fft4 {
       const int s = t + P * i;
 #pragma unroll
       for (int k1 = 1; k1 < R1; k1++) {
-        cplx<T> w = tw[s * k1];
+        cplx<T> w = tw[s * k1 * TS];
         if (INV) w.y = -w.y;
         v[i * R1 + k1] = cmul(v[i * R1 + k1], w);
       }
@@ -248,14 +253,16 @@ __device__ __forceinline__ Vec16<T> bload16(__amdgpu_buffer_rsrc_t r, uint32_t v
 template <typename T, int R1, int R2, int YB, bool CONV>
 __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf_rhs(
     const T *__restrict__ u, const T *__restrict__ Fg, const uint32_t *__restrict__ touch_bits, int fmode,
-    T dt_inv_h, T f_scale, const cplx<T> *__restrict__ tw, cplx<T> *__restrict__ spec) {
+    T dt_inv_h, T f_scale, const cplx<T> *__restrict__ tw, cplx<T> *__restrict__ spec, int nz) {
   using F4 = Fft4<T, R1, R2, false, false>;
   using SM = XfSmem<T, R1, R2, YB>;
   using V = Vec16<T>;
   constexpr int N = R1 * R2, P = F4::P, E = F4::E, NP = 3 * YB / 2;
   constexpr int NH = N / 2 + 1, mask = N - 1, NT = NP * P, US = SM::US, OS = SM::OS, HR = SM::HR;
   constexpr int EPC = 16 / sizeof(T), CPR = N / EPC;
-  constexpr int64_t G = (int64_t)N * N * N, NN = (int64_t)N * N;
+  constexpr int64_t NN = (int64_t)N * N;
+  const int64_t G = NN * nz;
+  const int zmask = nz - 1;
   constexpr int RUNS = 3 * YB * CPR / NT;              // r runs per thread
   static_assert(RUNS * NT == 3 * YB * CPR, "runs must divide among the threads");
   constexpr int GMAX = sizeof(T) == 4 ? 8 : 4;
@@ -300,8 +307,8 @@ __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf_rhs(
       int row, x4;
       const uint32_t at = run_at(g0 + k, row, x4);
       if (CONV) {
-        vzm[k] = bload16<T>(urs, at + (uint32_t)(((z - 1) & mask) * NN * TB));
-        vzp[k] = bload16<T>(urs, at + (uint32_t)(((z + 1) & mask) * NN * TB));
+        vzm[k] = bload16<T>(urs, at + (uint32_t)(((z - 1) & zmask) * NN * TB));
+        vzp[k] = bload16<T>(urs, at + (uint32_t)(((z + 1) & zmask) * NN * TB));
       }
       fv[k] = bload16<T>(frs, has[g0 + k] ? at + (uint32_t)(z * NN * TB) : fbytes);
     }
@@ -437,7 +444,7 @@ __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf_rhs(
   __syncthreads();
   for (int e = tid; e < 3 * NH * YB; e += NT) {
     const int yy = e % YB, ck = e / YB, k = ck % NH, cc = ck / NH;
-    spec[(((int64_t)cc * NH + k) * N + z) * N + y0 + yy] = outs[ck * OS + yy];
+    spec[(((int64_t)cc * NH + k) * nz + z) * N + y0 + yy] = outs[ck * OS + yy];
   }
 }
 
@@ -465,25 +472,29 @@ __global__ __launch_bounds__(256) void k_y(cplx<T> *__restrict__ spec, int64_t n
 }
 
 // ------------------------------------------------- pass z with the solve ----
-template <typename T, int R1, int R2>
+// z transforms of length NZ = R1 R2 on a grid of NY x NY x NZ nodes (NZ = NY
+// or NY / 2); the tables are those of length NY, read at stride NY / NZ.
+template <typename T, int R1, int R2, int NY>
 __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ? 2 : 1) void k_z_solve(
     cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ tw, const T *__restrict__ lam,
     const T *__restrict__ sg, T nu_dt) {
-  using Ff = Fft4<T, R1, R2, false, true>;
-  using Fi = Fft4<T, R2, R1, true, true>;
-  constexpr int N = R1 * R2, P = Ff::P, E = Ff::E, YB = XfCfg<T>::YB, NH = N / 2 + 1;
+  constexpr int NZ = R1 * R2, TS = NY / NZ;
+  static_assert(TS * NZ == NY && (TS == 1 || TS == 2), "nz = n or n / 2");
+  using Ff = Fft4<T, R1, R2, false, true, TS>;
+  using Fi = Fft4<T, R2, R1, true, true, TS>;
+  constexpr int P = Ff::P, E = Ff::E, YB = XfCfg<T>::YB, NH = NY / 2 + 1;
   // per-y exchange space, padded to 2 (mod 32) values so that the 16 y's and
   // neighbouring t's of a wave fall in distinct LDS banks
   constexpr int XS0 = (R1 * (R2 + 1) > R2 * (R1 + 1)) ? R1 * (R2 + 1) : R2 * (R1 + 1);
   constexpr int XSZ = XS0 + ((2 - XS0 % 32) + 32) % 32;
   __shared__ cplx<T> xch[YB * XSZ];
-  const int nyb = N / YB;
+  const int nyb = NY / YB;
   const int kx = blockIdx.x / nyb, y0 = (blockIdx.x % nyb) * YB;
   const int yy = threadIdx.x % YB, t = threadIdx.x / YB;
   constexpr uint32_t CB = sizeof(cplx<T>);
-  constexpr uint32_t cs = (uint32_t)NH * N * N * CB;                // component stride, bytes
+  constexpr uint32_t cs = (uint32_t)NH * NZ * NY * CB;              // component stride, bytes
   const __amdgpu_buffer_rsrc_t rs = spec_rsrc(spec, 3 * cs);
-  const uint32_t voff = ((uint32_t)(kx * N + t) * N + y0 + yy) * CB;  // (kx, z = t, y)
+  const uint32_t voff = ((uint32_t)(kx * NZ + t) * NY + y0 + yy) * CB;  // (kx, z = t, y)
   cplx<T> v[3][E];
 #pragma unroll
   for (int c = 0; c < 3; c++)
@@ -491,7 +502,7 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ?
     for (int i = 0; i < R2 / P; i++)
 #pragma unroll
       for (int j = 0; j < R1; j++)
-        v[c][i * R1 + j] = bload(rs, voff, c * cs + (uint32_t)((P * i + R2 * j) * N) * CB, T(0));
+        v[c][i * R1 + j] = bload(rs, voff, c * cs + (uint32_t)((P * i + R2 * j) * NY) * CB, T(0));
 #pragma unroll
   for (int c = 0; c < 3; c++) Ff::run(v[c], t, xch + yy * XSZ, tw);
   // per mode (kx, ky, kz): w = r^/(1 + nu dt lambda), then remove the s-component
@@ -504,8 +515,8 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ?
     for (int k2 = 0; k2 < R2; k2++) {
       const int e = i * R2 + k2;
       const int kz = (t + P * i) + R1 * k2;
-      const T rden = T(1) / (T(1) + nu_dt * (lxy + lam[kz]));
-      const T s2 = sg[kz];
+      const T rden = T(1) / (T(1) + nu_dt * (lxy + lam[kz * TS]));
+      const T s2 = sg[kz * TS];
       cplx<T> w0{v[0][e].x * rden, v[0][e].y * rden};
       cplx<T> w1{v[1][e].x * rden, v[1][e].y * rden};
       cplx<T> w2{v[2][e].x * rden, v[2][e].y * rden};
@@ -530,17 +541,17 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ?
 #pragma unroll
     for (int i = 0; i < R2 / P; i++)
 #pragma unroll
-      for (int j = 0; j < R1; j++) bstore(rs, voff, c * cs + (uint32_t)((P * i + R2 * j) * N) * CB, v[c][i * R1 + j]);
+      for (int j = 0; j < R1; j++) bstore(rs, voff, c * cs + (uint32_t)((P * i + R2 * j) * NY) * CB, v[c][i * R1 + j]);
 }
 
 // ------------------------------------------------------ pass x, inverse ----
 template <typename T, int R1, int R2, int YB>
 __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xi(
-    const cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ tw, T scale, T *__restrict__ u) {
+    const cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ tw, T scale, T *__restrict__ u, int nz) {
   using F4 = Fft4<T, R1, R2, true, false>;
   constexpr int N = R1 * R2, P = F4::P, E = F4::E, NP = 3 * YB / 2;
-  constexpr int NH = N / 2 + 1, mask = N - 1, NT = NP * P;
-  constexpr int64_t G = (int64_t)N * N * N;
+  constexpr int NH = N / 2 + 1, NT = NP * P;
+  const int64_t G = (int64_t)N * N * nz;
   __shared__ __attribute__((aligned(16))) unsigned char smem[XfSmem<T, R1, R2, YB>::BYTES_INV];
   constexpr int OS = XfSmem<T, R1, R2, YB>::OS;
   cplx<T> *stage = (cplx<T> *)smem;                   // [3][NH][OS]
@@ -558,7 +569,7 @@ __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xi(
       const int e = tid + k * NT;
       if (e < TOT) {
         const int q = e % CPRUN, ck = e / CPRUN, kk = ck % NH, cc = ck / NH;
-        tmp[k] = *(const V *)(spec + (((int64_t)cc * NH + kk) * N + z) * N + y0 + q * CPC);
+        tmp[k] = *(const V *)(spec + (((int64_t)cc * NH + kk) * nz + z) * N + y0 + q * CPC);
       }
     }
 #pragma unroll
@@ -604,9 +615,13 @@ __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xi(
     }
 }
 
-template <typename T, int R1, int R2>
+// (R1, R2): factors of n (x and y); (Z1, Z2): factors of nz (z).
+template <typename T, int R1, int R2, int Z1, int Z2>
 hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect, double f_scale, T *u_out) {
   constexpr int N = R1 * R2, P = R1 < R2 ? R1 : R2, YB = XfCfg<T>::YB, NH = N / 2 + 1;
+  constexpr int NZ = Z1 * Z2, PZ = Z1 < Z2 ? Z1 : Z2;
+  const int nz = c->nz;
+  if (c->n != N || nz != NZ) return hipErrorInvalidValue;
   cplx<T> *spec = (cplx<T> *)c->ws.spec;
   const cplx<T> *tw = (const cplx<T> *)c->ws.tw;
   {
@@ -615,13 +630,13 @@ hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect
     const T dtih = (T)c->p.dt * (T)(1.0 / c->h);
     constexpr int YR = XrCfg<T>::YB;
     if (convect)
-      hipLaunchKernelGGL((k_xf_rhs<T, R1, R2, YR, true>), dim3(N * (N / YR)), dim3(3 * YR / 2 * P), 0, c->stream,
-                         u_in, Fg, c->ws.touch_bits, fm, dtih, (T)f_scale, tw, spec);
+      hipLaunchKernelGGL((k_xf_rhs<T, R1, R2, YR, true>), dim3(NZ * (N / YR)), dim3(3 * YR / 2 * P), 0, c->stream,
+                         u_in, Fg, c->ws.touch_bits, fm, dtih, (T)f_scale, tw, spec, nz);
     else
-      hipLaunchKernelGGL((k_xf_rhs<T, R1, R2, YR, false>), dim3(N * (N / YR)), dim3(3 * YR / 2 * P), 0, c->stream,
-                         u_in, Fg, c->ws.touch_bits, fm, dtih, (T)f_scale, tw, spec);
+      hipLaunchKernelGGL((k_xf_rhs<T, R1, R2, YR, false>), dim3(NZ * (N / YR)), dim3(3 * YR / 2 * P), 0, c->stream,
+                         u_in, Fg, c->ws.touch_bits, fm, dtih, (T)f_scale, tw, spec, nz);
   }
-  const int64_t npen = (int64_t)3 * NH * N;
+  const int64_t npen = (int64_t)3 * NH * NZ;
   const unsigned ny = (unsigned)((npen + 256 / P - 1) / (256 / P));
   {
     PhaseScope ps(c, PH_FFT_Y);
@@ -629,7 +644,7 @@ hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect
   }
   {
     PhaseScope ps(c, PH_FFT_Z_SOLVE);
-    hipLaunchKernelGGL((k_z_solve<T, R1, R2>), dim3(NH * (N / YB)), dim3(YB * P), 0, c->stream, spec, tw,
+    hipLaunchKernelGGL((k_z_solve<T, Z1, Z2, N>), dim3(NH * (N / YB)), dim3(YB * PZ), 0, c->stream, spec, tw,
                        (const T *)c->ws.lam, (const T *)c->ws.sgrad, (T)(c->p.mu * c->p.dt / c->p.rho));
   }
   {
@@ -639,24 +654,35 @@ hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect
   {
     PhaseScope ps(c, PH_FFT_X_INV);
     constexpr int YI = XiCfg<T>::YB;
-    hipLaunchKernelGGL((k_xi<T, R1, R2, YI>), dim3(N * (N / YI)), dim3(3 * YI / 2 * P), 0, c->stream, spec, tw,
-                       (T)(1.0 / (double)c->G), u_out);
+    hipLaunchKernelGGL((k_xi<T, R1, R2, YI>), dim3(NZ * (N / YI)), dim3(3 * YI / 2 * P), 0, c->stream, spec, tw,
+                       (T)(1.0 / (double)c->G), u_out, nz);
   }
   return hipGetLastError();
 }
 
 }  // namespace
 
-bool fluid_reg_supported(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }
+bool fluid_reg_supported(int n, int nz) {
+  return (n == 32 || n == 64 || n == 128 || n == 256) && (nz == n || 2 * nz == n);
+}
 
 template <typename T>
 hipError_t launch_fluid_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect, double f_scale,
                             T *u_out) {
+  const bool half = 2 * c->nz == c->n;
   switch (c->n) {
-    case 32: return run_reg<T, 8, 4>(c, u_in, Fg, fmode, convect, f_scale, u_out);
-    case 64: return run_reg<T, 8, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out);
-    case 128: return run_reg<T, 16, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out);
-    case 256: return run_reg<T, 16, 16>(c, u_in, Fg, fmode, convect, f_scale, u_out);
+    case 32:
+      return half ? run_reg<T, 8, 4, 4, 4>(c, u_in, Fg, fmode, convect, f_scale, u_out)
+                  : run_reg<T, 8, 4, 8, 4>(c, u_in, Fg, fmode, convect, f_scale, u_out);
+    case 64:
+      return half ? run_reg<T, 8, 8, 8, 4>(c, u_in, Fg, fmode, convect, f_scale, u_out)
+                  : run_reg<T, 8, 8, 8, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out);
+    case 128:
+      return half ? run_reg<T, 16, 8, 8, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out)
+                  : run_reg<T, 16, 8, 16, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out);
+    case 256:
+      return half ? run_reg<T, 16, 16, 16, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out)
+                  : run_reg<T, 16, 16, 16, 16>(c, u_in, Fg, fmode, convect, f_scale, u_out);
     default: return hipErrorInvalidValue;
   }
 }

@@ -283,7 +283,7 @@ hipError_t launch_fluid_solve(ib_ctx *c, const T *r, T *u_out) {
 
 template <typename T>
 hipError_t launch_fluid(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect, double f_scale, T *u_out) {
-  if (fluid_reg_supported(c->n)) return launch_fluid_reg<T>(c, u_in, Fg, fmode, convect, f_scale, u_out);
+  if (fluid_reg_supported(c->n, c->nz)) return launch_fluid_reg<T>(c, u_in, Fg, fmode, convect, f_scale, u_out);
   hipError_t e = launch_rhs<T>(c, u_in, Fg, fmode, convect, f_scale, (T *)c->ws.r);
   if (e != hipSuccess) return e;
   return launch_fluid_solve<T>(c, (const T *)c->ws.r, u_out);
@@ -307,17 +307,17 @@ template hipError_t launch_fluid_solve<double>(ib_ctx *, const double *, double 
 // u_k(x) < 0.  One thread per grid point; the result, times dt, goes to tmp.
 template <typename T>
 __global__ __launch_bounds__(256) void k_adv_adjoint(const T *__restrict__ u, const T *__restrict__ r, int n,
-                                                     int log2n, T inv_h, T dt, T *__restrict__ tmp) {
-  const int64_t G = (int64_t)n << (2 * log2n);
+                                                     int nz, int log2n, T inv_h, T dt, T *__restrict__ tmp) {
+  const int64_t G = (int64_t)nz << (2 * log2n);
   const int64_t p = gtid();
   if (p >= G) return;
-  const int mask = n - 1;
+  const int mask = n - 1, maskz = nz - 1;
   const int x = (int)(p & mask), y = (int)((p >> log2n) & mask), z = (int)(p >> (2 * log2n));
   const int64_t zo = (int64_t)z << (2 * log2n), yo = (int64_t)y << log2n;
   const int64_t pm[3] = {zo + yo + ((x - 1) & mask), zo + ((int64_t)((y - 1) & mask) << log2n) + x,
-                         ((int64_t)((z - 1) & mask) << (2 * log2n)) + yo + x};
+                         ((int64_t)((z - 1) & maskz) << (2 * log2n)) + yo + x};
   const int64_t pp[3] = {zo + yo + ((x + 1) & mask), zo + ((int64_t)((y + 1) & mask) << log2n) + x,
-                         ((int64_t)((z + 1) & mask) << (2 * log2n)) + yo + x};
+                         ((int64_t)((z + 1) & maskz) << (2 * log2n)) + yo + x};
 #pragma unroll
   for (int c = 0; c < 3; c++) {
     T acc = T(0);
@@ -351,7 +351,7 @@ template <typename T>
 hipError_t launch_adv_adjoint(ib_ctx *c, const T *u_n, T *ubar, T *tmp) {
   PhaseScope ps(c, PH_ADJ_ADVECT);
   const unsigned g1 = (unsigned)((c->G + 255) / 256), g3 = (unsigned)((3 * c->G + 255) / 256);
-  hipLaunchKernelGGL(k_adv_adjoint<T>, dim3(g1), dim3(256), 0, c->stream, u_n, (const T *)ubar, c->n, c->log2n,
+  hipLaunchKernelGGL(k_adv_adjoint<T>, dim3(g1), dim3(256), 0, c->stream, u_n, (const T *)ubar, c->n, c->nz, c->log2n,
                      (T)(1.0 / c->h), (T)c->p.dt, tmp);
   hipLaunchKernelGGL(k_sub_inplace<T>, dim3(g3), dim3(256), 0, c->stream, ubar, (const T *)tmp, 3 * c->G);
   return hipGetLastError();

@@ -222,7 +222,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_force_rec(Material m, const double *__restrict__ X,
                                                    const int32_t *__restrict__ slot, const double *__restrict__ dir,
                                                    int64_t D, double amp, const int32_t *__restrict__ inv, double h,
-                                                   int n, int log2nt, double *__restrict__ F, Rec<T> *__restrict__ recs) {
+                                                   int n, int nz, int log2nt, double *__restrict__ F,
+                                                   Rec<T> *__restrict__ recs) {
   const int64_t q = (int64_t)xcd_runs<16>(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;   // lattice neighbours on one L2
   const int64_t M = m.M;
   if (q >= M) return;
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(256) void k_force_rec(Material m, const double *__r
     const double fl = floor(s);
     r.f[d] = (T)(s - fl);
     const int64_t ci = isfinite(s) ? (int64_t)fl : 0;
-    cc[d] = (int)(ci & (int64_t)(n - 1));
+    cc[d] = (int)(ci & (int64_t)((d == 2 ? nz : n) - 1));
   }
   r.F[0] = (T)f.x;
   r.F[1] = (T)f.y;
@@ -271,7 +272,7 @@ hipError_t launch_force_rec(ib_ctx *c, const double *X, double amp, double *F) {
   if (c->M == 0) return hipSuccess;
   PhaseScope ps(c, PH_FORCE);
   hipLaunchKernelGGL(k_force_rec<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream, c->mat, X,
-                     c->ws.drive_slot, c->ws.drive_dir, c->n_drive, amp, c->ws.inv, c->h, c->n, c->log2nt, F,
+                     c->ws.drive_slot, c->ws.drive_dir, c->n_drive, amp, c->ws.inv, c->h, c->n, c->nz, c->log2nt, F,
                      (Rec<T> *)c->ws.recs);
   return hipGetLastError();
 }

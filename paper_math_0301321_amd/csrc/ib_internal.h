@@ -39,8 +39,8 @@ struct alignas(16) Rec<double> {
 
 // Cell key (binning of Sec. 3.3): cells are grouped in 8^3 tiles;
 // key = tile * 512 + (lz * 8 + ly) * 8 + lx with l the cell within the tile and
-// tile = (tz * nt + ty) * nt + tx, nt = n / 8.  A tile's markers are one
-// contiguous run of the sorted order.
+// tile = (tz * nt + ty) * nt + tx, nt = n / 8 (tz < nz / 8).  A tile's
+// markers are one contiguous run of the sorted order.
 __host__ __device__ __forceinline__ uint32_t cell_key(int cx, int cy, int cz, int log2nt) {
   const uint32_t tile = ((uint32_t)(cz >> 3) << (2 * log2nt)) | ((uint32_t)(cy >> 3) << log2nt) | (uint32_t)(cx >> 3);
   return (tile << 9) | ((uint32_t)(cz & 7) << 6) | ((uint32_t)(cy & 7) << 3) | (uint32_t)(cx & 7);
@@ -115,10 +115,12 @@ struct Workspace {
   int32_t *scan_tmp;           // [3 ceil(ntiles / 1024)] per-block scan totals
   void *partials;              // [item_cap][kPartStride] each item's spread halo, [3][11^3] + pad
   void *r;                     // [3][G] right-hand side (radix-2 path only; null for n = 32 .. 256)
-  void *spec;                  // [3][n/2+1][n][n] complex spectrum
+  void *spec;                  // [3][n/2+1][nz][n] complex spectrum
   int32_t *nonfinite;          // [1] flag for checked mode
   // tables (fluid precision)
-  void *tw;                    // [n/2] complex exp(-2 pi i k / n)
+  // Along z (nz = n / s, s = 1 or 2) the same tables serve with stride s:
+  // exp(-2 pi i k / nz) = tw[s k], and likewise lam and sgrad.
+  void *tw;                    // [n] complex exp(-2 pi i k / n)
   void *lam;                   // [n] (4/h^2) sin^2(pi m / n)
   void *sgrad;                 // [n] sin(2 pi m / n) / h (exact 0 at m = 0, n/2)
   // drive
@@ -147,7 +149,8 @@ struct TimerRec {
 struct ib_ctx {
   ib_params p;
   int n = 0, log2n = 0;
-  int64_t G = 0, M = 0;
+  int nz = 0, log2nz = 0;   // nodes along z: n (cube) or n / 2 (half-cube)
+  int64_t G = 0, M = 0;     // G = n * n * nz
   double h = 0.0;
   bool fp32 = false;
   bool check = false;
@@ -161,6 +164,7 @@ struct ib_ctx {
   int sort_passes = 0, digit_bits = 0;
   int sorted_buf = 0;   // which keys/vals buffer holds the sorted result
   int log2nt = 0;       // log2(n / 8)
+  int log2ntz = 0;      // log2(nz / 8)
   int64_t ntiles = 0;
   int ncu = 256;        // compute units of the device
   int item_grid = 0;    // most single-wave blocks of the spreading kernel
@@ -196,7 +200,7 @@ template <typename T>
 hipError_t launch_fluid_solve(ib_ctx *c, const T *r, T *u_out);           // FFT, solve, iFFT
 // The whole NS update u_out = Lop(u_in - dt A(u_in) [convect] + f_scale F): register
 // FFT passes for n in {32, 64, 128, 256}, otherwise launch_rhs + launch_fluid_solve.
-bool fluid_reg_supported(int n);
+bool fluid_reg_supported(int n, int nz);
 template <typename T>
 hipError_t launch_fluid_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect, double f_scale,
                             T *u_out);

@@ -78,13 +78,13 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
                                                            const int32_t *__restrict__ counts,
                                                            const int32_t *__restrict__ perm,
                                                            const Rec<T> *__restrict__ recs, const T *__restrict__ u,
-                                                           int n, int log2nt, int64_t M, double dt,
+                                                           int n, int nz, int log2nt, int64_t M, double dt,
                                                            double *__restrict__ X, double *__restrict__ U) {
   __shared__ U4<T> uh[kHalo3];
   const int tid = threadIdx.x;
   const int W = counts[0];
-  const int mask = n - 1, tmask = (1 << log2nt) - 1;
-  const int64_t G = (int64_t)n * n * n;
+  const int mask = n - 1, maskz = nz - 1, tmask = (1 << log2nt) - 1;
+  const int64_t G = (int64_t)n * n * nz;
   constexpr int kPer = (kHalo3 + kInterpThreads - 1) / kInterpThreads;
   // blocks in runs of 16 per XCD: neighbouring items (tiles) share halo rows in its L2
   for (int item = xcd_runs<16>(blockIdx.x, gridDim.x); item < W; item += gridDim.x) {
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
     for (int i = 0; i < kPer; i++) {
       const int e = min(tid + kInterpThreads * i, kHalo3 - 1);
       const int hz = e / (kHalo * kHalo), r = e - hz * (kHalo * kHalo), hy = r / kHalo, hx = r - hy * kHalo;
-      const int64_t p = ((int64_t)((z0 + hz) & mask) * n + ((y0 + hy) & mask)) * n + ((x0 + hx) & mask);
+      const int64_t p = ((int64_t)((z0 + hz) & maskz) * n + ((y0 + hy) & mask)) * n + ((x0 + hx) & mask);
       hv[i][0] = u[p];
       hv[i][1] = u[G + p];
       hv[i][2] = u[2 * G + p];
@@ -184,12 +184,12 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__ keys,
                                                     const int32_t *__restrict__ perm, Rec<T> *__restrict__ recs,
-                                                    const T *__restrict__ u, int n, int log2n, int log2nt, int64_t M,
-                                                    double dt, double inv_h, double *__restrict__ Xbar) {
+                                                    const T *__restrict__ u, int n, int nz, int log2n, int log2nt,
+                                                    int64_t M, double dt, double inv_h, double *__restrict__ Xbar) {
   const int64_t i = gtid();
   if (i >= M) return;
-  const int mask = n - 1;
-  const int64_t G = (int64_t)n << (2 * log2n);
+  const int mask = n - 1, maskz = nz - 1;
+  const int64_t G = (int64_t)nz << (2 * log2n);
   const Cell cc = key_cell(keys[i], log2nt);
   const int64_t q = perm[i];
   const double xb0 = Xbar[q], xb1 = Xbar[M + q], xb2 = Xbar[2 * M + q];
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__
   dphi4<T>(f2, gz);
   T g0 = 0, g1 = 0, g2 = 0;
   for (int c3 = 0; c3 < 4; c3++) {
-    const int64_t zo = (int64_t)((cc.z + c3 - 1) & mask) << (2 * log2n);
+    const int64_t zo = (int64_t)((cc.z + c3 - 1) & maskz) << (2 * log2n);
     for (int c2 = 0; c2 < 4; c2++) {
       const int64_t yo = zo + ((int64_t)((cc.y + c2 - 1) & mask) << log2n);
       for (int c1 = 0; c1 < 4; c1++) {
@@ -232,12 +232,12 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_adj_spread(const uint32_t *__restrict__ keys,
                                                     const int32_t *__restrict__ perm, const Rec<T> *__restrict__ recs,
                                                     const T *__restrict__ ub, const double *__restrict__ F, int n,
-                                                    int log2n, int log2nt, int64_t M, double scale, double inv_h,
+                                                    int nz, int log2n, int log2nt, int64_t M, double scale, double inv_h,
                                                     double *__restrict__ Xbar, double *__restrict__ fbar) {
   const int64_t i = gtid();
   if (i >= M) return;
-  const int mask = n - 1;
-  const int64_t G = (int64_t)n << (2 * log2n);
+  const int mask = n - 1, maskz = nz - 1;
+  const int64_t G = (int64_t)nz << (2 * log2n);
   const Cell cc = key_cell(keys[i], log2nt);
   const int64_t q = perm[i];
   const T f0 = (T)F[q], f1 = (T)F[M + q], f2 = (T)F[2 * M + q];
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(256) void k_adj_spread(const uint32_t *__restrict__
   dphi4<T>(r2, gz);
   T a0 = 0, a1 = 0, a2 = 0, g0 = 0, g1 = 0, g2 = 0;
   for (int c3 = 0; c3 < 4; c3++) {
-    const int64_t zo = (int64_t)((cc.z + c3 - 1) & mask) << (2 * log2n);
+    const int64_t zo = (int64_t)((cc.z + c3 - 1) & maskz) << (2 * log2n);
     for (int c2 = 0; c2 < 4; c2++) {
       const int64_t yo = zo + ((int64_t)((cc.y + c2 - 1) & mask) << log2n);
       for (int c1 = 0; c1 < 4; c1++) {
@@ -287,7 +287,8 @@ hipError_t launch_interp(ib_ctx *c, const T *u, double *X_inout, double *U_out, 
   const int grid = (int)std::min<int64_t>(c->item_cap, (int64_t)c->ncu * 16);
   hipLaunchKernelGGL(k_interp<T>, dim3(grid), dim3(kInterpThreads), 0, c->stream, c->ws.tile_start,
                      c->ws.tile_item0, c->ws.item_tile, c->chunk, c->ws.nitems, c->ws.vals[c->sorted_buf],
-                     (const Rec<T> *)c->ws.recs, u, c->n, c->log2nt, c->M, dt, X_inout, U_out);
+                     (const Rec<T> *)c->ws.recs, u, c->n, c->nz, c->log2nt, c->M, dt, X_inout,
+                     U_out);
   return hipGetLastError();
 }
 
@@ -297,7 +298,7 @@ hipError_t launch_adj_interp(ib_ctx *c, const T *u_np1, double *Xbar) {
   PhaseScope ps(c, PH_ADJ_INTERP);
   hipLaunchKernelGGL(k_adj_interp<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
                      c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (Rec<T> *)c->ws.recs, u_np1, c->n,
-                     c->log2n, c->log2nt, c->M, c->p.dt, 1.0 / c->h, Xbar);
+                     c->nz, c->log2n, c->log2nt, c->M, c->p.dt, 1.0 / c->h, Xbar);
   return hipGetLastError();
 }
 
@@ -308,7 +309,7 @@ hipError_t launch_adj_spread(ib_ctx *c, const T *ubar_n, const double *F, double
   const double scale = (c->p.dt / c->p.rho) / (c->h * c->h * c->h);
   hipLaunchKernelGGL(k_adj_spread<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
                      c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (const Rec<T> *)c->ws.recs, ubar_n, F, c->n,
-                     c->log2n, c->log2nt, c->M, scale, 1.0 / c->h, Xbar, fbar);
+                     c->nz, c->log2n, c->log2nt, c->M, scale, 1.0 / c->h, Xbar, fbar);
   return hipGetLastError();
 }
 

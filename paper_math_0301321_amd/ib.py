@@ -5,9 +5,9 @@ checks tensor shapes, dtypes and devices, passes raw device pointers and
 turns error codes into exceptions.  There is no fallback: if the library is
 not built, importing this module raises.
 
-Tensors: markers (3, M) float64 on the GPU; grid fields (3, N, N, N) in the
+Tensors: markers (3, M) float64 on the GPU; grid fields (3, Nz, N, N) in the
 fluid precision (float32 for ``precision="fp32"``, float64 for ``"fp64"``),
-indexed [component, z, y, x].
+indexed [component, z, y, x] (Nz = N for the cube, N / 2 for the half-cube).
 """
 from __future__ import annotations
 
@@ -35,7 +35,7 @@ class IBError(RuntimeError):
 class ib_params(C.Structure):
     _fields_ = [("n", C.c_int32), ("L", C.c_double), ("rho", C.c_double), ("mu", C.c_double),
                 ("dt", C.c_double), ("fluid_precision", C.c_int32), ("convect", C.c_int32),
-                ("n_markers", C.c_int64), ("stream", C.c_void_p)]
+                ("n_markers", C.c_int64), ("stream", C.c_void_p), ("nz", C.c_int32)]
 
 
 class ib_lattice(C.Structure):
@@ -117,6 +117,7 @@ class Context:
         self.lib = load_library()
         self.wl = wl
         self.N = int(wl.N if N is None else N)
+        self.Nz = int(wl.nz) * self.N // int(wl.N)     # z nodes: N (cube) or N / 2 (half-cube)
         self.M = int(wl.M)
         self.precision = precision
         if precision not in ("fp32", "fp64"):
@@ -142,7 +143,7 @@ class Context:
         self.stream = stream
         p = ib_params(self.N, float(wl.L), float(wl.rho), float(wl.mu), float(wl.dt),
                       IB_FLUID_FP32 if precision == "fp32" else IB_FLUID_FP64, self.convect, self.M,
-                      C.c_void_p(stream))
+                      C.c_void_p(stream), self.Nz)
         e = ib_elastic(_ptr(self.w), _ptr(self.k), _ptr(self.X_ref), _ptr(self.kappa),
                        len(lats), lat_arr,
                        sab.shape[1] if sab.ndim == 2 else 0, sab.ctypes.data_as(C.c_void_p),
@@ -177,11 +178,15 @@ class Context:
             raise ValueError(f"{name} must be a contiguous cuda float64 tensor of shape (3, {self.M})")
         return _ptr(t)
 
+    @property
+    def grid_shape(self) -> tuple:
+        """Shape of a grid field: (3, Nz, N, N), [component, z, y, x]."""
+        return (3, self.Nz, self.N, self.N)
+
     def _grid(self, t, name):
-        N = self.N
         if (t.device.type != "cuda" or t.dtype != self.fluid_dtype or not t.is_contiguous()
-                or tuple(t.shape) != (3, N, N, N)):
-            raise ValueError(f"{name} must be a contiguous cuda {self.fluid_dtype} tensor of shape (3, {N}, {N}, {N})")
+                or tuple(t.shape) != self.grid_shape):
+            raise ValueError(f"{name} must be a contiguous cuda {self.fluid_dtype} tensor of shape {self.grid_shape}")
         return _ptr(t)
 
     @property
@@ -189,7 +194,7 @@ class Context:
         return int(self.lib.ib_workspace_bytes(self._h))
 
     def new_grid(self):
-        return torch.zeros((3, self.N, self.N, self.N), dtype=self.fluid_dtype, device=self.device)
+        return torch.zeros(self.grid_shape, dtype=self.fluid_dtype, device=self.device)
 
     def set_stiffness(self, k: torch.Tensor):
         if k.device.type != "cuda" or k.dtype != torch.float64 or not k.is_contiguous() or k.numel() != self.M:

@@ -1,0 +1,218 @@
+"""GPU parity on the half-cube grid of Sec. 4 (n x n x n/2, box 1 x 1 x 1/2):
+the HIP library through the C-ABI against the FP64 oracle, which is itself
+pinned on this grid by periodic extension to the cube.
+
+Tolerances as for the cube: binning bit-exact; FP64 1e-12 per kernel and
+1e-10 over several steps; FP32 fluid with FP64 markers 2e-6 per kernel and
+1e-5 on velocity and marker displacement over multi-step runs.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_math_0301321_amd import workloads as W
+from tests.gpu_util import announce, dev, host, rel_max
+
+pytestmark = pytest.mark.gpu
+
+TOL1 = {"fp64": 1e-12, "fp32": 2e-6}
+
+
+@pytest.fixture(scope="module")
+def ibm():
+    from paper_math_0301321_amd import ib
+    ib.load_library()
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    return ib
+
+
+def _fd(prec):
+    return torch.float32 if prec == "fp32" else torch.float64
+
+
+def _free_wl(N, X, convect=1):
+    M = X.shape[1]
+    return W.Workload(name="free_half", N=N, L=1.0, rho=1.0, mu=0.01, dt=1e-3, n_steps=1, convect=convect,
+                      X0=X, w=np.ones(M), k=np.ones(M), X_ref=X.copy(), kappa=np.zeros(M), Nz=N // 2)
+
+
+def _markers(N, M, seed):
+    """Random markers over more than one period in every direction (they wrap),
+    a tenth of them exactly on nodes."""
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-0.3, 1.3, size=(3, M))
+    X[2] = rng.uniform(-0.2, 0.7, size=M)
+    on = rng.random(M) < 0.1
+    X[:, on] = np.round(X[:, on] * N) / N
+    return X, rng.standard_normal((3, M))
+
+
+def test_create_rejects_other_shapes(ibm):
+    X = np.zeros((3, 0))
+    for n, nz in ((16, 8), (512, 256), (64, 16), (64, 128), (64, 48)):
+        wl = _free_wl(n, X)
+        wl.Nz = nz
+        with pytest.raises(ibm.IBError) as ei:
+            ibm.Context(wl, "fp32")
+        assert ei.value.code == ibm.IB_ENOTSUP, (n, nz)
+    ctx = ibm.Context(_free_wl(64, X), "fp32")
+    assert ctx.grid_shape == (3, 32, 64, 64)
+
+
+@pytest.mark.parametrize("case", ["rand32", "rand64", "tiny64", "halfcube256"])
+def test_bin_bit_exact(ibm, oracle_mod, case):
+    if case.startswith("rand"):
+        N = int(case[4:])
+        X, _ = _markers(N, 20000, seed=N + 1)
+        wl = _free_wl(N, X)
+    elif case == "tiny64":
+        wl = W.tiny_halfcube(64)
+    else:
+        wl = W.halfcube(256)
+    announce("half-cube bin", case, wl.N, wl.nz, wl.M)
+    ctx = ibm.Context(wl, "fp32")
+    keys, perm = ctx.bin(dev(wl.X0))
+    torch.cuda.synchronize()
+    ok, op = oracle_mod.bin_markers(wl.N, wl.L, wl.X0, Nz=wl.nz)
+    assert np.array_equal(host(keys).astype(np.int64) & 0xFFFFFFFF, ok.astype(np.int64))
+    assert np.array_equal(perm.cpu().numpy(), op)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("N", [32, 64])
+def test_spread_and_interp_parity(ibm, oracle_mod, prec, N):
+    X, F = _markers(N, 3000 if N < 64 else 40000, seed=60 + N)
+    announce("half-cube spread/interp", prec, N)
+    ctx = ibm.Context(_free_wl(N, X), prec)
+    Fg = host(ctx.spread(dev(X), dev(F)))
+    Fo = oracle_mod.spread(N, 1.0, X, F, Nz=N // 2)
+    assert Fg.shape == Fo.shape
+    assert rel_max(Fg, Fo) < TOL1[prec]
+    u = W.random_field(N, seed=61, Nz=N // 2)
+    U = host(ctx.interp(dev(X), dev(u, _fd(prec))))
+    uo = u.astype(np.float32).astype(np.float64) if prec == "fp32" else u
+    assert rel_max(U, oracle_mod.interp(N, 1.0, X, uo)) < TOL1[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("N,convect", [(32, 1), (64, 1), (128, 0), (128, 1)])
+def test_fluid_parity(ibm, oracle_mod, prec, N, convect):
+    u = 0.3 * W.random_field(N, seed=70, Nz=N // 2)
+    F = W.random_field(N, seed=71, Nz=N // 2)
+    if prec == "fp32":
+        u, F = u.astype(np.float32).astype(np.float64), F.astype(np.float32).astype(np.float64)
+    wl = _free_wl(N, np.zeros((3, 0)), convect)
+    announce("half-cube fluid", prec, N, convect)
+    ctx = ibm.Context(wl, prec)
+    ut = dev(u, _fd(prec))
+    ctx.fluid(ut, dev(F, _fd(prec)))
+    uo = oracle_mod.fluid(N, 1.0, wl.rho, wl.mu, wl.dt, convect, u, F)
+    assert rel_max(host(ut), uo) < TOL1[prec]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+@pytest.mark.parametrize("m", [1, 37])
+def test_z_mode_decay_256x256x128(ibm, prec, tol, m):
+    """Closed form at the paper's grid: u_x = sin(2 pi m z / nz), divergence-free,
+    untouched by the advection (u_x does not vary along x, u_z = 0), decays by
+    1 / (1 + nu dt (4/h^2) sin^2(pi m / nz)) in one step (eqs. discreteNS1-2)."""
+    n, nz = 256, 128
+    wl = _free_wl(n, np.zeros((3, 0)))
+    announce("half-cube z mode", prec, m)
+    ctx = ibm.Context(wl, prec)
+    u = ctx.new_grid()
+    z = torch.arange(nz, dtype=torch.float64, device="cuda")
+    u[0] = torch.sin(2.0 * math.pi * m * z / nz).view(nz, 1, 1).to(u.dtype).expand(nz, n, n)
+    u0 = u[0].double().clone()
+    ctx.fluid(u)
+    torch.cuda.synchronize()
+    h = 1.0 / n
+    g = 1.0 / (1.0 + wl.mu / wl.rho * wl.dt * (4.0 / h ** 2) * math.sin(math.pi * m / nz) ** 2)
+    err = (u[0].double() - g * u0).abs().max().item() / (g * u0).abs().max().item()
+    assert err < tol, (prec, m, err)
+    assert u[1].abs().max().item() < tol and u[2].abs().max().item() < tol
+
+
+def _run_gpu(ibm, wl, prec, n_steps):
+    ctx = ibm.Context(wl, prec)
+    X = dev(wl.X0)
+    u = ctx.new_grid()
+    for n in range(n_steps):
+        ctx.step(X, u, n * wl.dt)
+    torch.cuda.synchronize()
+    return host(X), host(u)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("N", [32, 64])
+def test_step_parity_multistep(ibm, oracle_mod, prec, N):
+    wl = W.tiny_halfcube(N)
+    n = wl.n_steps
+    announce("half-cube step", N, prec, n)
+    Xg, ug = _run_gpu(ibm, wl, prec, n)
+    Xo, uo = oracle_mod.run(wl, n)
+    assert ug.shape == uo.shape == (3, N // 2, N, N)
+    eX, eu = rel_max(Xg - wl.X0, Xo - wl.X0), rel_max(ug, uo)
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert eX < tol and eu < tol, (N, prec, eX, eu)
+
+
+def test_full_size_one_step(ibm, oracle_mod):
+    """256 x 256 x 128 grid, 1.5M markers (flat-spiral half-cube model): one step
+    in both precisions against the oracle."""
+    wl = W.halfcube(256)
+    announce("half-cube full-size one step", wl.N, wl.nz, wl.M)
+    Xo, uo = oracle_mod.run(wl, 1)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-5)):
+        Xg, ug = _run_gpu(ibm, wl, prec, 1)
+        eX, eu = rel_max(Xg - wl.X0, Xo - wl.X0), rel_max(ug, uo)
+        assert eX < tol and eu < tol, (prec, eX, eu)
+
+
+@pytest.mark.parametrize("convect", [0, 1])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-4)])
+def test_adjoint_step_parity(ibm, oracle_mod, prec, tol, convect):
+    wl = W.tiny_halfcube(32)
+    wl.convect = convect
+    rng = np.random.default_rng(80)
+    X = wl.X0 + 2e-3 * rng.standard_normal(wl.X0.shape)
+    u = 0.05 * W.random_field(32, seed=81, Nz=16)
+    if prec == "fp32":
+        u = u.astype(np.float32).astype(np.float64)
+    t = 3e-4
+    m = oracle_mod.Model(wl)
+    _, u1 = oracle_mod.step(m, wl, X, u, t, convect=convect)
+    Xb1 = rng.standard_normal(X.shape)
+    ub1 = rng.standard_normal(u.shape)
+    if prec == "fp32":
+        u1 = u1.astype(np.float32).astype(np.float64)
+        ub1 = ub1.astype(np.float32).astype(np.float64)
+    Xbo, ubo, kbo = oracle_mod.adjoint_step(m, wl, X, u1, t, Xb1, ub1, np.zeros(wl.M), convect=convect, u_n=u)
+    announce("half-cube adjoint", prec, "convect", convect)
+    ctx = ibm.Context(wl, prec, convect=convect)
+    fd = _fd(prec)
+    Xb, ub, kb = dev(Xb1), dev(ub1, fd), torch.zeros(wl.M, dtype=torch.float64, device="cuda")
+    ctx.adjoint_step(dev(X), dev(u1, fd), t, Xb, ub, kb, u_n=dev(u, fd) if convect else None)
+    torch.cuda.synchronize()
+    assert rel_max(host(Xb) - Xb1, Xbo - Xb1) < tol
+    assert rel_max(host(ub), ubo) < tol
+    assert rel_max(host(kb), kbo) < tol
+
+
+def test_mixed_velocity_error_after_100_steps(ibm, oracle_mod):
+    """The per-field bound on the half-cube: 100 steps (advection on) of the
+    64 x 64 x 32 replica of the 1.5M-marker half-cube model; the mixed step
+    within 1e-5 of the FP64 oracle, the FP64 step within 1e-9."""
+    wl = W.halfcube(256).with_grid(64)
+    assert (wl.N, wl.nz) == (64, 32)
+    n = 100
+    announce("half-cube 100-step error", wl.N, wl.nz, wl.M)
+    Xo, uo = oracle_mod.run(wl, n)
+    for prec, tol in (("fp64", 1e-9), ("fp32", 1e-5)):
+        Xg, ug = _run_gpu(ibm, wl, prec, n)
+        eX, eu = rel_max(Xg - wl.X0, Xo - wl.X0), rel_max(ug, uo)
+        print(f"[gpu-case] half-cube 100 steps {prec}: rel u {eu:.3e}, rel dX {eX:.3e}", flush=True)
+        assert eu <= tol and eX <= tol, (prec, eu, eX)
