@@ -153,8 +153,10 @@ def run_gpu(wl, precision, steps, warmup, timed_phases=(), every=1):
 
 def extras(wl, n=10):
     """Rates beside the headline (not part of it): the adjoint step with the upwind
-    advection on the same workload (mixed precision), and the 128^3 window-model
-    workload stepping with the membrane's centre line recorded every 10th step."""
+    advection on the same workload (mixed precision), the 128^3 window-model
+    workload stepping with the membrane's centre line recorded every 10th step,
+    and the half-cube model (256 x 256 x 128 grid, flat membrane, 1.5M markers)
+    stepping in mixed precision and in FP64."""
     import torch
     from paper_math_0301321_amd import ib, workloads as W, diagnostics as D
     out = {}
@@ -190,6 +192,26 @@ def extras(wl, n=10):
     torch.cuda.synchronize()
     out["window128_steps_per_s"] = round(50 / (e0.elapsed_time(e1) / 1e3), 2)
     out["window128_markers"] = wlw.M
+    del cw, uw
+    # the half-cube model (256 x 256 x 128, the grid of the paper's reported runs)
+    wlh = W.halfcube(256)
+    for prec in ("fp32", "fp64"):
+        ch = ib.Context(wlh, prec)
+        Xh = torch.as_tensor(wlh.X0, dtype=torch.float64, device="cuda").contiguous()
+        uh = ch.new_grid()
+        for k in range(5):
+            ch.step(Xh, uh, k * wlh.dt)
+        torch.cuda.synchronize()
+        e0.record()
+        for k in range(5, 55):
+            ch.step(Xh, uh, k * wlh.dt)
+        e1.record()
+        torch.cuda.synchronize()
+        key = "halfcube256_mixed_steps_per_s" if prec == "fp32" else "halfcube256_fp64_steps_per_s"
+        out[key] = round(50 / (e0.elapsed_time(e1) / 1e3), 2)
+        del ch, uh
+    out["halfcube256_grid"] = [wlh.N, wlh.N, wlh.nz]
+    out["halfcube256_markers"] = wlh.M
     return out
 
 
@@ -198,7 +220,7 @@ def cpu_baseline(wl, sample_steps: int):
     import oracle
     model = oracle.Model(wl)
     X = wl.X0.copy()
-    u = np.zeros((3, wl.N, wl.N, wl.N))
+    u = np.zeros(wl.grid_shape)
     t0 = time.perf_counter()
     for n in range(sample_steps):
         X, u = oracle.step(model, wl, X, u, n * wl.dt)
