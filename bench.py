@@ -45,18 +45,20 @@ def worklist_sizes(wl, ncu=256):
     force reaches, the tiles cut into several items with their items, and the markers of
     lattices with stretch or bend moduli."""
     import numpy as np
-    n, nt = wl.N, wl.N // 8
-    c = np.floor(wl.X0 / wl.h).astype(np.int64) & (n - 1)
+    n, nt, ntz = wl.N, wl.N // 8, wl.nz // 8
+    c = np.floor(wl.X0 / wl.h).astype(np.int64)
+    c[:2] &= n - 1
+    c[2] &= wl.nz - 1
     t = c // 8
     tile = (t[2] * nt + t[1]) * nt + t[0]
-    K = np.bincount(tile, minlength=nt ** 3)
+    K = np.bincount(tile, minlength=nt * nt * ntz)
     te = np.cumsum(K)
     ts = te - K
     chunk = max(256, -(-wl.M // (8 * ncu)))
     nit = np.where(K > 0, (te - 1) // chunk - ts // chunk + 1, 0)
     items = int(nit.sum())
     split_items = int(nit[nit > 1].sum())
-    occ = (K > 0).reshape(nt, nt, nt)
+    occ = (K > 0).reshape(ntz, nt, nt)
     touched = np.zeros_like(occ)
     for dz in (-1, 0, 1):
         for dy in (-1, 0, 1):
@@ -68,11 +70,13 @@ def worklist_sizes(wl, ncu=256):
             "lattice_markers": int(lat)}
 
 
-def phase_bytes(phase, N, M, b, wls):
-    """Algorithmic HBM bytes per launch of each single-kernel phase (fluid precision b bytes):
-    every input read once and every output written once, at the sizes of the design notes."""
-    G = N ** 3
-    spec = 3 * (N // 2 + 1) * N * N * 2 * b       # half spectrum, 3 components
+def phase_bytes(phase, N, M, b, wls, Nz=None):
+    """Algorithmic HBM bytes per launch of each single-kernel phase (fluid precision b bytes)
+    on an N x N x Nz grid (Nz = N by default): every input read once and every output
+    written once, at the sizes of the design notes."""
+    Nz = N if Nz is None else Nz
+    G = N * N * Nz
+    spec = 3 * (N // 2 + 1) * N * Nz * 2 * b      # half spectrum, 3 components
     grid = 3 * G * b
     rec = 32 if b == 4 else 64                    # sorted marker record
     halo = 3 * 11 ** 3 * b                        # one work item's spread halo
@@ -226,7 +230,8 @@ def cpu_baseline(wl, sample_steps: int):
         X, u = oracle.step(model, wl, X, u, n * wl.dt)
     dt = time.perf_counter() - t0
     return {"value": sample_steps / dt, "unit": "steps/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{sample_steps} full FP64 oracle step(s) of {wl.name} ({wl.N}^3 grid, {wl.M} markers), "
+            "sample": f"{sample_steps} full FP64 oracle step(s) of {wl.name} ({wl.N}x{wl.N}x{wl.nz} grid, "
+                      f"{wl.M} markers), "
                       f"{dt:.1f} s wall"}
 
 
@@ -237,6 +242,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--fp64-steps", type=int, default=None, help="steps of the FP64 comparison run (default: --steps)")
     ap.add_argument("--grid", type=int, default=256)
+    ap.add_argument("--workload", choices=("helix", "halfcube"), default="helix",
+                    help="helix: the helicoid in a coiled tube on the n^3 cube (default); halfcube: the "
+                         "flat-membrane half-cube model on n x n x n/2")
     ap.add_argument("--cpu-sample-steps", type=int, default=8,
                     help="oracle steps timed on the host (one step of the default workload takes ~2 s on 16 cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -255,8 +263,8 @@ def main():
     import torch
     from paper_math_0301321_amd import workloads as W
 
-    wl = W.config3(N=args.grid)
-    print(f"[bench] workload {wl.name}: N={wl.N} M={wl.M}", file=sys.stderr, flush=True)
+    wl = W.config3(N=args.grid) if args.workload == "helix" else W.halfcube(N=args.grid)
+    print(f"[bench] workload {wl.name}: grid {wl.N}x{wl.N}x{wl.nz} M={wl.M}", file=sys.stderr, flush=True)
     wls = worklist_sizes(wl, torch.cuda.get_device_properties(0).multi_processor_count)
     # 1) phase breakdown (every phase timed; not the headline number)
     if args.calibrate_copy:
@@ -284,14 +292,14 @@ def main():
           file=sys.stderr, flush=True)
     tot, calls = mixed["phases"][dom]
     avg_ms = tot / calls
-    nbytes = phase_bytes(dom, wl.N, wl.M, 4, wls)
+    nbytes = phase_bytes(dom, wl.N, wl.M, 4, wls, wl.nz)
     ach = nbytes / (avg_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": SINGLE_KERNEL[dom], "phase": dom, "achieved": round(ach, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
             "traffic": traffic_for(SINGLE_KERNEL[dom], wl.name),
             "bytes_per_launch": nbytes, "avg_ms": round(avg_ms, 5), "launches": calls}
     brk_steps = max(5, args.steps // 5)
-    step_bytes = sum(phase_bytes(k, wl.N, wl.M, 4, wls) * v[1]
+    step_bytes = sum(phase_bytes(k, wl.N, wl.M, 4, wls, wl.nz) * v[1]
                      for k, v in ph.items() if k in SINGLE_KERNEL) / brk_steps
 
     extra = {}
@@ -309,7 +317,7 @@ def main():
             extra["mixed_vs_fp64_rel_dX"] = float((dXm - dX64).abs().max() / dX64.abs().max())
         print(f"[bench] fp64: {v64:.1f} steps/s", file=sys.stderr, flush=True)
 
-    if not args.no_extras:
+    if not args.no_extras and args.workload == "helix":
         extra.update(extras(wl))
 
     cpu = None
@@ -317,13 +325,20 @@ def main():
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         cpu = cpu_baseline(wl, args.cpu_sample_steps)
 
+    if args.workload == "helix":
+        metric = "IB steps/s at 256^3 grid + 1.5M markers; mixed vs FP64 at stated error"
+        shape = f"{wl.N}^3 periodic grid"
+    else:
+        metric = f"IB steps/s at {wl.N}x{wl.N}x{wl.nz} half-cube grid + {wl.M} markers (flat membrane)"
+        shape = f"{wl.N}x{wl.N}x{wl.nz} periodic half-cube grid"
     out = {
-        "metric": "IB steps/s at 256^3 grid + 1.5M markers; mixed vs FP64 at stated error",
+        "metric": metric,
         "value": round(value, 2), "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {wl.N}^3 periodic grid, {wl.M} markers (BM 1200x500 + wall 1800x500), "
-                               f"dt {wl.dt}, {wl.drive_freq:g} Hz drive", "grid": wl.N, "markers": wl.M,
+        "config": {"workload": f"{wl.name}: {shape}, {wl.M} markers (BM 1200x500 + wall 1800x500), "
+                               f"dt {wl.dt}, {wl.drive_freq:g} Hz drive",
+                   "grid": wl.N if wl.nz == wl.N else [wl.N, wl.N, wl.nz], "markers": wl.M,
                    "precision": "FP32 fluid, FP64 markers and forces", "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
