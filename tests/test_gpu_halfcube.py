@@ -216,3 +216,29 @@ def test_mixed_velocity_error_after_100_steps(ibm, oracle_mod):
         eX, eu = rel_max(Xg - wl.X0, Xo - wl.X0), rel_max(ug, uo)
         print(f"[gpu-case] half-cube 100 steps {prec}: rel u {eu:.3e}, rel dX {eX:.3e}", flush=True)
         assert eu <= tol and eX <= tol, (prec, eu, eX)
+
+
+@pytest.mark.parametrize("convect", [0, 1])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_rollout_gradient_matches_oracle(ibm, oracle_mod, prec, tol, convect):
+    """The checkpointed autograd rollout on the half-cube: the stiffness gradient
+    of the membrane loss against the oracle's reverse-mode gradient (markers
+    displaced by 2e-3 so that the strains, and the gradient, are well resolved)."""
+    from paper_math_0301321_amd import rollout
+    wl = W.tiny_halfcube(32)
+    wl.convect = convect
+    rng = np.random.default_rng(90)
+    wl.X0 = wl.X0 + 2e-3 * rng.standard_normal(wl.X0.shape)
+    idx = W.bm_index(wl, np.arange(30), 3)
+    announce("half-cube rollout", prec, "convect", convect)
+    Lo, kbo, _, _ = oracle_mod.gradient_k(wl, 7, idx, convect=convect)
+    ctx = ibm.Context(wl, prec, convect=convect)
+    kt = dev(wl.k).requires_grad_(True)
+    X0 = dev(wl.X0)
+    XT, _ = rollout.rollout(kt, X0, ctx.new_grid(), ctx, 7, 3)        # segments 3, 3, 1
+    L = rollout.membrane_loss(XT, X0, torch.as_tensor(idx, device="cuda"))
+    L.backward()
+    torch.cuda.synchronize()
+    kb = host(kt.grad)
+    assert abs(float(L) - Lo) <= (2e-5 if prec == "fp32" else 1e-12) * Lo, (float(L), Lo)
+    assert np.linalg.norm(kb - kbo) / np.linalg.norm(kbo) < tol
