@@ -255,7 +255,7 @@ def main():
                     help="first run one plain 256 MiB device copy (reference kernel for traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: this program runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU decomposition is design only)", file=sys.stderr)
         sys.exit(2)
 

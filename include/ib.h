@@ -43,7 +43,7 @@ enum {
   IB_EINVAL = -1,      /* bad argument (size, pointer, parameter out of range)   */
   IB_ENOMEM = -2,      /* device allocation failed                                */
   IB_EDEVICE = -3,     /* HIP runtime / kernel launch error                       */
-  IB_ENOTSUP = -4,     /* valid request outside what this build supports          */
+  IB_ENOTSUP = -4,     /* valid request outside what this library supports        */
   IB_ENONFINITE = -5   /* IB_CHECK=1 found a NaN or Inf in an output              */
 };
 

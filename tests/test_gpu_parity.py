@@ -5,7 +5,7 @@ Tolerances (relative max-norm per field, max|gpu - oracle| / max|oracle|):
   * FP64 fluid: 1e-12 for one kernel / step, 1e-10 after 10 steps -- only the
     summation order differs from the oracle;
   * FP32 fluid (FP64 markers): 2e-6 for one spread / interp / fluid solve
-    (a few FP32 ulps times the log2(n) FFT stages), and the benchmark spec's bound
+    (a few FP32 ulps times the log2(n) FFT stages), and the stated bound
     1e-5 on velocity and marker displacement over multi-step runs.
 Markers are compared by displacement X - X0, since X itself is O(1).
 """
