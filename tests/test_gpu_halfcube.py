@@ -136,6 +136,18 @@ def test_z_mode_decay_256x256x128(ibm, prec, tol, m):
     assert u[1].abs().max().item() < tol and u[2].abs().max().item() < tol
 
 
+def test_step_without_markers(ibm, oracle_mod):
+    """A half-cube fluid with no markers: the step is the Navier-Stokes update alone."""
+    wl = _free_wl(32, np.zeros((3, 0)))
+    announce("half-cube step, no markers")
+    ctx = ibm.Context(wl, "fp64")
+    u0 = 0.2 * W.random_field(32, seed=95, Nz=16)
+    ut = dev(u0)
+    ctx.step(dev(np.zeros((3, 0))), ut, 0.0)
+    torch.cuda.synchronize()
+    assert rel_max(host(ut), oracle_mod.fluid(32, 1.0, 1.0, 0.01, 1e-3, 1, u0)) < 1e-12
+
+
 def _run_gpu(ibm, wl, prec, n_steps):
     ctx = ibm.Context(wl, prec)
     X = dev(wl.X0)
