@@ -162,3 +162,23 @@ def test_bench_byte_model_covers_every_timed_kernel():
         v = bench.phase_bytes(phase, wl.N, wl.M, 4, wls)
         assert v is not None and (v > 0 or (phase == "split" and wls["split_tiles"] == 0)), phase
         assert kernel in bench.KERNEL_SOURCE
+
+
+def test_bench_byte_model_on_the_half_cube():
+    """The byte model and work-list sizes on an n x n x n/2 grid: the grid and
+    spectrum terms are half the cube's, and the binning sees the tiles of the
+    half-height box."""
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(os.path.dirname(__file__), "..", "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    from paper_math_0301321_amd import workloads as W
+    wl = W.tiny_halfcube(32)
+    wls = bench.worklist_sizes(wl)
+    assert wls["tiles_touched"] <= (32 // 8) ** 2 * (16 // 8)
+    n, nz, b = 32, 16, 4
+    G, spec_b = n * n * nz, 3 * (n // 2 + 1) * n * nz * 2 * b
+    assert bench.phase_bytes("fft_y", n, wl.M, b, wls, nz) == 2 * spec_b
+    assert bench.phase_bytes("fft_x_inv", n, wl.M, b, wls, nz) == spec_b + 3 * G * b
+    assert bench.phase_bytes("fft_x_inv", n, wl.M, b, wls, nz) * 2 == bench.phase_bytes("fft_x_inv", n, wl.M, b, wls)
