@@ -82,8 +82,8 @@ def phase_bytes(phase, N, M, b, wls, Nz=None):
     halo = 3 * 11 ** 3 * b                        # one work item's spread halo
     items, touched = wls["items"], wls["tiles_touched"]
     return {
-        # X, w, k, X_ref, kappa, inv, drive slot; record; 6 lattice constants of each lattice marker
-        "force": M * (24 + 8 + 8 + 24 + 8 + 4 + 4 + rec) + 48 * wls.get("lattice_markers", 0),
+        # X, w, k, X_ref, kappa, inv, drive slot; record; 12 lattice constants of each lattice marker
+        "force": M * (24 + 8 + 8 + 24 + 8 + 4 + 4 + rec) + 96 * wls.get("lattice_markers", 0),
         "spread": M * rec + items * halo,                       # records in, item halos out
         "split": wls["split_items"] * halo + wls["split_tiles"] * halo,   # split tiles' halos in, sums out
         "gather": items * halo + touched * 512 * 3 * b,         # halos in, touched tiles out

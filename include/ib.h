@@ -82,7 +82,8 @@ typedef struct {
  * with kbar, wbar the means over the edge's two markers and Y = X_ref.
  * w, k, X_ref, kappa are DEVICE arrays read at every call (the caller may
  * change their contents between calls; ib_set_material swaps pointers),
- * except that the lattice rest lengths |Yb-Ya|, Lc and the factors wbar, w_c
+ * except that the lattice rest lengths |Yb-Ya|, Lc, the reference second
+ * differences Ya - 2Yc + Yb and the factors wbar, w_c
  * are derived from X_ref and w once, at ib_create and at every
  * ib_set_material that passes w or X_ref: after changing the contents of
  * either in place, call ib_set_material with it again.

@@ -365,7 +365,7 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
     bool moduli = false;
     for (int l = 0; l < e->n_lattices; l++) moduli = moduli || e->lattices[l].Ks != 0.0 || e->lattices[l].Kb != 0.0;
     if (moduli && M > 0) {
-      chk_alloc(dalloc(c, &w.lat_pre, 6 * M));
+      chk_alloc(dalloc(c, &w.lat_pre, (int64_t)kLatPre * M));
       mt.lat_pre = w.lat_pre;
       if (err == hipSuccess) err = launch_lattice_pre(c);
       if (err == hipSuccess) err = hipStreamSynchronize(c->stream);

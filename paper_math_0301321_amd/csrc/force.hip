@@ -22,12 +22,14 @@ __device__ __forceinline__ V3 ld3(const double *__restrict__ A, int64_t M, int64
 }
 __device__ __forceinline__ double nrm(const V3 &a) { return sqrt(a.x * a.x + a.y * a.y + a.z * a.z); }
 
-// Reference-shape constants of a lattice marker q = (i1, i2), [6][M]:
+// Reference-shape constants of a lattice marker q = (i1, i2), [12][M]:
 //   0, 1: rest length Le of the edge (q, q + 1 along index 1) and Ks w / Le^2
 //         (w the mean of the two endpoint weights);
 //   2, 3: the same for the edge to the next row (index 2, wrapping when periodic);
 //   4, 5: Kb w_q / Lc^4 of the bend triples centred at q along index 1 and 2
 //         (Lc the mean rest length of the triple's two edges);
+//   6 .. 8, 9 .. 11: the reference second difference Y_a - 2 Y_q + Y_b of
+//         those two triples (x, y, z);
 // zero where the edge or triple does not exist.  They depend only on X_ref and
 // w, so they are computed when those are set; the stiffness multipliers k are
 // applied at run time.
@@ -35,7 +37,7 @@ __global__ __launch_bounds__(256) void k_lattice_pre(Material m, double *__restr
   const int64_t q = gtid();
   const int64_t M = m.M;
   if (q >= M) return;
-  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double v[kLatPre] = {};
   for (int l = 0; l < m.lat.n; l++) {
     const LatticeDev &L = m.lat.l[l];
     if (q < L.first || q >= L.first + (int64_t)L.n1 * L.n2) continue;
@@ -51,10 +53,13 @@ __global__ __launch_bounds__(256) void k_lattice_pre(Material m, double *__restr
       le = nrm(dy);
       ke = L.Ks * (0.5 * (m.w[q] + m.w[o])) / (le * le);
     };
-    auto bend = [&](int64_t a, int64_t b) {
+    auto bend = [&](int64_t a, int64_t b, double *d2) {
       const V3 ya = ld3(m.X_ref, M, a), yb = ld3(m.X_ref, M, b);
       const V3 e1{yq.x - ya.x, yq.y - ya.y, yq.z - ya.z}, e2{yb.x - yq.x, yb.y - yq.y, yb.z - yq.z};
       const double Lc = 0.5 * (nrm(e1) + nrm(e2));
+      d2[0] = ya.x - 2.0 * yq.x + yb.x;
+      d2[1] = ya.y - 2.0 * yq.y + yb.y;
+      d2[2] = ya.z - 2.0 * yq.z + yb.z;
       return L.Kb * m.w[q] / (Lc * Lc * Lc * Lc);
     };
     if (L.Ks != 0.0) {
@@ -62,12 +67,12 @@ __global__ __launch_bounds__(256) void k_lattice_pre(Material m, double *__restr
       if (per || i2 < n2 - 1) edge(idx(i1, w2(i2 + 1)), v[2], v[3]);
     }
     if (L.Kb != 0.0) {
-      if (i1 >= 1 && i1 <= n1 - 2) v[4] = bend(idx(i1 - 1, i2), idx(i1 + 1, i2));
-      if (per || (i2 >= 1 && i2 <= n2 - 2)) v[5] = bend(idx(i1, w2(i2 - 1)), idx(i1, w2(i2 + 1)));
+      if (i1 >= 1 && i1 <= n1 - 2) v[4] = bend(idx(i1 - 1, i2), idx(i1 + 1, i2), v + 6);
+      if (per || (i2 >= 1 && i2 <= n2 - 2)) v[5] = bend(idx(i1, w2(i2 - 1)), idx(i1, w2(i2 + 1)), v + 9);
     }
     break;
   }
-  for (int j = 0; j < 6; j++) pre[j * M + q] = v[j];
+  for (int j = 0; j < kLatPre; j++) pre[j * M + q] = v[j];
 }
 
 // Force on marker q from the stretch edge (q, o) with rest length le and
@@ -84,16 +89,17 @@ __device__ __forceinline__ void stretch_on(const Material &m, const double *__re
   f.z += s * d.z;
 }
 
-// Force on marker q from the bend triple (a, c, b) with cb = Kb w_c / Lc^4;
+// Force on marker q from the bend triple (a, c, b) with cb = Kb w_c / Lc^4 and
+// d2 (3 strided values) the reference second difference Y_a - 2 Y_c + Y_b;
 // role: 0 = end, 1 = centre.
 __device__ __forceinline__ void bend_on(const Material &m, const double *__restrict__ X, int64_t a,
-                                        int64_t c, int64_t b, int role, double cb, V3 &f) {
+                                        int64_t c, int64_t b, int role, double cb, const double *__restrict__ d2,
+                                        V3 &f) {
   const int64_t M = m.M;
   const V3 xa = ld3(X, M, a), xb = ld3(X, M, b), xc = ld3(X, M, c);
-  const V3 ya = ld3(m.X_ref, M, a), yb = ld3(m.X_ref, M, b), yc = ld3(m.X_ref, M, c);
-  const V3 v{(xa.x - 2.0 * xc.x + xb.x) - (ya.x - 2.0 * yc.x + yb.x),
-             (xa.y - 2.0 * xc.y + xb.y) - (ya.y - 2.0 * yc.y + yb.y),
-             (xa.z - 2.0 * xc.z + xb.z) - (ya.z - 2.0 * yc.z + yb.z)};
+  const V3 y2 = ld3(d2, M, c);
+  const V3 v{(xa.x - 2.0 * xc.x + xb.x) - y2.x, (xa.y - 2.0 * xc.y + xb.y) - y2.y,
+             (xa.z - 2.0 * xc.z + xb.z) - y2.z};
   const double K = cb * m.k[c];
   const double s = role ? 2.0 * K : -K;
   f.x += s * v.x;
@@ -125,27 +131,27 @@ __device__ void lattice_force(const Material &m, const LatticeDev &L, const doub
     if (has_up) stretch_on(m, X, q, idx(i1, w2(i2 + 1)), xq, P[2 * M + q], P[3 * M + q], f);
   }
   if (L.Kb != 0.0) {
-    const double *C1 = P + 4 * M, *C2 = P + 5 * M;
+    const double *C1 = P + 4 * M, *C2 = P + 5 * M, *D1 = P + 6 * M, *D2 = P + 9 * M;
     // direction 1: centres 1 .. n1-2
-    if (i1 >= 1 && i1 <= n1 - 2) bend_on(m, X, idx(i1 - 1, i2), q, idx(i1 + 1, i2), 1, C1[q], f);
+    if (i1 >= 1 && i1 <= n1 - 2) bend_on(m, X, idx(i1 - 1, i2), q, idx(i1 + 1, i2), 1, C1[q], D1, f);
     if (i1 + 1 <= n1 - 2) {
       const int64_t c = idx(i1 + 1, i2);
-      bend_on(m, X, q, c, idx(i1 + 2, i2), 0, C1[c], f);
+      bend_on(m, X, q, c, idx(i1 + 2, i2), 0, C1[c], D1, f);
     }
     if (i1 - 1 >= 1) {
       const int64_t c = idx(i1 - 1, i2);
-      bend_on(m, X, idx(i1 - 2, i2), c, q, 0, C1[c], f);
+      bend_on(m, X, idx(i1 - 2, i2), c, q, 0, C1[c], D1, f);
     }
     // direction 2: centres 1 .. n2-2, or every row when periodic
     auto centre_ok = [&](int64_t c2) { return per || (c2 >= 1 && c2 <= n2 - 2); };
-    if (centre_ok(i2)) bend_on(m, X, idx(i1, w2(i2 - 1)), q, idx(i1, w2(i2 + 1)), 1, C2[q], f);
+    if (centre_ok(i2)) bend_on(m, X, idx(i1, w2(i2 - 1)), q, idx(i1, w2(i2 + 1)), 1, C2[q], D2, f);
     if ((per || i2 + 1 < n2) && centre_ok(i2 + 1)) {
       const int64_t c = idx(i1, w2(i2 + 1));
-      bend_on(m, X, q, c, idx(i1, w2(i2 + 2)), 0, C2[c], f);
+      bend_on(m, X, q, c, idx(i1, w2(i2 + 2)), 0, C2[c], D2, f);
     }
     if ((per || i2 - 1 >= 0) && centre_ok(i2 - 1)) {
       const int64_t c = idx(i1, w2(i2 - 1));
-      bend_on(m, X, idx(i1, w2(i2 - 2)), c, q, 0, C2[c], f);
+      bend_on(m, X, idx(i1, w2(i2 - 2)), c, q, 0, C2[c], D2, f);
     }
   }
 }

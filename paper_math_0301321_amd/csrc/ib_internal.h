@@ -12,6 +12,7 @@
 namespace ib {
 
 constexpr int kMaxLattices = 16;
+constexpr int kLatPre = 12;       // reference-shape constants per lattice marker (see k_lattice_pre)
 constexpr int kTile = 8;          // cells per tile edge: markers are binned by 8^3-cell tiles
 constexpr int kHalo = 11;         // nodes per edge of a tile's stencil halo (cells -1 .. 9)
 constexpr int kHalo3 = kHalo * kHalo * kHalo;
@@ -84,7 +85,7 @@ struct Material {
   const double *sp_rest;      // [2S]
   double K_spring;
   int64_t M;
-  // reference-shape constants of the lattices, [6][M] (see k_lattice_pre), or null
+  // reference-shape constants of the lattices, [kLatPre][M] (see k_lattice_pre), or null
   const double *lat_pre;
 };
 
@@ -130,7 +131,7 @@ struct Workspace {
   // spring adjacency
   int32_t *sp_rowptr, *sp_col;
   double *sp_rest;
-  double *lat_pre;             // [6][M] lattice reference constants (null without lattice moduli)
+  double *lat_pre;             // [kLatPre][M] lattice reference constants (null without lattice moduli)
 };
 
 // Phases timed by the optional HIP-event instrumentation.
