@@ -89,14 +89,12 @@ __device__ __forceinline__ void stretch_on(const Material &m, const double *__re
   f.z += s * d.z;
 }
 
-// Force on marker q from the bend triple (a, c, b) with cb = Kb w_c / Lc^4 and
-// d2 (3 strided values) the reference second difference Y_a - 2 Y_c + Y_b;
-// role: 0 = end, 1 = centre.
-__device__ __forceinline__ void bend_on(const Material &m, const double *__restrict__ X, int64_t a,
-                                        int64_t c, int64_t b, int role, double cb, const double *__restrict__ d2,
-                                        V3 &f) {
+// Force on marker q from the bend triple with positions xa, xc (centre c), xb,
+// cb = Kb w_c / Lc^4 and d2 (3 strided values) the reference second
+// difference Y_a - 2 Y_c + Y_b; role: 0 = end, 1 = centre.
+__device__ __forceinline__ void bend_on(const Material &m, const V3 &xa, const V3 &xc, const V3 &xb, int64_t c,
+                                        int role, double cb, const double *__restrict__ d2, V3 &f) {
   const int64_t M = m.M;
-  const V3 xa = ld3(X, M, a), xb = ld3(X, M, b), xc = ld3(X, M, c);
   const V3 y2 = ld3(d2, M, c);
   const V3 v{(xa.x - 2.0 * xc.x + xb.x) - y2.x, (xa.y - 2.0 * xc.y + xb.y) - y2.y,
              (xa.z - 2.0 * xc.z + xb.z) - y2.z};
@@ -132,26 +130,36 @@ __device__ void lattice_force(const Material &m, const LatticeDev &L, const doub
   }
   if (L.Kb != 0.0) {
     const double *C1 = P + 4 * M, *C2 = P + 5 * M, *D1 = P + 6 * M, *D2 = P + 9 * M;
+    // Along each direction the triples containing q are centred at q, at its
+    // successor and at its predecessor (in that order); they need the
+    // positions at offsets -2 .. 2, each read once.
     // direction 1: centres 1 .. n1-2
-    if (i1 >= 1 && i1 <= n1 - 2) bend_on(m, X, idx(i1 - 1, i2), q, idx(i1 + 1, i2), 1, C1[q], D1, f);
-    if (i1 + 1 <= n1 - 2) {
-      const int64_t c = idx(i1 + 1, i2);
-      bend_on(m, X, q, c, idx(i1 + 2, i2), 0, C1[c], D1, f);
-    }
-    if (i1 - 1 >= 1) {
-      const int64_t c = idx(i1 - 1, i2);
-      bend_on(m, X, idx(i1 - 2, i2), c, q, 0, C1[c], D1, f);
+    {
+      const bool b0 = i1 >= 1 && i1 <= n1 - 2, bp = i1 + 1 <= n1 - 2, bm = i1 - 1 >= 1;
+      const int64_t qm = idx(i1 - 1, i2), qp = idx(i1 + 1, i2);
+      V3 xm{}, xp{}, xm2{}, xp2{};
+      if (b0 || bm) xm = ld3(X, M, qm);
+      if (b0 || bp) xp = ld3(X, M, qp);
+      if (bm) xm2 = ld3(X, M, idx(i1 - 2, i2));
+      if (bp) xp2 = ld3(X, M, idx(i1 + 2, i2));
+      if (b0) bend_on(m, xm, xq, xp, q, 1, C1[q], D1, f);
+      if (bp) bend_on(m, xq, xp, xp2, qp, 0, C1[qp], D1, f);
+      if (bm) bend_on(m, xm2, xm, xq, qm, 0, C1[qm], D1, f);
     }
     // direction 2: centres 1 .. n2-2, or every row when periodic
-    auto centre_ok = [&](int64_t c2) { return per || (c2 >= 1 && c2 <= n2 - 2); };
-    if (centre_ok(i2)) bend_on(m, X, idx(i1, w2(i2 - 1)), q, idx(i1, w2(i2 + 1)), 1, C2[q], D2, f);
-    if ((per || i2 + 1 < n2) && centre_ok(i2 + 1)) {
-      const int64_t c = idx(i1, w2(i2 + 1));
-      bend_on(m, X, q, c, idx(i1, w2(i2 + 2)), 0, C2[c], D2, f);
-    }
-    if ((per || i2 - 1 >= 0) && centre_ok(i2 - 1)) {
-      const int64_t c = idx(i1, w2(i2 - 1));
-      bend_on(m, X, idx(i1, w2(i2 - 2)), c, q, 0, C2[c], D2, f);
+    {
+      auto centre_ok = [&](int64_t c2) { return per || (c2 >= 1 && c2 <= n2 - 2); };
+      const bool b0 = centre_ok(i2), bp = (per || i2 + 1 < n2) && centre_ok(i2 + 1),
+                 bm = (per || i2 - 1 >= 0) && centre_ok(i2 - 1);
+      const int64_t qm = idx(i1, w2(i2 - 1)), qp = idx(i1, w2(i2 + 1));
+      V3 xm{}, xp{}, xm2{}, xp2{};
+      if (b0 || bm) xm = ld3(X, M, qm);
+      if (b0 || bp) xp = ld3(X, M, qp);
+      if (bm) xm2 = ld3(X, M, idx(i1, w2(i2 - 2)));
+      if (bp) xp2 = ld3(X, M, idx(i1, w2(i2 + 2)));
+      if (b0) bend_on(m, xm, xq, xp, q, 1, C2[q], D2, f);
+      if (bp) bend_on(m, xq, xp, xp2, qp, 0, C2[qp], D2, f);
+      if (bm) bend_on(m, xm2, xm, xq, qm, 0, C2[qm], D2, f);
     }
   }
 }
