@@ -75,30 +75,29 @@ __global__ __launch_bounds__(256) void k_lattice_pre(Material m, double *__restr
   for (int j = 0; j < kLatPre; j++) pre[j * M + q] = v[j];
 }
 
-// Force on marker q from the stretch edge (q, o) with rest length le and
-// ke = Ks w / le^2 (of the edge's lower endpoint).
-__device__ __forceinline__ void stretch_on(const Material &m, const double *__restrict__ X, int64_t q,
-                                           int64_t o, const V3 &xq, double le, double ke, V3 &f) {
-  const int64_t M = m.M;
-  const V3 xo = ld3(X, M, o);
+// Force on marker q (position xq, multiplier kq) from the stretch edge to o
+// (position xo, multiplier ko) with rest length le and ke = Ks w / le^2 (of
+// the edge's lower endpoint).
+__device__ __forceinline__ void stretch_on(const V3 &xq, double kq, const V3 &xo, double ko, double le, double ke,
+                                           V3 &f) {
   const V3 d{xo.x - xq.x, xo.y - xq.y, xo.z - xq.z};
   const double len = nrm(d);
-  const double s = ke * (0.5 * (m.k[q] + m.k[o])) * (len - le) / len;
+  const double s = ke * (0.5 * (kq + ko)) * (len - le) / len;
   f.x += s * d.x;
   f.y += s * d.y;
   f.z += s * d.z;
 }
 
-// Force on marker q from the bend triple with positions xa, xc (centre c), xb,
-// cb = Kb w_c / Lc^4 and d2 (3 strided values) the reference second
-// difference Y_a - 2 Y_c + Y_b; role: 0 = end, 1 = centre.
+// Force on marker q from the bend triple with positions xa, xc (centre c,
+// multiplier kc), xb, cb = Kb w_c / Lc^4 and d2 (3 strided values) the
+// reference second difference Y_a - 2 Y_c + Y_b; role: 0 = end, 1 = centre.
 __device__ __forceinline__ void bend_on(const Material &m, const V3 &xa, const V3 &xc, const V3 &xb, int64_t c,
-                                        int role, double cb, const double *__restrict__ d2, V3 &f) {
+                                        double kc, int role, double cb, const double *__restrict__ d2, V3 &f) {
   const int64_t M = m.M;
   const V3 y2 = ld3(d2, M, c);
   const V3 v{(xa.x - 2.0 * xc.x + xb.x) - y2.x, (xa.y - 2.0 * xc.y + xb.y) - y2.y,
              (xa.z - 2.0 * xc.z + xb.z) - y2.z};
-  const double K = cb * m.k[c];
+  const double K = cb * kc;
   const double s = role ? 2.0 * K : -K;
   f.x += s * v.x;
   f.y += s * v.y;
@@ -116,50 +115,48 @@ __device__ void lattice_force(const Material &m, const LatticeDev &L, const doub
   auto idx = [&](int64_t a1, int64_t a2) { return L.first + a2 * n1 + a1; };
   auto w2 = [&](int64_t a2) { return per ? (a2 + n2) % n2 : a2; };
   const bool has_dn = per || i2 > 0, has_up = per || i2 < n2 - 1;
+  if (L.Ks == 0.0 && L.Kb == 0.0) return;
+  // the four neighbours' positions and multipliers, read once for the edges and the bends
+  const int64_t q1m = idx(i1 - 1, i2), q1p = idx(i1 + 1, i2), q2m = idx(i1, w2(i2 - 1)), q2p = idx(i1, w2(i2 + 1));
+  V3 x1m{}, x1p{}, x2m{}, x2p{};
+  double k1m = 0.0, k1p = 0.0, k2m = 0.0, k2p = 0.0;
+  if (i1 > 0) { x1m = ld3(X, M, q1m); k1m = m.k[q1m]; }
+  if (i1 < n1 - 1) { x1p = ld3(X, M, q1p); k1p = m.k[q1p]; }
+  if (has_dn) { x2m = ld3(X, M, q2m); k2m = m.k[q2m]; }
+  if (has_up) { x2p = ld3(X, M, q2p); k2p = m.k[q2p]; }
+  const double kq = m.k[q];
   if (L.Ks != 0.0) {
-    if (i1 > 0) {
-      const int64_t o = idx(i1 - 1, i2);
-      stretch_on(m, X, q, o, xq, P[o], P[M + o], f);
-    }
-    if (i1 < n1 - 1) stretch_on(m, X, q, idx(i1 + 1, i2), xq, P[q], P[M + q], f);
-    if (has_dn) {
-      const int64_t o = idx(i1, w2(i2 - 1));
-      stretch_on(m, X, q, o, xq, P[2 * M + o], P[3 * M + o], f);
-    }
-    if (has_up) stretch_on(m, X, q, idx(i1, w2(i2 + 1)), xq, P[2 * M + q], P[3 * M + q], f);
+    if (i1 > 0) stretch_on(xq, kq, x1m, k1m, P[q1m], P[M + q1m], f);
+    if (i1 < n1 - 1) stretch_on(xq, kq, x1p, k1p, P[q], P[M + q], f);
+    if (has_dn) stretch_on(xq, kq, x2m, k2m, P[2 * M + q2m], P[3 * M + q2m], f);
+    if (has_up) stretch_on(xq, kq, x2p, k2p, P[2 * M + q], P[3 * M + q], f);
   }
   if (L.Kb != 0.0) {
     const double *C1 = P + 4 * M, *C2 = P + 5 * M, *D1 = P + 6 * M, *D2 = P + 9 * M;
     // Along each direction the triples containing q are centred at q, at its
     // successor and at its predecessor (in that order); they need the
     // positions at offsets -2 .. 2, each read once.
-    // direction 1: centres 1 .. n1-2
+    // direction 1: centres 1 .. n1-2 (the neighbours exist wherever a triple does)
     {
       const bool b0 = i1 >= 1 && i1 <= n1 - 2, bp = i1 + 1 <= n1 - 2, bm = i1 - 1 >= 1;
-      const int64_t qm = idx(i1 - 1, i2), qp = idx(i1 + 1, i2);
-      V3 xm{}, xp{}, xm2{}, xp2{};
-      if (b0 || bm) xm = ld3(X, M, qm);
-      if (b0 || bp) xp = ld3(X, M, qp);
+      V3 xm2{}, xp2{};
       if (bm) xm2 = ld3(X, M, idx(i1 - 2, i2));
       if (bp) xp2 = ld3(X, M, idx(i1 + 2, i2));
-      if (b0) bend_on(m, xm, xq, xp, q, 1, C1[q], D1, f);
-      if (bp) bend_on(m, xq, xp, xp2, qp, 0, C1[qp], D1, f);
-      if (bm) bend_on(m, xm2, xm, xq, qm, 0, C1[qm], D1, f);
+      if (b0) bend_on(m, x1m, xq, x1p, q, kq, 1, C1[q], D1, f);
+      if (bp) bend_on(m, xq, x1p, xp2, q1p, k1p, 0, C1[q1p], D1, f);
+      if (bm) bend_on(m, xm2, x1m, xq, q1m, k1m, 0, C1[q1m], D1, f);
     }
     // direction 2: centres 1 .. n2-2, or every row when periodic
     {
       auto centre_ok = [&](int64_t c2) { return per || (c2 >= 1 && c2 <= n2 - 2); };
       const bool b0 = centre_ok(i2), bp = (per || i2 + 1 < n2) && centre_ok(i2 + 1),
                  bm = (per || i2 - 1 >= 0) && centre_ok(i2 - 1);
-      const int64_t qm = idx(i1, w2(i2 - 1)), qp = idx(i1, w2(i2 + 1));
-      V3 xm{}, xp{}, xm2{}, xp2{};
-      if (b0 || bm) xm = ld3(X, M, qm);
-      if (b0 || bp) xp = ld3(X, M, qp);
+      V3 xm2{}, xp2{};
       if (bm) xm2 = ld3(X, M, idx(i1, w2(i2 - 2)));
       if (bp) xp2 = ld3(X, M, idx(i1, w2(i2 + 2)));
-      if (b0) bend_on(m, xm, xq, xp, q, 1, C2[q], D2, f);
-      if (bp) bend_on(m, xq, xp, xp2, qp, 0, C2[qp], D2, f);
-      if (bm) bend_on(m, xm2, xm, xq, qm, 0, C2[qm], D2, f);
+      if (b0) bend_on(m, x2m, xq, x2p, q, kq, 1, C2[q], D2, f);
+      if (bp) bend_on(m, xq, x2p, xp2, q2p, k2p, 0, C2[q2p], D2, f);
+      if (bm) bend_on(m, xm2, x2m, xq, q2m, k2m, 0, C2[q2m], D2, f);
     }
   }
 }
