@@ -157,15 +157,17 @@ def test_rollout_config4_per_marker_fd(mods):
 
 
 def test_rollout_config4_vs_oracle_gradient(mods, oracle_mod):
-    """The same 50-step gradient against the FP64 oracle's; FP64 and mixed fluid."""
+    """The same 50-step gradient against the FP64 oracle's; FP64 and mixed fluid.
+    The loss is the mean squared displacement, so its relative error is about
+    twice the displacement's: 2e-5 for the mixed step's 1e-5 bound."""
     ib, rollout = mods
     wl = W.config4()
     idx = wl.meta["loss_idx"]
     announce("config4 oracle gradient")
     Lo, kbo, _, _ = oracle_mod.gradient_k(wl, wl.n_steps, idx)
-    for prec, tol in (("fp64", 1e-4), ("fp32", 5e-3)):
+    for prec, tol, ltol in (("fp64", 1e-4, 1e-5), ("fp32", 5e-3, 2e-5)):
         L, kb = _gpu_grad(ib, rollout, wl, prec, wl.n_steps, wl.meta["ckpt"], idx)
-        assert abs(L - Lo) <= 1e-5 * Lo, (prec, L, Lo)
+        assert abs(L - Lo) <= ltol * Lo, (prec, L, Lo)
         assert _rel_l2(kb, kbo) < tol, (prec, _rel_l2(kb, kbo))
 
 
