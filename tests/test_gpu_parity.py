@@ -96,6 +96,18 @@ def test_force_parity(ibm, oracle_mod, case):
         assert rel_max(F, Fo) < 1e-12, (case, t, rel_max(F, Fo))
 
 
+@pytest.mark.parametrize("case", ["helix_tiny", "helix128", "window_tiny"])
+def test_force_vanishes_at_reference_shape(ibm, case):
+    """At the reference shape every elastic term is at rest and the drive is
+    sin(0) = 0 at t = 0: the force is exactly zero (rest lengths and reference
+    second differences are formed the same way as the running ones)."""
+    wl = {"helix_tiny": W.tiny_helix, "helix128": W.config2, "window_tiny": lambda: W.tiny_helix(window=12)}[case]()
+    announce("force at rest", case)
+    ctx = ibm.Context(wl, "fp64")
+    F = host(ctx.force(dev(wl.X_ref), 0.0))
+    assert np.count_nonzero(F) == 0, (case, np.abs(F).max())
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("N", [8, 16, 32, 64])
 def test_spread_parity(ibm, oracle_mod, prec, N):
