@@ -380,3 +380,17 @@ def test_response_linear_in_drive(oracle_mod):
     ratio = np.linalg.norm(d10) / np.linalg.norm(d1)
     assert abs(ratio - 10.0) < 1e-3 * 10.0
     assert np.linalg.norm(d10 - 10.0 * d1) < 1e-3 * np.linalg.norm(d10)
+
+
+def test_force_vanishes_at_reference_shape(oracle_mod):
+    """Every elastic energy is zero, with zero gradient, at the reference shape
+    (stretch and bend are measured from it, tethers hold it), and the drive is
+    sin(0) = 0 at t = 0: the oracle's force there is exactly zero; off it, it
+    is not."""
+    for wl in (W.tiny_helix(), W.tiny_helix(window=12), W.tiny_halfcube(32)):
+        model = oracle_mod.Model(wl)
+        F = oracle_mod.force(model, wl.X_ref, 0.0)
+        assert np.count_nonzero(F) == 0, (wl.name, np.abs(F).max())
+        assert np.abs(oracle_mod.force(model, wl.X_ref, 1.3e-4)).max() > 0      # the drive
+        X = wl.X_ref + 1e-6 * np.random.default_rng(0).standard_normal(wl.X_ref.shape)
+        assert np.abs(oracle_mod.force(model, X, 0.0)).max() > 0                # the elastic terms
