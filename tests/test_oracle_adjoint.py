@@ -13,12 +13,14 @@ import pytest
 from paper_math_0301321_amd import workloads as W
 
 
-def _setup(N=16):
-    wl = W.tiny_helix(N=N)
+def _setup(N=16, half=False):
+    """The tiny helix on the N^3 cube, or the tiny flat-membrane model on the
+    N x N x N/2 half-cube."""
+    wl = W.tiny_halfcube(N) if half else W.tiny_helix(N=N)
     wl.convect = 0
     rng = np.random.default_rng(31)
     X = wl.X0 + 2e-3 * rng.standard_normal(wl.X0.shape)
-    u = 0.05 * W.random_field(N, seed=32)
+    u = 0.05 * W.random_field(N, seed=32, Nz=wl.nz)
     return wl, X, u, rng
 
 
@@ -46,9 +48,10 @@ def test_advect_adjoint_is_transpose_of_linearised_advection(oracle_mod):
         assert abs(l2 - r2) <= 1e-9 * max(abs(r2), 1.0), (c, l2, r2)
 
 
+@pytest.mark.parametrize("half", [False, True])
 @pytest.mark.parametrize("convect", [0, 1])
-def test_adjoint_step_is_transpose_of_linearised_step(oracle_mod, convect):
-    wl, X, u, rng = _setup()
+def test_adjoint_step_is_transpose_of_linearised_step(oracle_mod, convect, half):
+    wl, X, u, rng = _setup(half=half)
     wl.convect = convect
     t = 3e-4
     dX = rng.standard_normal(X.shape)
