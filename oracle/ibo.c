@@ -229,22 +229,55 @@ double ibo_energy(const ibo_model *m, const double *X) {
  * F_q = f(q) dq.  delta_h vanishes unless |x_d - X_d| < 2h, so only the 4^3
  * nodes floor(X/h)-1 .. floor(X/h)+2 are visited; node indices wrap
  * periodically.  Plain scatter in marker order.
+ *
+ * Threads split the z-planes, not the markers: thread t of nt owns the
+ * planes k with k mod nt = t, visits every marker in index order and adds
+ * only into its own planes.  Each node therefore receives its terms in marker
+ * order, as in a serial loop, and the result does not depend on the number
+ * of threads.  The weight of node (i, j, k) is phi(s1 - i) phi(s2 - j)
+ * phi(s3 - k) / h^3; the twelve factors are evaluated once per marker.
  * ---------------------------------------------------------------------- */
+static void my_planes(int64_t *t, int64_t *nt) {
+#ifdef _OPENMP
+  *t = omp_get_thread_num();
+  *nt = omp_get_num_threads();
+#else
+  *t = 0;
+  *nt = 1;
+#endif
+}
+
+/* phi(s - j) for the four nodes j = floor(s) - 1 .. floor(s) + 2 */
+static void phi4(double s, int64_t c, double w[4]) {
+  for (int a = 0; a < 4; a++) w[a] = ibo_phi(s - (double)(c - 1 + a));
+}
+
 void ibo_spread(int N, int Nz, double L, int64_t M, const double *X, const double *Fq, double *Fg) {
   int64_t G = (int64_t)N * N * Nz;
   double h = L / N, inv_h3 = 1.0 / (h * h * h);
   memset(Fg, 0, sizeof(double) * 3 * (size_t)G);
-  for (int64_t q = 0; q < M; q++) {
-    double s[3];
-    int64_t c[3];
-    for (int d = 0; d < 3; d++) { s[d] = X[d * M + q] / h; c[d] = (int64_t)floor(s[d]); }
-    for (int64_t k = c[2] - 1; k <= c[2] + 2; k++)
-      for (int64_t j = c[1] - 1; j <= c[1] + 2; j++)
-        for (int64_t i = c[0] - 1; i <= c[0] + 2; i++) {
-          double dlt = ibo_phi(s[0] - (double)i) * ibo_phi(s[1] - (double)j) * ibo_phi(s[2] - (double)k) * inv_h3;
-          int64_t p = gidx(N, Nz, i, j, k);
-          for (int cc = 0; cc < 3; cc++) Fg[cc * G + p] += Fq[cc * M + q] * dlt;
-        }
+#pragma omp parallel
+  {
+    int64_t t, nt;
+    my_planes(&t, &nt);
+    for (int64_t q = 0; q < M; q++) {
+      double s[3], w[3][4];
+      int64_t c[3];
+      for (int d = 0; d < 3; d++) { s[d] = X[d * M + q] / h; c[d] = (int64_t)floor(s[d]); }
+      int mine = 0;
+      for (int64_t k = c[2] - 1; k <= c[2] + 2; k++) mine |= wrap(k, Nz) % nt == t;
+      if (!mine) continue;
+      for (int d = 0; d < 3; d++) phi4(s[d], c[d], w[d]);
+      for (int64_t k = c[2] - 1; k <= c[2] + 2; k++) {
+        if (wrap(k, Nz) % nt != t) continue;
+        for (int64_t j = c[1] - 1; j <= c[1] + 2; j++)
+          for (int64_t i = c[0] - 1; i <= c[0] + 2; i++) {
+            double dlt = w[0][i - c[0] + 1] * w[1][j - c[1] + 1] * w[2][k - c[2] + 1] * inv_h3;
+            int64_t p = gidx(N, Nz, i, j, k);
+            for (int cc = 0; cc < 3; cc++) Fg[cc * G + p] += Fq[cc * M + q] * dlt;
+          }
+      }
+    }
   }
 }
 
@@ -257,13 +290,13 @@ void ibo_interp(int N, int Nz, double L, int64_t M, const double *X, const doubl
   double h = L / N;
 #pragma omp parallel for schedule(static)
   for (int64_t q = 0; q < M; q++) {
-    double s[3], acc[3] = {0.0, 0.0, 0.0};
+    double s[3], acc[3] = {0.0, 0.0, 0.0}, w[3][4];
     int64_t c[3];
-    for (int d = 0; d < 3; d++) { s[d] = X[d * M + q] / h; c[d] = (int64_t)floor(s[d]); }
+    for (int d = 0; d < 3; d++) { s[d] = X[d * M + q] / h; c[d] = (int64_t)floor(s[d]); phi4(s[d], c[d], w[d]); }
     for (int64_t k = c[2] - 1; k <= c[2] + 2; k++)
       for (int64_t j = c[1] - 1; j <= c[1] + 2; j++)
         for (int64_t i = c[0] - 1; i <= c[0] + 2; i++) {
-          double wgt = ibo_phi(s[0] - (double)i) * ibo_phi(s[1] - (double)j) * ibo_phi(s[2] - (double)k);
+          double wgt = w[0][i - c[0] + 1] * w[1][j - c[1] + 1] * w[2][k - c[2] + 1];
           int64_t p = gidx(N, Nz, i, j, k);
           for (int cc = 0; cc < 3; cc++) acc[cc] += u[cc * G + p] * wgt;
         }
@@ -523,6 +556,15 @@ static double dphi(double r) {
   return r < 0.0 ? -g : g;
 }
 
+/* phi(s - j) and phi'(s - j) / h for the four nodes j = floor(s) - 1 .. floor(s) + 2 */
+static void phi4_d(double s, int64_t c, double h, double w[4], double g[4]) {
+  for (int a = 0; a < 4; a++) {
+    double r = s - (double)(c - 1 + a);
+    w[a] = ibo_phi(r);
+    g[a] = dphi(r) / h;
+  }
+}
+
 /* One edge term E = 1/2 Ku kf (|d| - L0)^2 / D, D = L0^2 (rest_sq) or 1, with
  * d = Xb - Xa, Ku the stiffness at unit k-factor and kf the k-factor.
  * Adds H v into out and returns f_unit . v, the force of the edge at unit
@@ -641,46 +683,73 @@ void ibo_adjoint_step_u(const ibo_model *m, int N, int Nz, double L, double rho,
   ibo_force(m, X_n, t, f);
   for (int64_t p = 0; p < 3 * M; p++) Ub[p] = dt * Xbar[p];
 
-  /* interpolation: phi' term into Xbar, transpose (a spread without 1/h^3) into utot */
-  memcpy(utot, ubar, sizeof(double) * 3 * (size_t)G);
+  /* interpolation: phi' term into Xbar (a gather per marker) */
+#pragma omp parallel for schedule(static)
   for (int64_t q = 0; q < M; q++) {
     double s[3];
     int64_t c[3];
     for (int d = 0; d < 3; d++) { s[d] = X_n[d * M + q] / h; c[d] = (int64_t)floor(s[d]); }
-    double gX[3] = {0.0, 0.0, 0.0};
+    double gX[3] = {0.0, 0.0, 0.0}, w[3][4], g[3][4];
+    for (int d = 0; d < 3; d++) phi4_d(s[d], c[d], h, w[d], g[d]);
     for (int64_t k = c[2] - 1; k <= c[2] + 2; k++)
       for (int64_t j = c[1] - 1; j <= c[1] + 2; j++)
         for (int64_t i = c[0] - 1; i <= c[0] + 2; i++) {
-          double r[3] = {s[0] - (double)i, s[1] - (double)j, s[2] - (double)k};
-          double p0 = ibo_phi(r[0]), p1 = ibo_phi(r[1]), p2 = ibo_phi(r[2]);
-          double g0 = dphi(r[0]) / h, g1 = dphi(r[1]) / h, g2 = dphi(r[2]) / h;
+          int a0 = (int)(i - c[0] + 1), a1 = (int)(j - c[1] + 1), a2 = (int)(k - c[2] + 1);
+          double p0 = w[0][a0], p1 = w[1][a1], p2 = w[2][a2];
+          double g0 = g[0][a0], g1 = g[1][a1], g2 = g[2][a2];
           int64_t p = gidx(N, Nz, i, j, k);
           double uU = 0.0;
           for (int cc = 0; cc < 3; cc++) uU += u_np1[cc * G + p] * Ub[cc * M + q];
           gX[0] += uU * g0 * p1 * p2;
           gX[1] += uU * p0 * g1 * p2;
           gX[2] += uU * p0 * p1 * g2;
-          double wgt = p0 * p1 * p2;
-          for (int cc = 0; cc < 3; cc++) utot[cc * G + p] += Ub[cc * M + q] * wgt;
         }
     for (int d = 0; d < 3; d++) Xbar[d * M + q] += gX[d];
+  }
+  /* and its transpose, a spread without 1/h^3, into utot (z-planes dealt
+   * to threads as in ibo_spread: every node sums in marker order) */
+  memcpy(utot, ubar, sizeof(double) * 3 * (size_t)G);
+#pragma omp parallel
+  {
+    int64_t t, nt;
+    my_planes(&t, &nt);
+    for (int64_t q = 0; q < M; q++) {
+      double s[3], w[3][4];
+      int64_t c[3];
+      for (int d = 0; d < 3; d++) { s[d] = X_n[d * M + q] / h; c[d] = (int64_t)floor(s[d]); }
+      int mine = 0;
+      for (int64_t k = c[2] - 1; k <= c[2] + 2; k++) mine |= wrap(k, Nz) % nt == t;
+      if (!mine) continue;
+      for (int d = 0; d < 3; d++) phi4(s[d], c[d], w[d]);
+      for (int64_t k = c[2] - 1; k <= c[2] + 2; k++) {
+        if (wrap(k, Nz) % nt != t) continue;
+        for (int64_t j = c[1] - 1; j <= c[1] + 2; j++)
+          for (int64_t i = c[0] - 1; i <= c[0] + 2; i++) {
+            double wgt = w[0][i - c[0] + 1] * w[1][j - c[1] + 1] * w[2][k - c[2] + 1];
+            int64_t p = gidx(N, Nz, i, j, k);
+            for (int cc = 0; cc < 3; cc++) utot[cc * G + p] += Ub[cc * M + q] * wgt;
+          }
+      }
+    }
   }
 
   /* symmetric NS operator (no force, no advection) */
   ibo_fluid(N, Nz, L, rho, mu, dt, 0, utot, NULL, ubar);
 
-  /* spreading: transpose (an interpolation with 1/h^3) and phi' term */
+  /* spreading: transpose (an interpolation with 1/h^3) and phi' term, per marker */
+#pragma omp parallel for schedule(static)
   for (int64_t q = 0; q < M; q++) {
     double s[3];
     int64_t c[3];
     for (int d = 0; d < 3; d++) { s[d] = X_n[d * M + q] / h; c[d] = (int64_t)floor(s[d]); }
-    double gX[3] = {0.0, 0.0, 0.0}, acc[3] = {0.0, 0.0, 0.0};
+    double gX[3] = {0.0, 0.0, 0.0}, acc[3] = {0.0, 0.0, 0.0}, w[3][4], g[3][4];
+    for (int d = 0; d < 3; d++) phi4_d(s[d], c[d], h, w[d], g[d]);
     for (int64_t k = c[2] - 1; k <= c[2] + 2; k++)
       for (int64_t j = c[1] - 1; j <= c[1] + 2; j++)
         for (int64_t i = c[0] - 1; i <= c[0] + 2; i++) {
-          double r[3] = {s[0] - (double)i, s[1] - (double)j, s[2] - (double)k};
-          double p0 = ibo_phi(r[0]), p1 = ibo_phi(r[1]), p2 = ibo_phi(r[2]);
-          double g0 = dphi(r[0]) / h, g1 = dphi(r[1]) / h, g2 = dphi(r[2]) / h;
+          int a0 = (int)(i - c[0] + 1), a1 = (int)(j - c[1] + 1), a2 = (int)(k - c[2] + 1);
+          double p0 = w[0][a0], p1 = w[1][a1], p2 = w[2][a2];
+          double g0 = g[0][a0], g1 = g[1][a1], g2 = g[2][a2];
           int64_t p = gidx(N, Nz, i, j, k);
           double Ff = 0.0;
           for (int cc = 0; cc < 3; cc++) {
