@@ -92,7 +92,7 @@ def phase_bytes(phase, N, M, b, wls, Nz=None):
         "fft_z_solve": 2 * spec,
         "fft_y_inv": 2 * spec,
         "fft_x_inv": spec + grid,
-        "interp": M * (rec + 4 + 48) + touched * 512 * 3 * b,  # records, perm, X in/out; u of touched tiles
+        "interp": M * (4 + 4 + 48) + touched * 512 * 3 * b,    # cell key, perm, X in/out; u of touched tiles
     }.get(phase)
 
 
@@ -222,6 +222,73 @@ def extras(wl, n=10):
     return out
 
 
+def step_rate(wl, prec, steps, warmup, graph):
+    """Steps/s of `steps` steps after `warmup` (events around the steps), eager
+    launches or the step replayed as a HIP graph."""
+    import torch
+    from paper_math_0301321_amd import ib
+    ctx = ib.Context(wl, prec)
+    if graph:
+        ctx.graph_enable(True)
+    X = torch.as_tensor(wl.X0, dtype=torch.float64, device="cuda").contiguous()
+    u = ctx.new_grid()
+    for k in range(warmup):
+        ctx.step(X, u, k * wl.dt)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(warmup, warmup + steps):
+        ctx.step(X, u, k * wl.dt)
+    e1.record()
+    torch.cuda.synchronize()
+    return steps / (e0.elapsed_time(e1) / 1e3)
+
+
+def config_rates():
+    """Steps/s of the 32^3 shell (2,562 markers) and the 128^3 helix (500k
+    markers), both precisions, with and without the HIP graph."""
+    from paper_math_0301321_amd import workloads as W
+    out = {}
+    for name, wl, steps in (("shell32", W.config1(), 400), ("helix128", W.config2(), 200)):
+        for prec in ("fp32", "fp64"):
+            for graph in (False, True):
+                key = f"{name}_{'mixed' if prec == 'fp32' else 'fp64'}{'_graph' if graph else ''}_steps_per_s"
+                out[key] = round(step_rate(wl, prec, steps, 10, graph), 1)
+    return out
+
+
+def rollout_times(n=256):
+    """Seconds for the checkpointed differentiable rollout of the 256^3 adjoint
+    workload: 100 forward steps keeping a checkpoint every 20, then the
+    backward pass (each segment re-run from its checkpoint, then 100 adjoint
+    steps), the gradient of the membrane loss with respect to all 1.5M
+    stiffnesses; mixed and FP64."""
+    import torch
+    from paper_math_0301321_amd import ib, rollout, workloads as W
+    wl = W.config5(n)
+    idx = torch.as_tensor(wl.meta["loss_idx"], device="cuda")
+    out = {}
+    for prec in ("fp32", "fp64"):
+        ctx = ib.Context(wl, prec, convect=0)
+        X0 = torch.as_tensor(wl.X0, dtype=torch.float64, device="cuda").contiguous()
+        k = torch.as_tensor(wl.k, dtype=torch.float64, device="cuda").contiguous().requires_grad_(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        XT, _ = rollout.rollout(k, X0, ctx.new_grid(), ctx, wl.n_steps, wl.meta["ckpt"])
+        L = rollout.membrane_loss(XT, X0, idx)
+        L.backward()
+        e1.record()
+        torch.cuda.synchronize()
+        tag = "mixed" if prec == "fp32" else "fp64"
+        out[f"rollout{n}_{tag}_s"] = round(e0.elapsed_time(e1) / 1e3, 4)
+        out[f"rollout{n}_{tag}_grad_norm"] = float(k.grad.norm())
+        del ctx, k, XT, L
+    out[f"rollout{n}_spec"] = (f"{wl.n_steps} forward + {wl.n_steps} adjoint steps, checkpoint every "
+                               f"{wl.meta['ckpt']}, {wl.M} markers, gradient w.r.t. all stiffnesses")
+    return out
+
+
 def cpu_baseline(wl, sample_steps: int):
     import numpy as np
     import oracle
@@ -322,6 +389,12 @@ def main():
 
     if not args.no_extras and args.workload == "helix":
         extra.update(extras(wl))
+        extra[f"{wl.name}_mixed_graph_steps_per_s"] = round(step_rate(wl, "fp32", args.steps, args.warmup, True), 2)
+        print(f"[bench] graph: {extra[f'{wl.name}_mixed_graph_steps_per_s']} steps/s", file=sys.stderr, flush=True)
+        extra.update(config_rates())
+        print(f"[bench] config rates done", file=sys.stderr, flush=True)
+        extra.update(rollout_times(wl.N))
+        print(f"[bench] rollout done", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -337,7 +410,7 @@ def main():
     out = {
         "metric": metric,
         "value": round(value, 2), "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"{wl.name}: {shape}, {wl.M} markers (BM 1200x500 + wall 1800x500), "
                                f"dt {wl.dt}, {wl.drive_freq:g} Hz drive",

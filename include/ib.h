@@ -125,6 +125,20 @@ int ib_set_stream(ib_ctx *c, void *stream);
  * f^n dq.  Markers move with u^{n+1} interpolated at X^n (eq. discreteX). */
 int ib_step(ib_ctx *c, double *X, void *u, double t, double *F_lag_out);
 
+/* Replay ib_step as a HIP graph (the computation loop of Sec. 3.3 repeats the
+ * same launches every step).  While on, the first ib_step with a given
+ * (X, u, F_lag_out) triple captures the step's kernel launches (on an internal
+ * stream; nothing runs during the capture) into a graph, and every ib_step
+ * with the same three pointers launches that graph on the context's stream,
+ * with only the force kernel's drive amplitude A sin(2 pi f t) updated; other
+ * pointers capture anew.  ib_set_material drops the graph (it holds the
+ * material pointers).  Results are bitwise those of the launches without the
+ * graph.  Bypassed while the timers are enabled or IB_CHECK=1.  on = 0 drops
+ * the graph.  Capture or launch failures are IB_EDEVICE. */
+int ib_graph_enable(ib_ctx *c, int on);
+/* Graphs captured and launched on this context so far. */
+int ib_graph_stats(const ib_ctx *c, int64_t *captures, int64_t *launches);
+
 /* Sub-step 1: F_lag = f(X, t) dq, [3][M] double (overwritten). */
 int ib_force(ib_ctx *c, const double *X, double t, double *F_lag);
 

@@ -259,11 +259,13 @@ def adjoint_step(model: Model, wl, X_n, u_np1, t, Xbar, ubar, kbar, N=None, conv
     return Xb, ub, kb
 
 
-def gradient_k(wl, n_steps, loss_idx, N=None, k=None, X0=None, convect=0):
+def gradient_k(wl, n_steps, loss_idx, N=None, k=None, X0=None, convect=0, progress=None):
     """Loss L = (1/|W|) sum_{q in W} |X_q^T - X_q^0|^2 after n_steps steps (Stokes,
     or with the upwind advection when convect = 1) from (X0, u = 0), and its
     gradient with respect to the per-marker stiffness k, by the adjoint step run
-    backwards over stored states.  Returns (L, kbar, Xbar0, ubar0)."""
+    backwards over stored states.  Returns (L, kbar, Xbar0, ubar0).
+    ``progress(phase, n)``, when given, is called after every step of the
+    forward ("forward") and reverse ("adjoint") sweeps."""
     N = wl.N if N is None else N
     model = Model(wl, k)
     X0 = _f64(wl.X0 if X0 is None else X0)
@@ -273,6 +275,8 @@ def gradient_k(wl, n_steps, loss_idx, N=None, k=None, X0=None, convect=0):
         Xn, un = step(model, wl, Xs[-1], us[-1], n * wl.dt, N=N, convect=convect)
         Xs.append(Xn)
         us.append(un)
+        if progress is not None:
+            progress("forward", n)
     d = Xs[-1][:, idx] - X0[:, idx]
     L = float((d * d).sum() / len(idx))
     Xb = np.zeros_like(X0)
@@ -282,4 +286,6 @@ def gradient_k(wl, n_steps, loss_idx, N=None, k=None, X0=None, convect=0):
     for n in reversed(range(n_steps)):
         Xb, ub, kb = adjoint_step(model, wl, Xs[n], us[n + 1], n * wl.dt, Xb, ub, kb, N=N, convect=convect,
                                   u_n=us[n])
+        if progress is not None:
+            progress("adjoint", n)
     return L, kb, Xb, ub

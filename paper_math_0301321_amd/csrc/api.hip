@@ -124,6 +124,8 @@ int checked(ib_ctx *c, const void *grid, bool grid_f32, const double *markers) {
 
 }  // namespace
 
+static void graph_release(ib_ctx *c);
+
 // ------------------------------------------------------------- create ----
 extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) {
   if (!out) {
@@ -385,6 +387,8 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
 extern "C" void ib_destroy(ib_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  graph_release(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto &r : c->trec) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -471,6 +475,7 @@ extern "C" int ib_set_material(ib_ctx *c, const double *w, const double *k, cons
   if (k) c->mat.k = k;
   if (X_ref) c->mat.X_ref = X_ref;
   if (kappa) c->mat.kappa = kappa;
+  graph_release(c);   // a captured step holds the material pointers
   if (w || X_ref) IB_TRY(launch_lattice_pre(c));   // reference-shape constants follow X_ref and w
   return IB_OK;
 }
@@ -486,13 +491,107 @@ extern "C" const char *ib_last_error(const ib_ctx *c) { return c ? c->err.c_str(
 extern "C" int64_t ib_workspace_bytes(const ib_ctx *c) { return c ? c->ws_bytes : 0; }
 
 // -------------------------------------------------------- entry points ----
+// The four sub-steps of Sec. 3.2 as kernel launches on c->stream.
+template <typename T>
+static hipError_t step_launches(ib_ctx *c, double *X, T *u, double amp, double *F_lag_out) {
+  hipError_t e = launch_bin(c, X);
+  if (e == hipSuccess) e = launch_force_rec<T>(c, X, amp, F_lag_out);
+  if (e == hipSuccess) e = launch_spread<T>(c, (T *)c->ws.Fgrid, false, 1.0 / (c->h * c->h * c->h));
+  if (e == hipSuccess) e = launch_fluid<T>(c, u, (const T *)c->ws.Fgrid, 1, c->p.convect, c->p.dt / c->p.rho, u);
+  if (e == hipSuccess) e = launch_interp<T>(c, u, X, X, nullptr, c->p.dt);
+  return e;
+}
+
+static void graph_release(ib_ctx *c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+  c->graph_force = nullptr;
+  c->graph_force_args.clear();
+  c->graph_key[0] = c->graph_key[1] = c->graph_key[2] = nullptr;
+}
+
+// Capture the step's launches for these pointers into c->graph / c->graph_exec
+// and find the force kernel's node, whose drive amplitude changes per step.
+template <typename T>
+static int graph_capture(ib_ctx *c, double *X, T *u, double amp, double *F_lag_out) {
+  graph_release(c);
+  if (!c->cap_stream) IB_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  // the capture stream starts after the work already queued on the context's stream
+  hipStream_t user = c->stream;
+  IB_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  c->stream = c->cap_stream;
+  const hipError_t el = step_launches<T>(c, X, u, amp, F_lag_out);
+  c->stream = user;
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(c->cap_stream, &g);
+  if (el != hipSuccess || ee != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(c, IB_EDEVICE, std::string("ib_step: graph capture failed: ") +
+                                   hipGetErrorString(el != hipSuccess ? el : ee));
+  }
+  c->graph = g;
+  size_t nn = 0;
+  IB_TRY(hipGraphGetNodes(g, nullptr, &nn));
+  std::vector<hipGraphNode_t> nodes(nn);
+  if (nn) IB_TRY(hipGraphGetNodes(g, nodes.data(), &nn));
+  const void *fk = force_rec_kernel<T>();
+  for (hipGraphNode_t nd : nodes) {
+    hipGraphNodeType ty;
+    IB_TRY(hipGraphNodeGetType(nd, &ty));
+    if (ty != hipGraphNodeTypeKernel) continue;
+    hipKernelNodeParams kp{};
+    IB_TRY(hipGraphKernelNodeGetParams(nd, &kp));
+    if (kp.func == fk) {
+      c->graph_force = nd;
+      c->graph_force_params = kp;
+    }
+  }
+  if (c->M > 0 && !c->graph_force) {
+    graph_release(c);
+    return fail(c, IB_EDEVICE, "ib_step: the captured graph has no force kernel node");
+  }
+  if (c->graph_force) {
+    // argument pointers: the graph's own values, except the amplitude
+    if (!c->graph_force_params.kernelParams) {
+      graph_release(c);
+      return fail(c, IB_EDEVICE, "ib_step: the captured force node has no argument list");
+    }
+    c->graph_force_args.assign(c->graph_force_params.kernelParams,
+                               c->graph_force_params.kernelParams + kForceRecArgs);
+    c->graph_force_args[kForceRecAmpArg] = &c->graph_amp;
+    c->graph_force_params.kernelParams = c->graph_force_args.data();
+    c->graph_amp = amp;
+  }
+  IB_TRY(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+  c->graph_key[0] = X;
+  c->graph_key[1] = u;
+  c->graph_key[2] = F_lag_out;
+  c->graph_captures++;
+  return IB_OK;
+}
+
+template <typename T>
+static int step_graph(ib_ctx *c, double *X, T *u, double t, double *F_lag_out) {
+  const double amp = drive_amp(c, t);
+  if (!c->graph_exec || c->graph_key[0] != X || c->graph_key[1] != u || c->graph_key[2] != F_lag_out) {
+    const int rc = graph_capture<T>(c, X, u, amp, F_lag_out);
+    if (rc != IB_OK) return rc;
+  } else if (c->graph_force && amp != c->graph_amp) {
+    c->graph_amp = amp;
+    IB_TRY(hipGraphExecKernelNodeSetParams(c->graph_exec, c->graph_force, &c->graph_force_params));
+  }
+  IB_TRY(hipGraphLaunch(c->graph_exec, c->stream));
+  c->graph_launches++;
+  return IB_OK;
+}
+
 template <typename T>
 static int step_impl(ib_ctx *c, double *X, T *u, double t, double *F_lag_out) {
-  IB_TRY(launch_bin(c, X));
-  IB_TRY(launch_force_rec<T>(c, X, drive_amp(c, t), F_lag_out));
-  IB_TRY(launch_spread<T>(c, (T *)c->ws.Fgrid, false, 1.0 / (c->h * c->h * c->h)));
-  IB_TRY(launch_fluid<T>(c, u, (const T *)c->ws.Fgrid, 1, c->p.convect, c->p.dt / c->p.rho, u));
-  IB_TRY(launch_interp<T>(c, u, X, nullptr, c->p.dt));
+  // the graph is bypassed while the timers record events or IB_CHECK synchronises
+  if (c->graph_on && !c->timing && !c->check) return step_graph<T>(c, X, u, t, F_lag_out);
+  IB_TRY(step_launches<T>(c, X, u, drive_amp(c, t), F_lag_out));
   return checked(c, u, c->fp32, X);
 }
 
@@ -502,6 +601,21 @@ extern "C" int ib_step(ib_ctx *c, double *X, void *u, double t, double *F_lag_ou
   c->err.clear();
   return c->fp32 ? step_impl<float>(c, X, (float *)u, t, F_lag_out)
                  : step_impl<double>(c, X, (double *)u, t, F_lag_out);
+}
+
+extern "C" int ib_graph_enable(ib_ctx *c, int on) {
+  if (!c) return IB_EINVAL;
+  c->err.clear();
+  if (!on) graph_release(c);
+  c->graph_on = on != 0;
+  return IB_OK;
+}
+
+extern "C" int ib_graph_stats(const ib_ctx *c, int64_t *captures, int64_t *launches) {
+  if (!c || !captures || !launches) return IB_EINVAL;
+  *captures = c->graph_captures;
+  *launches = c->graph_launches;
+  return IB_OK;
 }
 
 extern "C" int ib_force(ib_ctx *c, const double *X, double t, double *F_lag) {
@@ -532,7 +646,7 @@ template <typename T>
 static int interp_impl(ib_ctx *c, const double *X, const T *u, double *U) {
   IB_TRY(launch_bin(c, X));
   IB_TRY(launch_prep<T>(c, X, nullptr));
-  IB_TRY(launch_interp<T>(c, u, nullptr, U, 0.0));
+  IB_TRY(launch_interp<T>(c, u, X, nullptr, U, 0.0));
   return checked(c, nullptr, false, U);
 }
 
@@ -578,13 +692,13 @@ static int adjoint_impl(ib_ctx *c, const double *X_n, const T *u_n, const T *u_n
   IB_TRY(launch_bin(c, X_n));
   IB_TRY(launch_force_rec<T>(c, X_n, drive_amp(c, t), c->ws.Flag));
   // interpolation / move: phi' term into Xbar, stage Ubar = dt Xbar
-  IB_TRY(launch_adj_interp<T>(c, u_np1, Xbar));
+  IB_TRY(launch_adj_interp<T>(c, u_np1, X_n, Xbar));
   // transpose of interpolation: ubar_tot = ubar + S(Ubar) h^3
   IB_TRY(launch_spread<T>(c, (T *)c->ws.Fgrid, false, 1.0));
   // the NS operator is symmetric: ubar^n = Lop ubar_tot
   IB_TRY(launch_fluid<T>(c, ubar, (const T *)c->ws.Fgrid, 1, 0, 1.0, ubar));
   // transpose of spreading (fbar) and its phi' term, then the force Jacobian
-  IB_TRY(launch_adj_spread<T>(c, ubar, c->ws.Flag, Xbar, c->ws.fb));
+  IB_TRY(launch_adj_spread<T>(c, ubar, c->ws.Flag, X_n, Xbar, c->ws.fb));
   IB_TRY(launch_hessvec(c, X_n, c->ws.fb, Xbar, kbar));
   // with advection, r = u - dt A(u) + ...: ubar^n = rbar - dt (dA/du)^T rbar at u^n
   if (c->p.convect) IB_TRY(launch_adv_adjoint<T>(c, u_n, ubar, (T *)c->ws.Fgrid));

@@ -299,6 +299,14 @@ hipError_t launch_force_rec(ib_ctx *c, const double *X, double amp, double *F) {
 template hipError_t launch_force_rec<float>(ib_ctx *, const double *, double, double *);
 template hipError_t launch_force_rec<double>(ib_ctx *, const double *, double, double *);
 
+// launch_force_rec passes amp as argument kForceRecAmpArg of k_force_rec
+template <typename T>
+const void *force_rec_kernel() {
+  return reinterpret_cast<const void *>(&k_force_rec<T>);
+}
+template const void *force_rec_kernel<float>();
+template const void *force_rec_kernel<double>();
+
 }  // namespace ib
 
 // ---------------------------------------------------------------------------

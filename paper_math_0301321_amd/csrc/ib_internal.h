@@ -180,6 +180,19 @@ struct ib_ctx {
   size_t tused = 0;
   double tms[ib::PH_COUNT] = {};
   int64_t tcalls[ib::PH_COUNT] = {};
+  // HIP graph of ib_step (ib_graph_enable): captured on cap_stream for one set of
+  // (X, u, F_lag_out) pointers, replayed on `stream` with the force kernel's
+  // drive amplitude updated per step
+  bool graph_on = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraphNode_t graph_force = nullptr;      // the force kernel's node (null when M = 0)
+  hipKernelNodeParams graph_force_params{};
+  std::vector<void *> graph_force_args;      // its argument pointers, the amplitude's pointing at graph_amp
+  double graph_amp = 0.0;
+  const void *graph_key[3] = {nullptr, nullptr, nullptr};
+  int64_t graph_captures = 0, graph_launches = 0;
 };
 
 namespace ib {
@@ -190,6 +203,12 @@ hipError_t launch_force(ib_ctx *c, const double *X, double amp, double *F);
 // force and the sorted records in one pass (needs the binning); F nullable
 template <typename T>
 hipError_t launch_force_rec(ib_ctx *c, const double *X, double amp, double *F);
+// the kernel launch_force_rec launches, and the position of `amp` among its arguments
+// (for updating a captured launch)
+template <typename T>
+const void *force_rec_kernel();
+constexpr int kForceRecAmpArg = 5;
+constexpr int kForceRecArgs = 13;
 template <typename T>
 hipError_t launch_prep(ib_ctx *c, const double *X, const double *F);      // sorted records
 template <typename T>
@@ -207,14 +226,16 @@ hipError_t launch_fluid_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, in
                             T *u_out);
 template <typename T>
 hipError_t launch_fluid(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect, double f_scale, T *u_out);
+// U = S*(X_pos) u (FP64 weights and sums); X_inout += dt U when given, U_out = U when given
 template <typename T>
-hipError_t launch_interp(ib_ctx *c, const T *u, double *X_inout, double *U_out, double dt);
+hipError_t launch_interp(ib_ctx *c, const T *u, const double *X_pos, double *X_inout, double *U_out, double dt);
 
 // adjoint pieces
 template <typename T>
-hipError_t launch_adj_interp(ib_ctx *c, const T *u_np1, double *Xbar);   // stages dt*Xbar in recs[].F
+hipError_t launch_adj_interp(ib_ctx *c, const T *u_np1, const double *X_n, double *Xbar);   // stages dt*Xbar in recs[].F
 template <typename T>
-hipError_t launch_adj_spread(ib_ctx *c, const T *ubar_n, const double *F, double *Xbar, double *fbar);
+hipError_t launch_adj_spread(ib_ctx *c, const T *ubar_n, const double *F, const double *X_n, double *Xbar,
+                             double *fbar);
 hipError_t launch_hessvec(ib_ctx *c, const double *X, const double *v, double *Xbar, double *kbar);
 // reference-shape constants of the lattices from X_ref and w (at creation and when they are set)
 hipError_t launch_lattice_pre(ib_ctx *c);

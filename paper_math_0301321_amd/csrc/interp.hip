@@ -6,8 +6,17 @@
 // stages the velocity on the tile's 11^3 halo (nodes -1 .. 9, wrapped) in LDS,
 // three components per node; then each thread interpolates one marker at a
 // time from LDS.  The weights come from the same X^n fractional offsets the
-// spread used (eq. discreteX interpolates u^{n+1} at X^n).  Velocities
-// accumulate in the fluid precision; the position update X += dt U is FP64.
+// spread used (eq. discreteX interpolates u^{n+1} at X^n).
+//
+// These gathers weight the grid values (fluid precision) with FP64 weights,
+// formed from the FP64 positions, and sum in FP64, in both fluid precisions;
+// the position update X += dt U is FP64.  Membrane markers lie far closer
+// together than h and read the same grid values, so the differences of their
+// velocities (which set the membrane's strain rates, and through them the
+// stretch and bend forces) keep the grid values' relative accuracy only if
+// the weights and sums do not round: with FP32 weights the second difference
+// of U across three neighbouring markers would carry an FP32 rounding of U
+// itself, orders of magnitude above the difference.
 #include <algorithm>
 
 #include "dev_common.h"
@@ -41,34 +50,43 @@ struct alignas(4 * sizeof(T)) U4 {
 constexpr int kInterpThreads = 256;
 constexpr int kInterpPer = 4;     // markers per thread per round
 
-// One marker: interpolate u from the staged halo and move it (or store U).
+// Fractional offset s - floor(s), s = x / h, in FP64: the same value the
+// force pass stores in the record (rounded there to the fluid precision).
+__device__ __forceinline__ double frac_of(double x, double h) {
+  const double s = x / h;
+  return s - floor(s);
+}
+
+// One marker at position x (its cell is the record's key): interpolate u from
+// the staged halo with FP64 weights, summing in FP64.
 template <typename T>
-__device__ __forceinline__ void interp_one(const U4<T> *uh, const Rec<T> &rec, T &a0, T &a1, T &a2) {
-  T wx[4], wy[4], wz[4];
-  phi4<T>(rec.f[0], wx);
-  phi4<T>(rec.f[1], wy);
-  phi4<T>(rec.f[2], wz);
-  const int base = halo_base(rec.key);
-  a0 = a1 = a2 = T(0);
+__device__ __forceinline__ void interp_one(const U4<T> *uh, uint32_t key, const double x[3], double h, double &a0,
+                                           double &a1, double &a2) {
+  double wx[4], wy[4], wz[4];
+  phi4<double>(frac_of(x[0], h), wx);
+  phi4<double>(frac_of(x[1], h), wy);
+  phi4<double>(frac_of(x[2], h), wz);
+  const int base = halo_base(key);
+  a0 = a1 = a2 = 0.0;
 #pragma unroll
   for (int c3 = 0; c3 < 4; c3++) {
 #pragma unroll
     for (int c2 = 0; c2 < 4; c2++) {
       const int row = base + c3 * (kHalo * kHalo) + c2 * kHalo;
-      const T wyz = wy[c2] * wz[c3];
+      const double wyz = wy[c2] * wz[c3];
 #pragma unroll
       for (int c1 = 0; c1 < 4; c1++) {
         const U4<T> v = uh[row + c1];
-        const T wt = wx[c1] * wyz;
-        a0 += v.x * wt;
-        a1 += v.y * wt;
-        a2 += v.z * wt;
+        const double wt = wx[c1] * wyz;
+        a0 += (double)v.x * wt;
+        a1 += (double)v.y * wt;
+        a2 += (double)v.z * wt;
       }
     }
   }
 }
 
-// Per round a thread takes up to kInterpPer markers: all their record and
+// Per round a thread takes up to kInterpPer markers: all their cell-key and
 // marker-id loads, and the halo loads, are issued together, then the position
 // loads, so that an item costs a few memory round trips.
 template <typename T>
@@ -77,8 +95,9 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
                                                            const int32_t *__restrict__ item_tile, int chunk,
                                                            const int32_t *__restrict__ counts,
                                                            const int32_t *__restrict__ perm,
-                                                           const Rec<T> *__restrict__ recs, const T *__restrict__ u,
-                                                           int n, int nz, int log2nt, int64_t M, double dt,
+                                                           const uint32_t *__restrict__ keys, const T *__restrict__ u,
+                                                           int n, int nz, int log2nt, int64_t M, double h,
+                                                           double dt, const double *__restrict__ Xpos,
                                                            double *__restrict__ X, double *__restrict__ U) {
   __shared__ U4<T> uh[kHalo3];
   const int tid = threadIdx.x;
@@ -114,13 +133,13 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
       hv[i][1] = u[G + p];
       hv[i][2] = u[2 * G + p];
     }
-    // first round's records and ids, in flight with the halo loads
-    Rec<T> rec[kInterpPer];
+    // first round's cell keys and ids, in flight with the halo loads
+    uint32_t key[kInterpPer];
     int64_t q[kInterpPer];
 #pragma unroll
     for (int m = 0; m < kInterpPer; m++) {
       const int j = min(j0 + tid + kInterpThreads * m, j1 - 1);
-      rec[m] = recs[j];
+      key[m] = keys[j];
       q[m] = perm[j];
     }
     __syncthreads();   // the previous item's reads of the halo are done
@@ -142,34 +161,33 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
 #pragma unroll
         for (int m = 0; m < kInterpPer; m++) {
           const int j = min(jr + tid + kInterpThreads * m, j1 - 1);
-          rec[m] = recs[j];
+          key[m] = keys[j];
           q[m] = perm[j];
         }
       }
+      // positions X^n (Xpos = X when moving): the weights and the move
       double xo[kInterpPer][3];
-      if (X) {
 #pragma unroll
-        for (int m = 0; m < kInterpPer; m++) {
-          xo[m][0] = X[q[m]];
-          xo[m][1] = X[M + q[m]];
-          xo[m][2] = X[2 * M + q[m]];
-        }
+      for (int m = 0; m < kInterpPer; m++) {
+        xo[m][0] = Xpos[q[m]];
+        xo[m][1] = Xpos[M + q[m]];
+        xo[m][2] = Xpos[2 * M + q[m]];
       }
 #pragma unroll
       for (int m = 0; m < kInterpPer; m++) {
         const int j = jr + tid + kInterpThreads * m;
         if (j < j1) {
-          T a0, a1, a2;
-          interp_one<T>(uh, rec[m], a0, a1, a2);
+          double a0, a1, a2;
+          interp_one<T>(uh, key[m], xo[m], h, a0, a1, a2);
           if (U) {
-            U[q[m]] = (double)a0;
-            U[M + q[m]] = (double)a1;
-            U[2 * M + q[m]] = (double)a2;
+            U[q[m]] = a0;
+            U[M + q[m]] = a1;
+            U[2 * M + q[m]] = a2;
           }
           if (X) {
-            X[q[m]] = xo[m][0] + dt * (double)a0;
-            X[M + q[m]] = xo[m][1] + dt * (double)a1;
-            X[2 * M + q[m]] = xo[m][2] + dt * (double)a2;
+            X[q[m]] = xo[m][0] + dt * a0;
+            X[M + q[m]] = xo[m][1] + dt * a1;
+            X[2 * M + q[m]] = xo[m][2] + dt * a2;
           }
         }
       }
@@ -181,11 +199,13 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
 //   Xbar_q += sum_x (u^{n+1}(x) . Ubar_q) dPhi_q/dX_q      (phi' term)
 // and Ubar is staged (sorted order, fluid precision) for the transpose of
 // interpolation, a spread without the 1/h^3 factor.
+// The gather is in FP64 (weights from the FP64 position X^n, as in k_interp).
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__ keys,
                                                     const int32_t *__restrict__ perm, Rec<T> *__restrict__ recs,
                                                     const T *__restrict__ u, int n, int nz, int log2n, int log2nt,
-                                                    int64_t M, double dt, double inv_h, double *__restrict__ Xbar) {
+                                                    int64_t M, double h, double dt, const double *__restrict__ X,
+                                                    double *__restrict__ Xbar) {
   const int64_t i = gtid();
   if (i >= M) return;
   const int mask = n - 1, maskz = nz - 1;
@@ -193,91 +213,95 @@ __global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__
   const Cell cc = key_cell(keys[i], log2nt);
   const int64_t q = perm[i];
   const double xb0 = Xbar[q], xb1 = Xbar[M + q], xb2 = Xbar[2 * M + q];
-  const T ub0 = (T)(dt * xb0), ub1 = (T)(dt * xb1), ub2 = (T)(dt * xb2);
+  const double ub0 = dt * xb0, ub1 = dt * xb1, ub2 = dt * xb2;
   // stage Ubar as the record's force: the transpose of interpolation is a spread
-  recs[i].F[0] = ub0;
-  recs[i].F[1] = ub1;
-  recs[i].F[2] = ub2;
-  const T f0 = recs[i].f[0], f1 = recs[i].f[1], f2 = recs[i].f[2];
-  T wx[4], wy[4], wz[4], gx[4], gy[4], gz[4];
-  phi4<T>(f0, wx);
-  phi4<T>(f1, wy);
-  phi4<T>(f2, wz);
-  dphi4<T>(f0, gx);
-  dphi4<T>(f1, gy);
-  dphi4<T>(f2, gz);
-  T g0 = 0, g1 = 0, g2 = 0;
+  recs[i].F[0] = (T)ub0;
+  recs[i].F[1] = (T)ub1;
+  recs[i].F[2] = (T)ub2;
+  const double f0 = frac_of(X[q], h), f1 = frac_of(X[M + q], h), f2 = frac_of(X[2 * M + q], h);
+  double wx[4], wy[4], wz[4], gx[4], gy[4], gz[4];
+  phi4<double>(f0, wx);
+  phi4<double>(f1, wy);
+  phi4<double>(f2, wz);
+  dphi4<double>(f0, gx);
+  dphi4<double>(f1, gy);
+  dphi4<double>(f2, gz);
+  double g0 = 0, g1 = 0, g2 = 0;
   for (int c3 = 0; c3 < 4; c3++) {
     const int64_t zo = (int64_t)((cc.z + c3 - 1) & maskz) << (2 * log2n);
     for (int c2 = 0; c2 < 4; c2++) {
       const int64_t yo = zo + ((int64_t)((cc.y + c2 - 1) & mask) << log2n);
       for (int c1 = 0; c1 < 4; c1++) {
         const int64_t p = yo + ((cc.x + c1 - 1) & mask);
-        const T uU = u[p] * ub0 + u[G + p] * ub1 + u[2 * G + p] * ub2;
+        const double uU = (double)u[p] * ub0 + (double)u[G + p] * ub1 + (double)u[2 * G + p] * ub2;
         g0 += uU * (gx[c1] * wy[c2] * wz[c3]);
         g1 += uU * (wx[c1] * gy[c2] * wz[c3]);
         g2 += uU * (wx[c1] * wy[c2] * gz[c3]);
       }
     }
   }
-  Xbar[q] = xb0 + (double)g0 * inv_h;
-  Xbar[M + q] = xb1 + (double)g1 * inv_h;
-  Xbar[2 * M + q] = xb2 + (double)g2 * inv_h;
+  Xbar[q] = xb0 + g0 / h;
+  Xbar[M + q] = xb1 + g1 / h;
+  Xbar[2 * M + q] = xb2 + g2 / h;
 }
 
 // Adjoint of the spreading, with Fbar = scale_F * ubar^n (scale_F = dt/rho):
 //   fbar_q = sum_x Fbar(x) Phi_q / h^3,
 //   Xbar_q += sum_x (Fbar(x) . f_q) dPhi_q/dX_q / h^3.
+// The gather is in FP64 (weights from the FP64 position X^n, as in k_interp):
+// fbar feeds the elastic Hessian, whose stretch and bend parts difference it
+// across neighbouring markers.
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_spread(const uint32_t *__restrict__ keys,
-                                                    const int32_t *__restrict__ perm, const Rec<T> *__restrict__ recs,
-                                                    const T *__restrict__ ub, const double *__restrict__ F, int n,
-                                                    int nz, int log2n, int log2nt, int64_t M, double scale, double inv_h,
-                                                    double *__restrict__ Xbar, double *__restrict__ fbar) {
+                                                    const int32_t *__restrict__ perm, const T *__restrict__ ub,
+                                                    const double *__restrict__ F, int n, int nz, int log2n,
+                                                    int log2nt, int64_t M, double scale, double h,
+                                                    const double *__restrict__ X, double *__restrict__ Xbar,
+                                                    double *__restrict__ fbar) {
   const int64_t i = gtid();
   if (i >= M) return;
   const int mask = n - 1, maskz = nz - 1;
   const int64_t G = (int64_t)nz << (2 * log2n);
   const Cell cc = key_cell(keys[i], log2nt);
   const int64_t q = perm[i];
-  const T f0 = (T)F[q], f1 = (T)F[M + q], f2 = (T)F[2 * M + q];
-  const T r0 = recs[i].f[0], r1 = recs[i].f[1], r2 = recs[i].f[2];
-  T wx[4], wy[4], wz[4], gx[4], gy[4], gz[4];
-  phi4<T>(r0, wx);
-  phi4<T>(r1, wy);
-  phi4<T>(r2, wz);
-  dphi4<T>(r0, gx);
-  dphi4<T>(r1, gy);
-  dphi4<T>(r2, gz);
-  T a0 = 0, a1 = 0, a2 = 0, g0 = 0, g1 = 0, g2 = 0;
+  const double f0 = F[q], f1 = F[M + q], f2 = F[2 * M + q];
+  const double r0 = frac_of(X[q], h), r1 = frac_of(X[M + q], h), r2 = frac_of(X[2 * M + q], h);
+  double wx[4], wy[4], wz[4], gx[4], gy[4], gz[4];
+  phi4<double>(r0, wx);
+  phi4<double>(r1, wy);
+  phi4<double>(r2, wz);
+  dphi4<double>(r0, gx);
+  dphi4<double>(r1, gy);
+  dphi4<double>(r2, gz);
+  double a0 = 0, a1 = 0, a2 = 0, g0 = 0, g1 = 0, g2 = 0;
   for (int c3 = 0; c3 < 4; c3++) {
     const int64_t zo = (int64_t)((cc.z + c3 - 1) & maskz) << (2 * log2n);
     for (int c2 = 0; c2 < 4; c2++) {
       const int64_t yo = zo + ((int64_t)((cc.y + c2 - 1) & mask) << log2n);
       for (int c1 = 0; c1 < 4; c1++) {
         const int64_t p = yo + ((cc.x + c1 - 1) & mask);
-        const T b0 = ub[p], b1 = ub[G + p], b2 = ub[2 * G + p];
-        const T wt = (wx[c1] * wy[c2]) * wz[c3];
+        const double b0 = ub[p], b1 = ub[G + p], b2 = ub[2 * G + p];
+        const double wt = (wx[c1] * wy[c2]) * wz[c3];
         a0 += b0 * wt;
         a1 += b1 * wt;
         a2 += b2 * wt;
-        const T Ff = b0 * f0 + b1 * f1 + b2 * f2;
+        const double Ff = b0 * f0 + b1 * f1 + b2 * f2;
         g0 += Ff * (gx[c1] * wy[c2] * wz[c3]);
         g1 += Ff * (wx[c1] * gy[c2] * wz[c3]);
         g2 += Ff * (wx[c1] * wy[c2] * gz[c3]);
       }
     }
   }
-  fbar[q] = scale * (double)a0;
-  fbar[M + q] = scale * (double)a1;
-  fbar[2 * M + q] = scale * (double)a2;
-  Xbar[q] += scale * (double)g0 * inv_h;
-  Xbar[M + q] += scale * (double)g1 * inv_h;
-  Xbar[2 * M + q] += scale * (double)g2 * inv_h;
+  fbar[q] = scale * a0;
+  fbar[M + q] = scale * a1;
+  fbar[2 * M + q] = scale * a2;
+  Xbar[q] += scale * g0 / h;
+  Xbar[M + q] += scale * g1 / h;
+  Xbar[2 * M + q] += scale * g2 / h;
 }
 
 template <typename T>
-hipError_t launch_interp(ib_ctx *c, const T *u, double *X_inout, double *U_out, double dt) {
+hipError_t launch_interp(ib_ctx *c, const T *u, const double *X_pos, double *X_inout, double *U_out, double dt) {
   if (c->M == 0) return hipSuccess;
   PhaseScope ps(c, PH_INTERP);
   // 16 blocks per CU (4 resident in FP32, 3 in FP64): a block takes a few
@@ -287,38 +311,41 @@ hipError_t launch_interp(ib_ctx *c, const T *u, double *X_inout, double *U_out, 
   const int grid = (int)std::min<int64_t>(c->item_cap, (int64_t)c->ncu * 16);
   hipLaunchKernelGGL(k_interp<T>, dim3(grid), dim3(kInterpThreads), 0, c->stream, c->ws.tile_start,
                      c->ws.tile_item0, c->ws.item_tile, c->chunk, c->ws.nitems, c->ws.vals[c->sorted_buf],
-                     (const Rec<T> *)c->ws.recs, u, c->n, c->nz, c->log2nt, c->M, dt, X_inout,
+                     c->ws.keys[c->sorted_buf], u, c->n, c->nz, c->log2nt, c->M, c->h, dt, X_pos, X_inout,
                      U_out);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_adj_interp(ib_ctx *c, const T *u_np1, double *Xbar) {
+hipError_t launch_adj_interp(ib_ctx *c, const T *u_np1, const double *X_n, double *Xbar) {
   if (c->M == 0) return hipSuccess;
   PhaseScope ps(c, PH_ADJ_INTERP);
   hipLaunchKernelGGL(k_adj_interp<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
                      c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (Rec<T> *)c->ws.recs, u_np1, c->n,
-                     c->nz, c->log2n, c->log2nt, c->M, c->p.dt, 1.0 / c->h, Xbar);
+                     c->nz, c->log2n, c->log2nt, c->M, c->h, c->p.dt, X_n, Xbar);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_adj_spread(ib_ctx *c, const T *ubar_n, const double *F, double *Xbar, double *fbar) {
+hipError_t launch_adj_spread(ib_ctx *c, const T *ubar_n, const double *F, const double *X_n, double *Xbar,
+                             double *fbar) {
   if (c->M == 0) return hipSuccess;
   PhaseScope ps(c, PH_ADJ_SPREAD);
   const double scale = (c->p.dt / c->p.rho) / (c->h * c->h * c->h);
   hipLaunchKernelGGL(k_adj_spread<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
-                     c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (const Rec<T> *)c->ws.recs, ubar_n, F, c->n,
-                     c->nz, c->log2n, c->log2nt, c->M, scale, 1.0 / c->h, Xbar, fbar);
+                     c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], ubar_n, F, c->n, c->nz, c->log2n,
+                     c->log2nt, c->M, scale, c->h, X_n, Xbar, fbar);
   return hipGetLastError();
 }
 
-template hipError_t launch_interp<float>(ib_ctx *, const float *, double *, double *, double);
-template hipError_t launch_interp<double>(ib_ctx *, const double *, double *, double *, double);
-template hipError_t launch_adj_interp<float>(ib_ctx *, const float *, double *);
-template hipError_t launch_adj_interp<double>(ib_ctx *, const double *, double *);
-template hipError_t launch_adj_spread<float>(ib_ctx *, const float *, const double *, double *, double *);
-template hipError_t launch_adj_spread<double>(ib_ctx *, const double *, const double *, double *, double *);
+template hipError_t launch_interp<float>(ib_ctx *, const float *, const double *, double *, double *, double);
+template hipError_t launch_interp<double>(ib_ctx *, const double *, const double *, double *, double *, double);
+template hipError_t launch_adj_interp<float>(ib_ctx *, const float *, const double *, double *);
+template hipError_t launch_adj_interp<double>(ib_ctx *, const double *, const double *, double *);
+template hipError_t launch_adj_spread<float>(ib_ctx *, const float *, const double *, const double *, double *,
+                                             double *);
+template hipError_t launch_adj_spread<double>(ib_ctx *, const double *, const double *, const double *, double *,
+                                              double *);
 
 // Diagnostics (Sec. 5): displacement of chosen markers along given unit
 // directions, disp[i] = (X[idx[i]] - X0[idx[i]]) . dir[i], and its running

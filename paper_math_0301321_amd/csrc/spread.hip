@@ -8,11 +8,12 @@
 //             (formed in FP64, stored in the fluid precision), force, key;
 //   k_spread  one single-wave block per chunk of the sorted markers (equal
 //             chunks) streams the chunk, whose work items are its parts of
-//             consecutive tiles.  Markers are staged 64 at a time as F_c phi(f_x - a) and
-//             phi(f_y - b) phi(f_z - c); a cell's contribution to its 4^3
-//             nodes is a 12 x 16 contraction over its markers, done on the
-//             matrix cores and added into the wave's 11^3 halo accumulator in
-//             LDS on a cell change.  Each item's halo is
+//             consecutive tiles.  Markers are staged in LDS 32 at a time as
+//             F_c phi(f_x - a) and phi(f_y - b) phi(f_z - c); each of the 64
+//             lanes owns one of a marker's 4^3 stencil nodes and keeps
+//             running sums (vector ALU, FP32 or FP64) while consecutive
+//             markers share a cell, adding them into the wave's 11^3 halo
+//             accumulator in LDS on a cell change.  Each item's halo is
 //             written, scaled, to its own partial buffer;
 //   k_split_reduce  for tiles cut into several items, adds the items' halos
 //             in item order into the first one;

@@ -54,7 +54,8 @@ class ib_elastic(C.Structure):
 
 EXPORTS = ["ib_create", "ib_destroy", "ib_set_material", "ib_set_stream", "ib_step", "ib_force",
            "ib_spread", "ib_interp", "ib_fluid", "ib_bin", "ib_adjoint_step", "ib_adjoint_step_u", "ib_probe", "ib_last_error",
-           "ib_workspace_bytes", "ib_timers_enable", "ib_timers_select", "ib_timers_read", "ib_timer_name"]
+           "ib_workspace_bytes", "ib_timers_enable", "ib_timers_select", "ib_timers_read", "ib_timer_name",
+           "ib_graph_enable", "ib_graph_stats"]
 IB_N_TIMERS = 32
 
 _lib = None
@@ -91,6 +92,8 @@ def load_library():
     lib.ib_timers_enable.argtypes = [vp, C.c_int]
     lib.ib_timers_select.argtypes = [vp, C.c_uint32]
     lib.ib_timers_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
+    lib.ib_graph_enable.argtypes = [vp, C.c_int]
+    lib.ib_graph_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.ib_timer_name.argtypes = [C.c_int]
     lib.ib_timer_name.restype = C.c_char_p
     for name in EXPORTS:
@@ -234,6 +237,16 @@ class Context:
                 out[name.decode()] = (ms[i], int(calls[i]))
         return out
 
+    def graph_enable(self, on: bool = True):
+        """Replay the step as a HIP graph (captured per (X, u, F_out) pointers)."""
+        self._check(self.lib.ib_graph_enable(self._h, 1 if on else 0))
+
+    def graph_stats(self) -> tuple:
+        """(graphs captured, graph launches) on this context."""
+        cap, lau = C.c_int64(), C.c_int64()
+        self._check(self.lib.ib_graph_stats(self._h, C.byref(cap), C.byref(lau)))
+        return int(cap.value), int(lau.value)
+
     def set_stream(self, stream):
         self.stream = stream
         self._check(self.lib.ib_set_stream(self._h, C.c_void_p(stream)))
@@ -292,8 +305,9 @@ class Context:
     def adjoint_step(self, X_n, u_np1, t: float, Xbar, ubar, kbar, u_n=None):
         """Adjoint of one step: Xbar, ubar (n+1 -> n) in place, kbar accumulated.  With
         convect = 1, u_n (the velocity the step started from) is required."""
-        if kbar.device.type != "cuda" or kbar.dtype != torch.float64 or kbar.numel() != self.M:
-            raise ValueError("kbar must be a cuda float64 tensor with M entries")
+        if (kbar.device.type != "cuda" or kbar.dtype != torch.float64 or not kbar.is_contiguous()
+                or kbar.numel() != self.M):
+            raise ValueError("kbar must be a contiguous cuda float64 tensor with M entries")
         un = None if u_n is None else self._grid(u_n, "u_n")
         self._check(self.lib.ib_adjoint_step_u(self._h, self._markers(X_n, "X_n"), un,
                                                self._grid(u_np1, "u_np1"), float(t), self._markers(Xbar, "Xbar"),

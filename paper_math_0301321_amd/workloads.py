@@ -407,4 +407,22 @@ def random_field(N: int, seed: int = 2, comps: int = 3, Nz: int | None = None):
     return rng.standard_normal((comps, N if Nz is None else Nz, N, N))
 
 
+def smooth_field(N: int, seed: int = 2, Nz: int | None = None, kmax: int = 6, terms: int = 12):
+    """A smooth periodic random field (3, Nz, N, N): per component, a sum of
+    ``terms`` plane waves with integer wave numbers in [-kmax, kmax] along each
+    axis (periodic on the N x N x Nz grid), normalised to max |value| = 1."""
+    Nz = N if Nz is None else int(Nz)
+    rng = np.random.default_rng(seed)
+    z = np.arange(Nz)[:, None, None] / Nz
+    y = np.arange(N)[None, :, None] / N
+    x = np.arange(N)[None, None, :] / N
+    out = np.zeros((3, Nz, N, N))
+    for c in range(3):
+        for _ in range(terms):
+            kx, ky, kz = rng.integers(-kmax, kmax + 1, size=3)
+            a, ph = rng.standard_normal(), rng.uniform(0.0, 2.0 * math.pi)
+            out[c] += a * np.cos(2.0 * math.pi * (kx * x + ky * y + kz * z) + ph)
+    return out / np.abs(out).max()
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}

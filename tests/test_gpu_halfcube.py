@@ -13,7 +13,7 @@ import pytest
 import torch
 
 from paper_math_0301321_amd import workloads as W
-from tests.gpu_util import announce, dev, host, rel_max
+from tests.gpu_util import FULL_SIZE_STARTS, announce, dev, full_size_case, host, rel_max, run_from
 
 pytestmark = pytest.mark.gpu
 
@@ -172,16 +172,38 @@ def test_step_parity_multistep(ibm, oracle_mod, prec, N):
     assert eX < tol and eu < tol, (N, prec, eX, eu)
 
 
-def test_full_size_one_step(ibm, oracle_mod):
-    """256 x 256 x 128 grid, 1.5M markers (flat-spiral half-cube model): one step
-    in both precisions against the oracle."""
+@pytest.mark.parametrize("start", sorted(FULL_SIZE_STARTS))
+def test_full_size_steps(ibm, oracle_mod, start):
+    """256 x 256 x 128 grid, 1.5M markers (flat-spiral half-cube model): the step
+    in both precisions against the oracle from a non-trivial state (from rest
+    over three steps, the drive on from the second; or a smooth random flow)."""
     wl = W.halfcube(256)
-    announce("half-cube full-size one step", wl.N, wl.nz, wl.M)
-    Xo, uo = oracle_mod.run(wl, 1)
+    announce("half-cube full-size steps", start, wl.N, wl.nz, wl.M)
+    u0, Xo, uo = full_size_case(oracle_mod, wl, start)
+    cfg = FULL_SIZE_STARTS[start]
     for prec, tol in (("fp64", 1e-10), ("fp32", 1e-5)):
-        Xg, ug = _run_gpu(ibm, wl, prec, 1)
+        Xg, ug = run_from(ibm, wl, prec, wl.X0, u0, cfg["n0"], cfg["n_steps"])
         eX, eu = rel_max(Xg - wl.X0, Xo - wl.X0), rel_max(ug, uo)
-        assert eX < tol and eu < tol, (prec, eX, eu)
+        print(f"[gpu-case] half-cube full-size {start} {prec}: rel u {eu:.3e}, rel dX {eX:.3e}", flush=True)
+        assert eX < tol and eu < tol, (start, prec, eX, eu)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_fluid(ibm, oracle_mod, prec):
+    """ib_fluid on the 256 x 256 x 128 grid (the passes the half-cube benchmark
+    times) on a random field with advection and a random force."""
+    N = 256
+    u = 0.5 * W.random_field(N, seed=72, Nz=N // 2)
+    F = 100.0 * W.random_field(N, seed=73, Nz=N // 2)
+    if prec == "fp32":
+        u, F = u.astype(np.float32).astype(np.float64), F.astype(np.float32).astype(np.float64)
+    wl = _free_wl(N, np.zeros((3, 0)), 1)
+    announce("half-cube full-size fluid", prec)
+    ctx = ibm.Context(wl, prec)
+    ut = dev(u, _fd(prec))
+    ctx.fluid(ut, dev(F, _fd(prec)))
+    uo = oracle_mod.fluid(N, 1.0, wl.rho, wl.mu, wl.dt, 1, u, F)
+    assert rel_max(host(ut), uo) < TOL1[prec]
 
 
 @pytest.mark.parametrize("convect", [0, 1])

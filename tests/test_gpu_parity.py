@@ -16,7 +16,7 @@ import pytest
 import torch
 
 from paper_math_0301321_amd import workloads as W
-from tests.gpu_util import announce, dev, host, rel_max
+from tests.gpu_util import FULL_SIZE_STARTS, announce, dev, full_size_case, host, rel_max, run_from
 
 pytestmark = pytest.mark.gpu
 
@@ -207,6 +207,25 @@ def test_step_force_output_and_no_markers(ibm, oracle_mod):
     assert rel_max(host(ut), oracle_mod.fluid(16, 1.0, 1.0, 0.01, 1e-3, 1, u0)) < 1e-12
 
 
+def test_checked_mode_reports_nonfinite(ibm, monkeypatch):
+    """IB_CHECK=1: every call synchronises and scans its outputs; a NaN planted
+    in the velocity (a value the kernels carry through without faulting: the
+    binning maps a non-finite position to cell 0) comes back as IB_ENONFINITE."""
+    monkeypatch.setenv("IB_CHECK", "1")
+    wl = W.tiny_helix()
+    announce("checked mode, planted NaN")
+    ctx = ibm.Context(wl, "fp32")
+    X = dev(wl.X0)
+    u = ctx.new_grid()
+    ctx.step(X, u, 0.0)
+    ctx.step(X, u, wl.dt)
+    u[1, 5, 6, 7] = float("nan")
+    with pytest.raises(ibm.IBError) as ei:
+        ctx.step(X, u, 2 * wl.dt)
+    assert ei.value.code == ibm.IB_ENONFINITE
+    assert "non-finite" in str(ei.value)
+
+
 def test_step_deterministic(ibm):
     wl = W.tiny_helix()
     announce("determinism")
@@ -215,15 +234,39 @@ def test_step_deterministic(ibm):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-def test_full_size_one_step(ibm, oracle_mod):
-    """256^3 grid, 1.5M markers: one step in both precisions against the oracle."""
+@pytest.mark.parametrize("start", sorted(FULL_SIZE_STARTS))
+def test_full_size_steps(ibm, oracle_mod, start):
+    """256^3 grid, 1.5M markers, the launch configuration the benchmark times:
+    the step in both precisions against the oracle from a non-trivial state."""
     wl = W.config3()
-    announce("full-size one step", wl.N, wl.M)
-    Xo, uo = oracle_mod.run(wl, 1)
+    announce("full-size steps", start, wl.N, wl.M)
+    u0, Xo, uo = full_size_case(oracle_mod, wl, start)
+    cfg = FULL_SIZE_STARTS[start]
     for prec, tol in (("fp64", 1e-10), ("fp32", 1e-5)):
-        Xg, ug = _run_gpu(ibm, wl, prec, 1)
+        # the mixed step starts from u0 rounded to FP32 (6e-8 relative, far below its bound)
+        Xg, ug = run_from(ibm, wl, prec, wl.X0, u0, cfg["n0"], cfg["n_steps"])
         eX, eu = rel_max(Xg - wl.X0, Xo - wl.X0), rel_max(ug, uo)
-        assert eX < tol and eu < tol, (prec, eX, eu)
+        print(f"[gpu-case] full-size {start} {prec}: rel u {eu:.3e}, rel dX {eX:.3e}", flush=True)
+        assert eX < tol and eu < tol, (start, prec, eX, eu)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_fluid(ibm, oracle_mod, prec):
+    """ib_fluid at 256^3 (the fused RHS + x transform, y, z-solve, inverse y and
+    x passes instantiated for n = 256) on a random field with advection and a
+    random force: each term changes u by about 10%."""
+    N = 256
+    u = 0.5 * W.random_field(N, seed=34)
+    F = 100.0 * W.random_field(N, seed=35)
+    if prec == "fp32":
+        u, F = u.astype(np.float32).astype(np.float64), F.astype(np.float32).astype(np.float64)
+    wl = _free_markers_wl(N, np.zeros((3, 0)))
+    announce("full-size fluid", prec, N)
+    ctx = ibm.Context(wl, prec)
+    ut = dev(u, _fluid_dtype(prec))
+    ctx.fluid(ut, dev(F, _fluid_dtype(prec)))
+    uo = oracle_mod.fluid(N, 1.0, wl.rho, wl.mu, wl.dt, 1, u, F)
+    assert rel_max(host(ut), uo) < TOL_FLUID[prec]
 
 
 # --------------------------------------------------------------------------
@@ -292,3 +335,43 @@ def test_mixed_velocity_error_after_100_steps(ibm, oracle_mod):
         errs[prec] = (eu, eX)
         print(f"[gpu-case] 100 steps {prec}: rel u {eu:.3e}, rel dX {eX:.3e}", flush=True)
         assert eu <= tol and eX <= tol, (prec, eu, eX)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("freq", W.C3_FREQS)
+def test_config3_sweep_window(ibm, oracle_mod, freq):
+    """The 256^3 workload's four drive frequencies (the paper's 2 : 5 : 10 : 15
+    ratio, scaled) on its 64^3 replica with the same 1.5M markers and time
+    step, over the 64-step window, checked every 8 steps: the mixed step within
+    1e-5 of the FP64 oracle in velocity and marker displacement, the FP64 step
+    within 1e-9.  Over a window each field's error is measured against that
+    field's largest magnitude over the window: the driven flow reverses, and at
+    a reversal the velocity's own maximum is 10-30 times below its peak."""
+    wl = W.config3(64, freq=freq)
+    marks = tuple(range(8, 65, 8))
+    announce("config3 sweep window", wl.N, wl.M, freq)
+    ref = {}
+
+    def keep(n, X, u):
+        if n in marks:
+            ref[n] = (X - wl.X0, u.copy())
+            print(f"[gpu-case] oracle step {n}", flush=True)
+
+    oracle_mod.run(wl, marks[-1], callback=keep)
+    scale_u = max(np.abs(ref[n][1]).max() for n in marks)
+    scale_X = max(np.abs(ref[n][0]).max() for n in marks)
+    assert scale_u > 0 and scale_X > 0
+    for prec, tol in (("fp64", 1e-9), ("fp32", 1e-5)):
+        ctx = ibm.Context(wl, prec)
+        X = dev(wl.X0)
+        u = ctx.new_grid()
+        err_u = err_X = 0.0
+        for n in range(marks[-1]):
+            ctx.step(X, u, n * wl.dt)
+            if n + 1 in marks:
+                dXo, uo = ref[n + 1]
+                err_u = max(err_u, np.abs(host(u) - uo).max())
+                err_X = max(err_X, np.abs(host(X) - wl.X0 - dXo).max())
+        eu, eX = err_u / scale_u, err_X / scale_X
+        print(f"[gpu-case] config3 window {freq:g} Hz {prec}: rel u {eu:.3e}, rel dX {eX:.3e}", flush=True)
+        assert eu < tol and eX < tol, (freq, prec, eu, eX)

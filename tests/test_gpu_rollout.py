@@ -200,3 +200,30 @@ def test_rollout_advection_vs_finite_differences(mods):
     for eps in (1e-4, 1e-3):
         dfd = (loss(wl.k + eps * v) - loss(wl.k - eps * v)) / (2 * eps)
         assert abs(gv - dfd) <= 1e-4 * abs(gv), (eps, gv, dfd)
+
+
+@pytest.mark.timeout(900)
+def test_rollout_config5_replica_vs_oracle_gradient(mods, oracle_mod):
+    """The adjoint at scale on its 64^3 replica: the 256^3 workload's 1.5M
+    markers and time step, 100 forward and 100 adjoint steps with a checkpoint
+    every 20; the loss and the stiffness gradient against the FP64 oracle's
+    reverse-mode gradient, in both precisions (tolerances as for the 128^3
+    adjoint workload: the nm strains limit the conditioning)."""
+    ib, rollout = mods
+    wl = W.config5(64)
+    idx = wl.meta["loss_idx"]
+    n, ck = wl.n_steps, wl.meta["ckpt"]
+    announce("config5 replica oracle gradient", wl.N, wl.M, n, ck)
+    def progress(phase, k):
+        if k % 10 == 0:
+            print(f"[gpu-case] oracle {phase} step {k}", flush=True)
+
+    Lo, kbo, _, _ = oracle_mod.gradient_k(wl, n, idx, progress=progress)
+    assert Lo > 0 and np.abs(kbo).max() > 0
+    for prec, tol, ltol in (("fp64", 1e-4, 1e-5), ("fp32", 5e-3, 2e-5)):
+        L, kb = _gpu_grad(ib, rollout, wl, prec, n, ck, idx)
+        print(f"[gpu-case] config5 replica {prec}: loss rel {abs(L - Lo) / Lo:.3e}, "
+              f"kbar rel L2 {_rel_l2(kb, kbo):.3e}", flush=True)
+        assert abs(L - Lo) <= ltol * Lo, (prec, L, Lo)
+        assert _rel_l2(kb, kbo) < tol, (prec, _rel_l2(kb, kbo))
+
