@@ -7,8 +7,11 @@ are large) the FP64 kbar matches the oracle to 1e-9 and the mixed one to 1e-4
 stiffness gradient is set by strains that FP64 positions (~0.5 cm, ulp 1e-16)
 resolve only to ~1e-5 relative: a 1-ulp perturbation of X0 moves the oracle's
 own kbar by 3e-4 (measured, 20 steps).  There FP64 kbar must match the oracle
-to 1e-4 and the mixed one (FP32 velocity rounding perturbs the strains far
-above FP64 roundoff; measured 2.5e-3) to 5e-3.  Finite differences are taken
+to 1e-4.  In the mixed step the interpolation and the adjoint's gathers use
+FP64 weights and sums, so neighbouring markers' velocity differences keep the
+FP32 grid's relative accuracy (with FP32 weights the 1.5M-marker replica's
+mixed kbar was 8.6e-3 off; with FP64 weights 3.5e-4); the bounds are 5e-3 on
+the 128^3 workload and 1e-3 on the 1.5M-marker replica.  Finite differences are taken
 along directions over all membrane stiffnesses, where the loss change is far
 above its roundoff (agreement <= 1e-4); per-marker differences are roundoff
 limited to ~3e-4 even with a 100x drive, and are checked to 1e-3.
@@ -167,6 +170,8 @@ def test_rollout_config4_vs_oracle_gradient(mods, oracle_mod):
     Lo, kbo, _, _ = oracle_mod.gradient_k(wl, wl.n_steps, idx)
     for prec, tol, ltol in (("fp64", 1e-4, 1e-5), ("fp32", 5e-3, 2e-5)):
         L, kb = _gpu_grad(ib, rollout, wl, prec, wl.n_steps, wl.meta["ckpt"], idx)
+        print(f"[gpu-case] config4 {prec}: loss rel {abs(L - Lo) / Lo:.3e}, kbar rel L2 {_rel_l2(kb, kbo):.3e}",
+              flush=True)
         assert abs(L - Lo) <= ltol * Lo, (prec, L, Lo)
         assert _rel_l2(kb, kbo) < tol, (prec, _rel_l2(kb, kbo))
 
@@ -220,7 +225,11 @@ def test_rollout_config5_replica_vs_oracle_gradient(mods, oracle_mod):
 
     Lo, kbo, _, _ = oracle_mod.gradient_k(wl, n, idx, progress=progress)
     assert Lo > 0 and np.abs(kbo).max() > 0
-    for prec, tol, ltol in (("fp64", 1e-4, 1e-5), ("fp32", 5e-3, 2e-5)):
+    # mixed: the loss window moves ~300 times less than the workload's largest
+    # displacement, and the mixed step's displacement error there is 2e-5 of
+    # the window's own scale (6e-6 of the largest; the same with FP32 or FP64
+    # interpolation weights), so the quadratic loss carries up to twice that
+    for prec, tol, ltol in (("fp64", 1e-4, 1e-5), ("fp32", 1e-3, 5e-5)):
         L, kb = _gpu_grad(ib, rollout, wl, prec, n, ck, idx)
         print(f"[gpu-case] config5 replica {prec}: loss rel {abs(L - Lo) / Lo:.3e}, "
               f"kbar rel L2 {_rel_l2(kb, kbo):.3e}", flush=True)
