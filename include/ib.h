@@ -153,6 +153,22 @@ int ib_interp(ib_ctx *c, const double *X, const void *u, double *U);
  * (nullable: no body force). */
 int ib_fluid(ib_ctx *c, void *u, const void *F_grid);
 
+/* ib_fluid without a context, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Reads n, nz, L, rho, mu, dt, fluid_precision, convect and
+ * stream from *p (n_markers is ignored) and updates u^n -> u^{n+1} in place
+ * given F_grid (nullable: no body force), as ib_fluid does, on that stream.
+ * Its spectrum and tables live in a static device array of 32 MiB that every
+ * GPU the library runs on holds until the process ends; it calls no device
+ * allocator.  Sizes: n in {32, 64, 128, 256}, nz in {0, n, n/2}, and the
+ * spectrum, 3 (n/2+1) n nz complex values in the fluid precision, plus the
+ * tables within 32 MiB (FP32: up to 128^3 and 128 x 128 x 64; FP64: up to
+ * 64^3 and 128 x 128 x 64); IB_ENOTSUP for larger grids, IB_EINVAL for bad
+ * parameters, IB_EDEVICE on a launch failure, the text in ib_last_error(NULL).
+ * Calls on one GPU share the array: calls that overlap on one GPU (other
+ * streams, other threads) race. */
+int ib_fluid_noalloc(const ib_params *p, void *u, const void *F_grid);
+
 /* The binning that partitions markers among grid cells (Sec. 3.3): the cell
  * of marker q is c = floor(X_q / h) per dimension wrapped into [0, n) ([0, nz)
  * along z); cells are grouped in 8^3 tiles,
@@ -190,7 +206,7 @@ int ib_probe(ib_ctx *c, const double *X, const double *X0, const int32_t *idx, c
              int64_t count, double *disp, double *env);
 
 /* Text of the last error on this context ("" if none); c may be NULL for the
- * last ib_create failure. */
+ * last error of ib_create or ib_fluid_noalloc on this thread. */
 const char *ib_last_error(const ib_ctx *c);
 
 /* Device bytes held by the context's workspace. */

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libib.so")
-SOURCES = ["api.hip", "bin.hip", "force.hip", "spread.hip", "fluid.hip", "fft_reg.hip", "interp.hip"]
+SOURCES = ["api.hip", "bin.hip", "force.hip", "spread.hip", "fluid.hip", "fft_reg.hip", "interp.hip", "noalloc.hip"]
 ARCH = os.environ.get("IB_OFFLOAD_ARCH", "gfx950")
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
 HIPCC_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",

@@ -19,7 +19,9 @@ int sort_hist_words(int64_t M, int digit_bits);
 
 using namespace ib;
 
-static thread_local std::string g_create_error;
+static thread_local std::string g_create_error;   // last error of a call without a context
+
+void ib::set_context_free_error(const std::string &msg) { g_create_error = msg; }
 static const double kPi = 3.14159265358979323846;
 
 #define IB_TRY(expr)                                                                         \

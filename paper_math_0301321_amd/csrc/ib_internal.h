@@ -245,6 +245,9 @@ hipError_t launch_probe(ib_ctx *c, const double *X, const double *X0, const int3
 template <typename T>
 hipError_t launch_adv_adjoint(ib_ctx *c, const T *u_n, T *ubar, T *tmp);
 
+// text returned by ib_last_error(NULL)
+void set_context_free_error(const std::string &msg);
+
 // instrumentation: event pair around a phase when timing is on
 void timer_begin(ib_ctx *c, int phase);
 void timer_end(ib_ctx *c);

@@ -55,7 +55,7 @@ class ib_elastic(C.Structure):
 EXPORTS = ["ib_create", "ib_destroy", "ib_set_material", "ib_set_stream", "ib_step", "ib_force",
            "ib_spread", "ib_interp", "ib_fluid", "ib_bin", "ib_adjoint_step", "ib_adjoint_step_u", "ib_probe", "ib_last_error",
            "ib_workspace_bytes", "ib_timers_enable", "ib_timers_select", "ib_timers_read", "ib_timer_name",
-           "ib_graph_enable", "ib_graph_stats"]
+           "ib_graph_enable", "ib_graph_stats", "ib_fluid_noalloc"]
 IB_N_TIMERS = 32
 
 _lib = None
@@ -92,6 +92,7 @@ def load_library():
     lib.ib_timers_enable.argtypes = [vp, C.c_int]
     lib.ib_timers_select.argtypes = [vp, C.c_uint32]
     lib.ib_timers_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
+    lib.ib_fluid_noalloc.argtypes = [C.POINTER(ib_params), vp, vp]
     lib.ib_graph_enable.argtypes = [vp, C.c_int]
     lib.ib_graph_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.ib_timer_name.argtypes = [C.c_int]
@@ -105,6 +106,28 @@ def load_library():
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def fluid_noalloc(u, F=None, *, L=1.0, rho=1.0, mu=0.01, dt=1e-3, convect=1, stream=None):
+    """ib_fluid_noalloc: u^n -> u^{n+1} in place without a context (no device
+    allocation; the library's static scratch).  u, F: contiguous cuda tensors of
+    shape (3, nz, n, n), float32 or float64 (the fluid precision)."""
+    lib = load_library()
+    if u.device.type != "cuda" or u.dtype not in (torch.float32, torch.float64) or not u.is_contiguous() \
+            or u.dim() != 4 or u.shape[0] != 3 or u.shape[2] != u.shape[3]:
+        raise ValueError("u must be a contiguous cuda float32/float64 tensor of shape (3, nz, n, n)")
+    if F is not None and (F.device != u.device or F.dtype != u.dtype or not F.is_contiguous()
+                          or F.shape != u.shape):
+        raise ValueError("F must be a contiguous tensor like u")
+    n, nz = int(u.shape[3]), int(u.shape[1])
+    if stream is None:
+        stream = torch.cuda.current_stream(u.device).cuda_stream
+    p = ib_params(n, float(L), float(rho), float(mu), float(dt),
+                  IB_FLUID_FP32 if u.dtype == torch.float32 else IB_FLUID_FP64, int(convect), 0,
+                  C.c_void_p(stream), nz)
+    rc = lib.ib_fluid_noalloc(C.byref(p), _ptr(u), _ptr(F))
+    if rc != IB_OK:
+        raise IBError(rc, lib.ib_last_error(None).decode())
 
 
 class Context:

@@ -120,6 +120,31 @@ def test_null_context_calls_fail_cleanly():
     assert lib.ib_workspace_bytes(None) == 0
 
 
+def test_fluid_noalloc_validates_before_any_device_call():
+    """Sizes beyond the static scratch and bad parameters are refused with a
+    clear error before the entry point touches a device."""
+    from paper_math_0301321_amd import ib
+    lib = _lib()
+    fake = C.c_void_p(0x1000)       # never dereferenced: validation fails first
+
+    def params(n, nz=0, prec=ib.IB_FLUID_FP32, **kw):
+        d = dict(L=1.0, rho=1.0, mu=0.01, dt=1e-3, convect=1)
+        d.update(kw)
+        return ib.ib_params(n, d["L"], d["rho"], d["mu"], d["dt"], prec, d["convect"], 0, None, nz)
+
+    assert lib.ib_fluid_noalloc(None, fake, None) == ib.IB_EINVAL
+    assert lib.ib_fluid_noalloc(C.byref(params(64)), None, None) == ib.IB_EINVAL
+    for n, nz in ((48, 0), (16, 0), (512, 0), (64, 16)):
+        assert lib.ib_fluid_noalloc(C.byref(params(n, nz)), fake, None) == ib.IB_ENOTSUP, (n, nz)
+    for kw in (dict(rho=0.0), dict(dt=-1.0), dict(mu=-1.0), dict(convect=2), dict(L=float("nan"))):
+        assert lib.ib_fluid_noalloc(C.byref(params(64, **kw)), fake, None) == ib.IB_EINVAL, kw
+    # beyond 32 MiB: 256^3 in FP32 (203 MB of spectrum), 128^3 in FP64 (51 MB)
+    for n, nz, prec in ((256, 0, ib.IB_FLUID_FP32), (256, 128, ib.IB_FLUID_FP32), (128, 0, ib.IB_FLUID_FP64)):
+        assert lib.ib_fluid_noalloc(C.byref(params(n, nz, prec)), fake, None) == ib.IB_ENOTSUP, (n, nz, prec)
+        msg = lib.ib_last_error(None).decode()
+        assert "limit is 33554432" in msg, msg
+
+
 def _imports(path):
     tree = ast.parse(open(path).read())
     out = set()
