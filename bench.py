@@ -199,6 +199,14 @@ def extras(wl, n=10):
     torch.cuda.synchronize()
     out["window128_steps_per_s"] = round(50 / (e0.elapsed_time(e1) / 1e3), 2)
     out["window128_markers"] = wlw.M
+    # and with every marker's position written every tenth step (host file under /tmp)
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        t0 = time.perf_counter()
+        D.run_with_output(cw, wlw, Xw, uw, 100, every=10, t0_step=60, positions=os.path.join(td, "X.npy"))
+        torch.cuda.synchronize()
+        out["window128_positions_every10_steps_per_s"] = round(100 / (time.perf_counter() - t0), 2)
+        out["window128_positions_bytes_per_record"] = 24 * wlw.M
     del cw, uw
     # the half-cube model (256 x 256 x 128, the grid of the paper's reported runs)
     wlh = W.halfcube(256)
