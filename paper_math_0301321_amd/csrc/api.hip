@@ -402,7 +402,7 @@ extern "C" void ib_destroy(ib_ctx *c) {
 // ------------------------------------------------------ instrumentation ----
 static const char *kPhaseNames[PH_COUNT] = {"bin", "force", "prep", "spread", "split", "gather", "rhs", "fft_x", "fft_y",
                                             "fft_z_solve", "fft_y_inv", "fft_x_inv", "interp", "adj_interp",
-                                            "adj_spread", "hessvec", "rhs_fft_x", "adj_advect"};
+                                            "adj_spread", "hessvec", "rhs_fft_x", "adj_advect", "fft_yx_inv"};
 
 static void timers_fold(ib_ctx *c) {
   if (c->tused == 0) return;

@@ -615,6 +615,111 @@ __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xi(
     }
 }
 
+// --------------------------------------- passes y and x, inverse, merged ----
+// One 1024-thread block per (component, z) plane: the inverse y transforms of
+// its n/2 + 1 kx pencils (each contiguous in the spectrum), kept in registers
+// (two pencils per 16-thread slot; the kx = n/2 pencil by slot 0 into LDS),
+// then for each half of the y rows an LDS transpose [y][kx] and the inverse x
+// transforms, two real rows per complex pencil, written as rows of u.  The
+// spectrum is read once and u written once: one pass over HBM for the two
+// transforms.  n = 256 (R1 = R2 = 16) in FP32: the plane's spectrum (264 KB)
+// fits the block's registers, the transpose of half the rows its LDS.
+template <typename T, int R1, int R2>
+struct YxiCfg {
+  static constexpr int N = R1 * R2, NH = N / 2 + 1, P = R1 < R2 ? R1 : R2;
+  static constexpr int SLOTS = 1024 / P;           // pencil slots of the block
+  static constexpr int HALF = N / 2;               // y rows per transpose
+  static constexpr int TS = NH;                    // transpose row stride (complex)
+  static constexpr size_t XCH = sizeof(cplx<T>) * SLOTS * R1 * (R2 + 1);   // pencil exchange space
+  static constexpr size_t TB = sizeof(cplx<T>) * HALF * TS;                // transpose, over the exchange space
+  static constexpr size_t BYTES = (XCH > TB ? XCH : TB) + sizeof(cplx<T>) * N;   // + the kx = n/2 pencil
+  static_assert(2 * SLOTS + 1 == NH && HALF == 2 * SLOTS, "two pencils per slot (and one more), two rows per x pencil");
+};
+
+template <typename T, int R1, int R2>
+__global__ __launch_bounds__(1024) void k_yxi(const cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ tw,
+                                              T scale, T *__restrict__ u, int nz) {
+  using C = YxiCfg<T, R1, R2>;
+  using F4 = Fft4<T, R1, R2, true, false>;
+  constexpr int N = C::N, NH = C::NH, P = C::P, E = F4::E, TS = C::TS;
+  static_assert(R2 / P == 1 && R1 / P == 1, "square four-step factors");
+  __shared__ __attribute__((aligned(16))) unsigned char smem[C::BYTES];
+  const int64_t G = (int64_t)N * N * nz;
+  const int c = blockIdx.x / nz, z = blockIdx.x % nz;
+  const int s = threadIdx.x / P, t = threadIdx.x % P;
+  cplx<T> *xch = (cplx<T> *)smem + s * R1 * (R2 + 1);
+  cplx<T> *tr = (cplx<T> *)smem;                   // [HALF][TS] after the y transforms
+  cplx<T> *nyq = (cplx<T> *)(smem + (C::XCH > C::TB ? C::XCH : C::TB));   // [N] the kx = n/2 pencil
+  auto pencil = [&](int kx) { return spec + (((int64_t)c * NH + kx) * nz + z) * N; };
+  // 1. inverse y transforms: kx = n/2 by slot 0 (into LDS), then pencils s and
+  // s + SLOTS (kx) of every slot, kept in registers
+  if (s == 0) {   // lanes 0 .. P-1 of wave 0 (the pencil's exchange is wave-local)
+    cplx<T> vn[E];
+    const cplx<T> *gn = pencil(N / 2);
+#pragma unroll
+    for (int j = 0; j < R1; j++) vn[j] = gn[t + R2 * j];
+    F4::run(vn, t, xch, tw);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; k2++) nyq[t + R1 * k2] = vn[k2];
+  }
+  cplx<T> va[E], vb[E];
+  {
+    const cplx<T> *ga = pencil(s);
+#pragma unroll
+    for (int j = 0; j < R1; j++) va[j] = ga[t + R2 * j];
+  }
+  F4::run(va, t, xch, tw);                          // y = t + R1 k2 in slot k2
+  {
+    const cplx<T> *gb = pencil(s + C::SLOTS);
+#pragma unroll
+    for (int j = 0; j < R1; j++) vb[j] = gb[t + R2 * j];
+  }
+  F4::run(vb, t, xch, tw);
+  // 2. per half of the rows: transpose to [y][kx], inverse x transforms of
+  // row pairs (2r, 2r + 1), r = s, and the rows written out
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    __syncthreads();   // the previous half's exchange space is free
+#pragma unroll
+    for (int k2 = 0; k2 < R2 / 2; k2++) {
+      const int yl = t + R1 * k2;                  // row within the half
+      tr[yl * TS + s] = va[k2 + h * R2 / 2];
+      tr[yl * TS + s + C::SLOTS] = vb[k2 + h * R2 / 2];
+    }
+    __syncthreads();
+    const int r0 = 2 * s;
+    cplx<T> v[E];
+#pragma unroll
+    for (int j = 0; j < R1; j++) {
+      const int k = t + R2 * j;
+      const bool hi = k > N / 2;
+      const int kk = hi ? N - k : k;
+      cplx<T> a = kk == N / 2 ? nyq[h * C::HALF + r0] : tr[r0 * TS + kk];
+      cplx<T> b = kk == N / 2 ? nyq[h * C::HALF + r0 + 1] : tr[(r0 + 1) * TS + kk];
+      if (hi) {
+        a.y = -a.y;
+        b.y = -b.y;
+      }
+      v[j] = cplx<T>{a.x - b.y, a.y + b.x};
+    }
+    __syncthreads();   // the transpose is consumed: its space becomes exchange space
+    F4::run(v, t, xch, tw);
+    T *ra = u + c * G + ((int64_t)z * N + h * C::HALF + r0) * N;
+#pragma unroll
+    for (int k2 = 0; k2 < R2; k2++) {
+      const int x = t + R1 * k2;
+      ra[x] = v[k2].x * scale;
+      ra[N + x] = v[k2].y * scale;
+    }
+  }
+}
+
+// The merged inverse y + x pass serves n = 256 in FP32.
+template <typename T, int R1, int R2>
+constexpr bool yx_merged() {
+  return sizeof(T) == 4 && R1 == 16 && R2 == 16;
+}
+
 // (R1, R2): factors of n (x and y); (Z1, Z2): factors of nz (z).
 template <typename T, int R1, int R2, int Z1, int Z2>
 hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect, double f_scale, T *u_out) {
@@ -646,6 +751,12 @@ hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect
     PhaseScope ps(c, PH_FFT_Z_SOLVE);
     hipLaunchKernelGGL((k_z_solve<T, Z1, Z2, N>), dim3(NH * (N / YB)), dim3(YB * PZ), 0, c->stream, spec, tw,
                        (const T *)c->ws.lam, (const T *)c->ws.sgrad, (T)(c->p.mu * c->p.dt / c->p.rho));
+  }
+  if constexpr (yx_merged<T, R1, R2>()) {
+    PhaseScope ps(c, PH_FFT_YX_INV);
+    hipLaunchKernelGGL((k_yxi<T, R1, R2>), dim3(3 * NZ), dim3(1024), 0, c->stream, (const cplx<T> *)spec, tw,
+                       (T)(1.0 / (double)c->G), u_out, nz);
+    return hipGetLastError();
   }
   {
     PhaseScope ps(c, PH_FFT_Y_INV);

@@ -137,7 +137,8 @@ struct Workspace {
 // Phases timed by the optional HIP-event instrumentation.
 enum Phase {
   PH_BIN = 0, PH_FORCE, PH_PREP, PH_SPREAD, PH_SPLIT, PH_GATHER, PH_RHS, PH_FFT_X, PH_FFT_Y, PH_FFT_Z_SOLVE,
-  PH_FFT_Y_INV, PH_FFT_X_INV, PH_INTERP, PH_ADJ_INTERP, PH_ADJ_SPREAD, PH_HESSVEC, PH_RHS_FFT_X, PH_ADJ_ADVECT, PH_COUNT
+  PH_FFT_Y_INV, PH_FFT_X_INV, PH_INTERP, PH_ADJ_INTERP, PH_ADJ_SPREAD, PH_HESSVEC, PH_RHS_FFT_X, PH_ADJ_ADVECT,
+  PH_FFT_YX_INV, PH_COUNT
 };
 
 struct TimerRec {
