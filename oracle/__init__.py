@@ -42,7 +42,8 @@ class _Model(C.Structure):
                 ("spring_ab", _i32p), ("spring_rest", _dp), ("K_spring", C.c_double),
                 ("n_drive", C.c_int64),
                 ("drive_idx", _i32p), ("drive_dir", _dp),
-                ("drive_A", C.c_double), ("drive_freq", C.c_double)]
+                ("drive_A", C.c_double), ("drive_freq", C.c_double),
+                ("disp", C.c_int32)]
 
 
 def lib():
@@ -69,10 +70,15 @@ def _ptr(a, t=_dp):
 
 
 class Model:
-    """Holds contiguous copies of a workload's material arrays for the C oracle."""
+    """Holds contiguous copies of a workload's material arrays for the C oracle.
 
-    def __init__(self, wl, k=None):
+    ``displacement=True``: every marker array passed with this model holds
+    displacements D = X - X_ref instead of positions (the elastic terms are
+    then formed from D, positions as X_ref + D)."""
+
+    def __init__(self, wl, k=None, displacement=False):
         self.M = wl.M
+        self.disp = bool(displacement)
         self.w = _f64(wl.w)
         self.k = _f64(wl.k if k is None else k)
         self.X_ref = _f64(wl.X_ref)
@@ -98,7 +104,7 @@ class Model:
             n_springs=self.sab.shape[1], spring_ab=_ptr(self.sab, _i32p),
             spring_rest=_ptr(self.srest), K_spring=float(wl.K_spring),
             n_drive=self.didx.shape[0], drive_idx=_ptr(self.didx, _i32p), drive_dir=_ptr(self.ddir),
-            drive_A=float(wl.drive_A), drive_freq=float(wl.drive_freq))
+            drive_A=float(wl.drive_A), drive_freq=float(wl.drive_freq), disp=int(self.disp))
 
     def ref(self):
         return C.byref(self.s)
@@ -142,6 +148,19 @@ def force(model: Model, X, t):
     F = np.zeros_like(X)
     lib().ibo_force(model.ref(), _ptr(X), C.c_double(t), _ptr(F))
     return F
+
+
+def positions(model: Model, X):
+    """Marker positions of the state X: X itself, or X_ref + X for a displacement model."""
+    X = _f64(X)
+    P = np.zeros_like(X)
+    lib().ibo_positions(model.ref(), _ptr(X), _ptr(P))
+    return P
+
+
+def initial_state(wl, displacement=False):
+    """The workload's initial marker state: X0, or X0 - X_ref as displacements."""
+    return _f64(wl.X0 - wl.X_ref) if displacement else _f64(wl.X0).copy()
 
 
 def energy(model: Model, X):
@@ -228,11 +247,12 @@ def step(model: Model, wl, X, u, t, N=None, convect=None, return_force=False):
     return (X, u, F) if return_force else (X, u)
 
 
-def run(wl, n_steps, X=None, u=None, N=None, k=None, convect=None, t0_step=0, callback=None):
-    """n_steps time steps from (X, u) (default: the workload's initial state, fluid at rest)."""
+def run(wl, n_steps, X=None, u=None, N=None, k=None, convect=None, t0_step=0, callback=None, displacement=False):
+    """n_steps time steps from (X, u) (default: the workload's initial state, fluid at rest);
+    with ``displacement`` the marker state is D = X - X_ref."""
     N = wl.N if N is None else N
-    model = Model(wl, k)
-    X = _f64(wl.X0 if X is None else X).copy()
+    model = Model(wl, k, displacement)
+    X = (initial_state(wl, displacement) if X is None else _f64(X)).copy()
     u = np.zeros((3, wl.nz * N // wl.N, N, N)) if u is None else _f64(u).copy()
     for n in range(t0_step, t0_step + n_steps):
         X, u = step(model, wl, X, u, n * wl.dt, N=N, convect=convect)
@@ -259,16 +279,18 @@ def adjoint_step(model: Model, wl, X_n, u_np1, t, Xbar, ubar, kbar, N=None, conv
     return Xb, ub, kb
 
 
-def gradient_k(wl, n_steps, loss_idx, N=None, k=None, X0=None, convect=0, progress=None):
+def gradient_k(wl, n_steps, loss_idx, N=None, k=None, X0=None, convect=0, progress=None, displacement=False):
     """Loss L = (1/|W|) sum_{q in W} |X_q^T - X_q^0|^2 after n_steps steps (Stokes,
     or with the upwind advection when convect = 1) from (X0, u = 0), and its
     gradient with respect to the per-marker stiffness k, by the adjoint step run
     backwards over stored states.  Returns (L, kbar, Xbar0, ubar0).
     ``progress(phase, n)``, when given, is called after every step of the
-    forward ("forward") and reverse ("adjoint") sweeps."""
+    forward ("forward") and reverse ("adjoint") sweeps.  With ``displacement``
+    the marker state (and X0) are displacements from X_ref; the loss is the
+    same (X^T - X^0 = D^T - D^0)."""
     N = wl.N if N is None else N
-    model = Model(wl, k)
-    X0 = _f64(wl.X0 if X0 is None else X0)
+    model = Model(wl, k, displacement)
+    X0 = initial_state(wl, displacement) if X0 is None else _f64(X0)
     idx = np.asarray(loss_idx, dtype=np.int64)
     Xs, us = [X0.copy()], [np.zeros((3, wl.nz * N // wl.N, N, N))]
     for n in range(n_steps):

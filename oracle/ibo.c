@@ -97,6 +97,10 @@ void ibo_bin(int N, int Nz, double L, int64_t M, const double *X, uint32_t *keys
  *   tether q:                     E = 1/2 kappa_q w_q |Xq - Yq|^2;
  * plus the window drive A w_q sin(2 pi f t) n_q (Sec. 4, oval window).
  * Y = X_ref.  Each marker's force is f(q) dq (area weight included).
+ * With disp = 1 the state holds D = X - Y: an edge vector is formed as
+ * (Yb - Ya) + (Db - Da), the bend's second difference as Da - 2Dc + Db and
+ * the tether's offset as D itself (the same quantities, each with the
+ * relative precision of the displacements).
  * ---------------------------------------------------------------------- */
 static inline double norm3(const double v[3]) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
 
@@ -108,13 +112,49 @@ static void addp(double *A, int64_t M, int64_t q, const double v[3], double s) {
   A[q] += s * v[0]; A[M + q] += s * v[1]; A[2 * M + q] += s * v[2];
 }
 
+/* Edge vector Xb - Xa of the state X: positions (disp = 0), or
+ * (Yb - Ya) + (Db - Da) from displacements D (disp = 1). */
+static void edge_vec(const ibo_model *m, const double *X, int64_t a, int64_t b, double d[3]) {
+  int64_t M = m->M;
+  double xa[3], xb[3];
+  getp(X, M, a, xa); getp(X, M, b, xb);
+  if (m->disp) {
+    double ya[3], yb[3];
+    getp(m->X_ref, M, a, ya); getp(m->X_ref, M, b, yb);
+    for (int i = 0; i < 3; i++) d[i] = (yb[i] - ya[i]) + (xb[i] - xa[i]);
+  } else {
+    for (int i = 0; i < 3; i++) d[i] = xb[i] - xa[i];
+  }
+}
+
+/* Second difference from the reference, (Xa - 2Xc + Xb) - (Ya - 2Yc + Yb):
+ * with displacements it is Da - 2Dc + Db. */
+static void bend_vec(const ibo_model *m, const double *X, int64_t a, int64_t c, int64_t b, double v[3]) {
+  int64_t M = m->M;
+  double xa[3], xb[3], xc[3];
+  getp(X, M, a, xa); getp(X, M, b, xb); getp(X, M, c, xc);
+  if (m->disp) {
+    for (int i = 0; i < 3; i++) v[i] = xa[i] - 2.0 * xc[i] + xb[i];
+  } else {
+    double ya[3], yb[3], yc[3];
+    getp(m->X_ref, M, a, ya); getp(m->X_ref, M, b, yb); getp(m->X_ref, M, c, yc);
+    for (int i = 0; i < 3; i++) v[i] = (xa[i] - 2.0 * xc[i] + xb[i]) - (ya[i] - 2.0 * yc[i] + yb[i]);
+  }
+}
+
+void ibo_positions(const ibo_model *m, const double *X, double *P) {
+  int64_t n3 = 3 * m->M;
+  for (int64_t p = 0; p < n3; p++) P[p] = m->disp ? m->X_ref[p] + X[p] : X[p];
+}
+
 /* Stretch edge: force added into F (if non-null), energy added into *E (if non-null). */
 static void stretch_edge(const ibo_model *m, const double *X, int64_t a, int64_t b, double Ks,
                          int use_w, double *F, double *E) {
   int64_t M = m->M;
-  double xa[3], xb[3], ya[3], yb[3], d[3], dy[3];
-  getp(X, M, a, xa); getp(X, M, b, xb); getp(m->X_ref, M, a, ya); getp(m->X_ref, M, b, yb);
-  for (int i = 0; i < 3; i++) { d[i] = xb[i] - xa[i]; dy[i] = yb[i] - ya[i]; }
+  double ya[3], yb[3], d[3], dy[3];
+  getp(m->X_ref, M, a, ya); getp(m->X_ref, M, b, yb);
+  edge_vec(m, X, a, b, d);
+  for (int i = 0; i < 3; i++) dy[i] = yb[i] - ya[i];
   double len = norm3(d), Le = norm3(dy);
   double K = Ks * 0.5 * (m->k[a] + m->k[b]);
   if (use_w) K *= 0.5 * (m->w[a] + m->w[b]);
@@ -130,11 +170,10 @@ static void stretch_edge(const ibo_model *m, const double *X, int64_t a, int64_t
 static void bend_triple(const ibo_model *m, const double *X, int64_t a, int64_t c, int64_t b,
                         double Kb, double *F, double *E) {
   int64_t M = m->M;
-  double xa[3], xb[3], xc[3], ya[3], yb[3], yc[3], v[3], e1[3], e2[3];
-  getp(X, M, a, xa); getp(X, M, b, xb); getp(X, M, c, xc);
+  double ya[3], yb[3], yc[3], v[3], e1[3], e2[3];
   getp(m->X_ref, M, a, ya); getp(m->X_ref, M, b, yb); getp(m->X_ref, M, c, yc);
+  bend_vec(m, X, a, c, b, v);
   for (int i = 0; i < 3; i++) {
-    v[i] = (xa[i] - 2.0 * xc[i] + xb[i]) - (ya[i] - 2.0 * yc[i] + yb[i]);
     e1[i] = yc[i] - ya[i];
     e2[i] = yb[i] - yc[i];
   }
@@ -178,10 +217,8 @@ static void elastic_terms(const ibo_model *m, const double *X, double *F, double
   }
   for (int64_t e = 0; e < m->n_springs; e++) {
     int64_t a = m->spring_ab[e], b = m->spring_ab[m->n_springs + e];
-    int64_t Mm = M;
-    double xa[3], xb[3], d[3];
-    getp(X, Mm, a, xa); getp(X, Mm, b, xb);
-    for (int i = 0; i < 3; i++) d[i] = xb[i] - xa[i];
+    double d[3];
+    edge_vec(m, X, a, b, d);
     double len = norm3(d), L0 = m->spring_rest[e];
     double K = m->K_spring * 0.5 * (m->k[a] + m->k[b]);
     if (E) *E += 0.5 * K * (len - L0) * (len - L0);
@@ -197,7 +234,7 @@ static void elastic_terms(const ibo_model *m, const double *X, double *F, double
       if (kw == 0.0) continue;
       double x[3], y[3], r[3];
       getp(X, M, q, x); getp(m->X_ref, M, q, y);
-      for (int i = 0; i < 3; i++) r[i] = x[i] - y[i];
+      for (int i = 0; i < 3; i++) r[i] = m->disp ? x[i] : x[i] - y[i];
       if (E) *E += 0.5 * kw * (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
       if (F) addp(F, M, q, r, -kw);
     }
@@ -520,14 +557,16 @@ void ibo_step(const ibo_model *m, int N, int Nz, double L, double rho, double mu
   double *Fg = (double *)malloc(sizeof(double) * 3 * (size_t)G);
   double *un = (double *)malloc(sizeof(double) * 3 * (size_t)G);
   double *U = (double *)malloc(sizeof(double) * 3 * (size_t)(M > 0 ? M : 1));
+  double *P = (double *)malloc(sizeof(double) * 3 * (size_t)(M > 0 ? M : 1));
+  ibo_positions(m, X, P);   /* where the delta function is evaluated */
   ibo_force(m, X, t, F);
   if (F_lag_out) memcpy(F_lag_out, F, sizeof(double) * 3 * (size_t)M);
-  ibo_spread(N, Nz, L, M, X, F, Fg);
+  ibo_spread(N, Nz, L, M, P, F, Fg);
   ibo_fluid(N, Nz, L, rho, mu, dt, convect, u, Fg, un);
-  ibo_interp(N, Nz, L, M, X, un, U);
+  ibo_interp(N, Nz, L, M, P, un, U);
   for (int64_t p = 0; p < 3 * M; p++) X[p] = X[p] + dt * U[p];
   memcpy(u, un, sizeof(double) * 3 * (size_t)G);
-  free(F); free(Fg); free(un); free(U);
+  free(F); free(Fg); free(un); free(U); free(P);
 }
 
 /* ------------------------------------------------------------------------
@@ -573,9 +612,10 @@ static void phi4_d(double s, int64_t c, double h, double w[4], double g[4]) {
 static double hess_edge(const ibo_model *m, const double *X, int64_t a, int64_t b, double Ku,
                         double kf, double L0, int rest_sq, const double *v, double *out) {
   int64_t M = m->M;
-  double xa[3], xb[3], d[3], va[3], vb[3], dv[3];
-  getp(X, M, a, xa); getp(X, M, b, xb); getp(v, M, a, va); getp(v, M, b, vb);
-  for (int i = 0; i < 3; i++) { d[i] = xb[i] - xa[i]; dv[i] = vb[i] - va[i]; }
+  double d[3], va[3], vb[3], dv[3];
+  edge_vec(m, X, a, b, d);
+  getp(v, M, a, va); getp(v, M, b, vb);
+  for (int i = 0; i < 3; i++) dv[i] = vb[i] - va[i];
   double len = norm3(d);
   double Ku_p = rest_sq ? Ku / (L0 * L0) : Ku;
   double Kp = Ku_p * kf;
@@ -626,15 +666,14 @@ static void elastic_hvp_and_kbar(const ibo_model *m, const double *X, const doub
               if (!per && (i2 == 0 || i2 == n2 - 1)) continue;
               a = IDX(i1, (i2 + n2 - 1) % n2); c = IDX(i1, i2); b = IDX(i1, (i2 + 1) % n2);
             }
-            double xa[3], xb[3], xc[3], ya[3], yb[3], yc[3], e1[3], e2v[3], z[3], vv[3];
-            getp(X, M, a, xa); getp(X, M, b, xb); getp(X, M, c, xc);
+            double ya[3], yb[3], yc[3], e1[3], e2v[3], z[3], vv[3];
             getp(m->X_ref, M, a, ya); getp(m->X_ref, M, b, yb); getp(m->X_ref, M, c, yc);
             double va[3], vb[3], vc[3];
             getp(v, M, a, va); getp(v, M, b, vb); getp(v, M, c, vc);
+            bend_vec(m, X, a, c, b, vv);
             for (int i = 0; i < 3; i++) {
               e1[i] = yc[i] - ya[i]; e2v[i] = yb[i] - yc[i];
               z[i] = va[i] - 2.0 * vc[i] + vb[i];
-              vv[i] = (xa[i] - 2.0 * xc[i] + xb[i]) - (ya[i] - 2.0 * yc[i] + yb[i]);
             }
             double Lc = 0.5 * (norm3(e1) + norm3(e2v));
             double K1 = Kb * m->w[c] / (Lc * Lc * Lc * Lc); /* per unit k_c */
@@ -680,6 +719,8 @@ void ibo_adjoint_step_u(const ibo_model *m, int N, int Nz, double L, double rho,
   double *f = (double *)malloc(mb), *Ub = (double *)malloc(mb), *fb = (double *)calloc(3 * (size_t)(M > 0 ? M : 1), sizeof(double));
   double *Hv = (double *)calloc(3 * (size_t)(M > 0 ? M : 1), sizeof(double));
   double *utot = (double *)malloc(sizeof(double) * 3 * (size_t)G);
+  double *Pn = (double *)malloc(mb);
+  ibo_positions(m, X_n, Pn);   /* the delta function's arguments at step n */
   ibo_force(m, X_n, t, f);
   for (int64_t p = 0; p < 3 * M; p++) Ub[p] = dt * Xbar[p];
 
@@ -688,7 +729,7 @@ void ibo_adjoint_step_u(const ibo_model *m, int N, int Nz, double L, double rho,
   for (int64_t q = 0; q < M; q++) {
     double s[3];
     int64_t c[3];
-    for (int d = 0; d < 3; d++) { s[d] = X_n[d * M + q] / h; c[d] = (int64_t)floor(s[d]); }
+    for (int d = 0; d < 3; d++) { s[d] = Pn[d * M + q] / h; c[d] = (int64_t)floor(s[d]); }
     double gX[3] = {0.0, 0.0, 0.0}, w[3][4], g[3][4];
     for (int d = 0; d < 3; d++) phi4_d(s[d], c[d], h, w[d], g[d]);
     for (int64_t k = c[2] - 1; k <= c[2] + 2; k++)
@@ -716,7 +757,7 @@ void ibo_adjoint_step_u(const ibo_model *m, int N, int Nz, double L, double rho,
     for (int64_t q = 0; q < M; q++) {
       double s[3], w[3][4];
       int64_t c[3];
-      for (int d = 0; d < 3; d++) { s[d] = X_n[d * M + q] / h; c[d] = (int64_t)floor(s[d]); }
+      for (int d = 0; d < 3; d++) { s[d] = Pn[d * M + q] / h; c[d] = (int64_t)floor(s[d]); }
       int mine = 0;
       for (int64_t k = c[2] - 1; k <= c[2] + 2; k++) mine |= wrap(k, Nz) % nt == t;
       if (!mine) continue;
@@ -741,7 +782,7 @@ void ibo_adjoint_step_u(const ibo_model *m, int N, int Nz, double L, double rho,
   for (int64_t q = 0; q < M; q++) {
     double s[3];
     int64_t c[3];
-    for (int d = 0; d < 3; d++) { s[d] = X_n[d * M + q] / h; c[d] = (int64_t)floor(s[d]); }
+    for (int d = 0; d < 3; d++) { s[d] = Pn[d * M + q] / h; c[d] = (int64_t)floor(s[d]); }
     double gX[3] = {0.0, 0.0, 0.0}, acc[3] = {0.0, 0.0, 0.0}, w[3][4], g[3][4];
     for (int d = 0; d < 3; d++) phi4_d(s[d], c[d], h, w[d], g[d]);
     for (int64_t k = c[2] - 1; k <= c[2] + 2; k++)
@@ -775,5 +816,5 @@ void ibo_adjoint_step_u(const ibo_model *m, int N, int Nz, double L, double rho,
     for (int64_t p = 0; p < 3 * G; p++) ubar[p] -= dt * utot[p];
   }
 
-  free(f); free(Ub); free(fb); free(Hv); free(utot);
+  free(f); free(Ub); free(fb); free(Hv); free(utot); free(Pn);
 }

@@ -60,10 +60,21 @@ typedef struct {
   const int32_t *drive_idx;                     /* [D]                     */
   const double *drive_dir;                      /* [3][D]                  */
   double drive_A, drive_freq;
+  /* 0: marker arrays hold positions X.  1: they hold displacements D = X - Y
+   * from the reference shape Y = X_ref; positions are formed as Y + D where
+   * the delta function is evaluated, and the elastic terms are written in D
+   * (an edge is (Yb - Ya) + (Db - Da), a second difference Da - 2Dc + Db), so
+   * that strains far below the positions' rounding keep their own relative
+   * precision. */
+  int32_t disp;
 } ibo_model;
 
 void   ibo_force(const ibo_model *m, const double *X, double t, double *F);
 double ibo_energy(const ibo_model *m, const double *X);
+
+/* Positions Y + D of a model's markers whose state array holds displacements
+ * (disp = 1); copies X when disp = 0.  P: [3][M]. */
+void ibo_positions(const ibo_model *m, const double *X, double *P);
 
 /* Sub-step 2, eq. discreteF: Fg = sum_q F_q delta_h(x - X_q) (overwrite). */
 void ibo_spread(int N, int Nz, double L, int64_t M, const double *X, const double *Fq, double *Fg);

@@ -35,12 +35,21 @@ def _lattice_wl(Y, X, k, w, n1, n2, Ks, Kb, periodic2=False):
                       drive_idx=np.zeros(0, np.int32), drive_dir=np.zeros((3, 0)), drive_A=0.0, drive_freq=0.0)
 
 
-def _force(oracle_mod, wl):
+@pytest.fixture(params=["positions", "displacements"])
+def mode(request):
+    """Every pin holds with the marker state as positions X and as
+    displacements D = X - X_ref (the oracle's two ways of forming the terms)."""
+    return request.param
+
+
+def _force(oracle_mod, mode, wl):
+    if mode == "displacements":
+        return oracle_mod.force(oracle_mod.Model(wl, displacement=True), wl.X0 - wl.X_ref, 0.0)
     return oracle_mod.force(oracle_mod.Model(wl), wl.X0, 0.0)
 
 
 @pytest.mark.parametrize("axis", [1, 2])
-def test_single_edge_stretch_magnitude(oracle_mod, axis):
+def test_single_edge_stretch_magnitude(oracle_mod, mode, axis):
     """One edge (along lattice direction 1 or 2) of rest length Le = 0.01, pulled
     to (1 + eps) Le along a skew unit direction e: each end feels
     Ks kbar wbar eps Le / Le^2 = Ks kbar wbar eps / Le along the edge, pulling
@@ -53,17 +62,17 @@ def test_single_edge_stretch_magnitude(oracle_mod, axis):
     X = Y.copy()
     X[:, 1] = ya + (1.0 + eps) * Le * e
     n1, n2 = (2, 1) if axis == 1 else (1, 2)
-    F = _force(oracle_mod, _lattice_wl(Y, X, k, w, n1, n2, Ks, 0.0))
+    F = _force(oracle_mod, mode, _lattice_wl(Y, X, k, w, n1, n2, Ks, 0.0))
     mag = Ks * 2.0 * 0.4 * eps * Le / Le ** 2                # = 4.0
     np.testing.assert_allclose(F[:, 1], -mag * e, rtol=1e-9, atol=0)
     np.testing.assert_allclose(F[:, 0], +mag * e, rtol=1e-9, atol=0)
     # compressed instead: the ends are pushed apart, same magnitude
     X[:, 1] = ya + (1.0 - eps) * Le * e
-    F = _force(oracle_mod, _lattice_wl(Y, X, k, w, n1, n2, Ks, 0.0))
+    F = _force(oracle_mod, mode, _lattice_wl(Y, X, k, w, n1, n2, Ks, 0.0))
     np.testing.assert_allclose(F[:, 1], +mag * e, rtol=1e-9, atol=0)
 
 
-def test_stretch_is_independent_of_rotation_of_the_edge(oracle_mod):
+def test_stretch_is_independent_of_rotation_of_the_edge(oracle_mod, mode):
     """The stretch force depends on |Xb - Xa| only: a rotated, unstretched edge
     carries no force; rotated and stretched it carries the closed-form force
     along its current direction (Le measured on the reference shape)."""
@@ -73,16 +82,16 @@ def test_stretch_is_independent_of_rotation_of_the_edge(oracle_mod):
     d = np.array([0.0, 0.6, 0.8])                           # rotated direction, unit
     X = Y.copy()
     X[:, 1] = Y[:, 0] + Le * d
-    F = _force(oracle_mod, _lattice_wl(Y, X, k, w, 2, 1, Ks, 0.0))
+    F = _force(oracle_mod, mode, _lattice_wl(Y, X, k, w, 2, 1, Ks, 0.0))
     assert np.abs(F).max() < 1e-9
     X[:, 1] = Y[:, 0] + (1.0 + eps) * Le * d
-    F = _force(oracle_mod, _lattice_wl(Y, X, k, w, 2, 1, Ks, 0.0))
+    F = _force(oracle_mod, mode, _lattice_wl(Y, X, k, w, 2, 1, Ks, 0.0))
     mag = Ks * 1.0 * 0.2 * eps / Le                          # = 2.0
     np.testing.assert_allclose(F[:, 1], -mag * d, rtol=1e-9, atol=0)
     np.testing.assert_allclose(F[:, 0], mag * d, rtol=1e-9, atol=0)
 
 
-def test_periodic_ring_stretch(oracle_mod):
+def test_periodic_ring_stretch(oracle_mod, mode):
     """A periodic lattice of one column and four rows (n1 = 1, n2 = 4) is a
     closed square ring of side Le.  Scaled by (1 + eps) about its centre, every
     edge is stretched by eps Le; a corner feels the two edge forces
@@ -95,7 +104,7 @@ def test_periodic_ring_stretch(oracle_mod):
     X = c[:, None] + (1.0 + eps) * (Y - c[:, None])
     k = np.array([1.0, 2.0, 3.0, 4.0])
     w = np.array([0.1, 0.2, 0.3, 0.4])
-    F = _force(oracle_mod, _lattice_wl(Y, X, k, w, 1, 4, Ks, 0.0, periodic2=True))
+    F = _force(oracle_mod, mode, _lattice_wl(Y, X, k, w, 1, 4, Ks, 0.0, periodic2=True))
     want = np.zeros((3, 4))
     for a in range(4):
         b = (a + 1) % 4
@@ -109,14 +118,14 @@ def test_periodic_ring_stretch(oracle_mod):
     f30 = Ks * 2.5 * 0.25 * eps / Le
     np.testing.assert_allclose(F[:, 0], [f01, f30, 0.0], rtol=1e-8, atol=1e-12)
     # with equal k and w on every marker the four corner forces point at the centre
-    F = _force(oracle_mod, _lattice_wl(Y, X, np.ones(4), np.full(4, 0.2), 1, 4, Ks, 0.0, periodic2=True))
+    F = _force(oracle_mod, mode, _lattice_wl(Y, X, np.ones(4), np.full(4, 0.2), 1, 4, Ks, 0.0, periodic2=True))
     for a in range(4):
         r = (c - X[:, a]) / np.linalg.norm(c - X[:, a])
         np.testing.assert_allclose(F[:, a], math.sqrt(2.0) * Ks * 0.2 * eps / Le * r, rtol=1e-8, atol=1e-12)
 
 
 @pytest.mark.parametrize("axis", [1, 2])
-def test_single_bend_triple_magnitude(oracle_mod, axis):
+def test_single_bend_triple_magnitude(oracle_mod, mode, axis):
     """Three markers in a line with spacings Le1 = 0.01, Le2 = 0.03 (Lc = 0.02);
     the centre displaced by delta across the line changes the second difference
     by -2 delta, so E = 2 Kb k_c w_c delta^2 / Lc^4 and the forces are
@@ -132,14 +141,14 @@ def test_single_bend_triple_magnitude(oracle_mod, axis):
     X = Y.copy()
     X[:, 1] += delta * nrm
     n1, n2 = (3, 1) if axis == 1 else (1, 3)
-    F = _force(oracle_mod, _lattice_wl(Y, X, k, w, n1, n2, 0.0, Kb))
+    F = _force(oracle_mod, mode, _lattice_wl(Y, X, k, w, n1, n2, 0.0, Kb))
     K = Kb * 2.0 * 0.25 / Lc ** 4
     np.testing.assert_allclose(F[:, 1], -4.0 * K * delta * nrm, rtol=1e-9, atol=0)
     np.testing.assert_allclose(F[:, 0], 2.0 * K * delta * nrm, rtol=1e-9, atol=0)
     np.testing.assert_allclose(F[:, 2], 2.0 * K * delta * nrm, rtol=1e-9, atol=0)
 
 
-def test_bend_end_displacement(oracle_mod):
+def test_bend_end_displacement(oracle_mod, mode):
     """Displacing an end by delta changes the second difference by +delta:
     forces -K delta on that end, +2 K delta on the centre, -K delta on the
     other end, K = Kb k_c w_c / Lc^4; a rigid translation of all three gives
@@ -150,17 +159,17 @@ def test_bend_end_displacement(oracle_mod):
     n = np.array([0.0, 0.0, 1.0])
     X = Y.copy()
     X[:, 2] += delta * n
-    F = _force(oracle_mod, _lattice_wl(Y, X, k, w, 3, 1, 0.0, Kb))
+    F = _force(oracle_mod, mode, _lattice_wl(Y, X, k, w, 3, 1, 0.0, Kb))
     K = Kb * 4.0 * 0.125 / Le ** 4
     np.testing.assert_allclose(F[:, 2], -K * delta * n, rtol=1e-9, atol=0)
     np.testing.assert_allclose(F[:, 1], 2.0 * K * delta * n, rtol=1e-9, atol=0)
     np.testing.assert_allclose(F[:, 0], -K * delta * n, rtol=1e-9, atol=0)
     Xt = Y + np.array([[1e-3], [-2e-3], [5e-4]])
-    F = _force(oracle_mod, _lattice_wl(Y, Xt, k, w, 3, 1, 0.0, Kb))
+    F = _force(oracle_mod, mode, _lattice_wl(Y, Xt, k, w, 3, 1, 0.0, Kb))
     assert np.abs(F).max() < 1e-6 * K * delta
 
 
-def test_lattice_2x2_counts_every_edge_once(oracle_mod):
+def test_lattice_2x2_counts_every_edge_once(oracle_mod, mode):
     """A 2 x 2 non-periodic lattice has four edges (two per direction) and no
     bend triples.  Stretching it uniformly by eps along direction 1 only loads
     the two direction-1 edges; the direction-2 edges stay at rest."""
@@ -171,7 +180,7 @@ def test_lattice_2x2_counts_every_edge_once(oracle_mod):
     X[0, [1, 3]] += eps * Le
     k = np.array([1.0, 2.0, 3.0, 4.0])
     w = np.array([0.4, 0.2, 0.1, 0.3])
-    F = _force(oracle_mod, _lattice_wl(Y, X, k, w, 2, 2, Ks, 5.0))
+    F = _force(oracle_mod, mode, _lattice_wl(Y, X, k, w, 2, 2, Ks, 5.0))
     f_lo = Ks * 1.5 * 0.3 * eps / Le     # edge 00-10
     f_hi = Ks * 3.5 * 0.2 * eps / Le     # edge 01-11
     # direction-2 edges (00-01, 10-11) are tilted by eps Le / Le: their length
