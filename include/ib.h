@@ -19,6 +19,14 @@
  *    precision (double for IB_FLUID_FP64, float for IB_FLUID_FP32).
  *  - Marker arrays (X, F_lag, U, Xbar) are DEVICE double arrays [3][M]
  *    (component-major).  X is stored unwrapped; only grid indices wrap.
+ *    With ib_params.displacement = 1 every marker-state argument (the X of
+ *    ib_step, ib_force, ib_spread, ib_interp, ib_bin, ib_adjoint_step(_u)
+ *    and ib_probe) holds D = X - X_ref instead: positions are formed as
+ *    X_ref + D where the delta function is evaluated, and the elastic terms
+ *    from D (an edge as (Yb - Ya) + (Db - Da), a second difference as
+ *    Da - 2Dc + Db, a tether offset as D), so that strains far below the
+ *    rounding of O(1) positions keep their relative precision.  The move is
+ *    D += dt U; Xbar is the same cotangent in both forms.
  *  - Per-marker forces are f(q) dq, i.e. force densities times the marker's
  *    area weight (so sum_x F_grid h^3 = sum_q F_lag[q]).
  *  - The caller owns every array it passes; the context owns only its
@@ -61,6 +69,8 @@ typedef struct {
   int64_t n_markers;         /* M >= 0, < 2^31                                      */
   void *stream;              /* hipStream_t (NULL: the null stream)                 */
   int32_t nz;                /* nodes along z: 0 or n (cube), n/2 (half-cube)       */
+  int32_t displacement;      /* 0: marker arrays X hold positions; 1: they hold     */
+                             /* displacements D = X - X_ref (see below)             */
 } ib_params;
 
 /* A rectangular material lattice Q (Sec. 3.2): markers first + i2*n1 + i1,
@@ -108,7 +118,8 @@ typedef struct {
 /* Validate, copy the topology, allocate the workspace.  IB_EINVAL on a bad
  * parameter or topology index, IB_ENOTSUP for n outside [8, 512] or not a
  * power of two, or nz other than 0, n and n/2 (n/2 only for n in [32, 256]),
- * IB_ENOMEM on allocation failure.  *out is NULL on error. */
+ * IB_ENOMEM on allocation failure, IB_EINVAL for displacement other than 0,
+ * 1.  *out is NULL on error. */
 int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out);
 void ib_destroy(ib_ctx *c);
 

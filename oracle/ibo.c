@@ -147,6 +147,22 @@ void ibo_positions(const ibo_model *m, const double *X, double *P) {
   for (int64_t p = 0; p < n3; p++) P[p] = m->disp ? m->X_ref[p] + X[p] : X[p];
 }
 
+/* Extension |d| - Le of an edge whose reference vector is dy (Le = |dy|) and
+ * current vector d.  From displacements (d = dy + dl, dl = Db - Da) it is
+ * formed as (2 dy.dl + dl.dl) / (|d| + Le), the same number without the
+ * cancellation of two lengths that agree to the strain. */
+static double extension(const ibo_model *m, const double *X, int64_t a, int64_t b, const double dy[3],
+                        const double d[3], double len, double Le) {
+  if (!m->disp) return len - Le;
+  int64_t M = m->M;
+  double xa[3], xb[3], dl[3];
+  getp(X, M, a, xa); getp(X, M, b, xb);
+  for (int i = 0; i < 3; i++) dl[i] = xb[i] - xa[i];
+  (void)d;
+  double num = 2.0 * (dy[0] * dl[0] + dy[1] * dl[1] + dy[2] * dl[2]) + (dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2]);
+  return num / (len + Le);
+}
+
 /* Stretch edge: force added into F (if non-null), energy added into *E (if non-null). */
 static void stretch_edge(const ibo_model *m, const double *X, int64_t a, int64_t b, double Ks,
                          int use_w, double *F, double *E) {
@@ -156,12 +172,13 @@ static void stretch_edge(const ibo_model *m, const double *X, int64_t a, int64_t
   edge_vec(m, X, a, b, d);
   for (int i = 0; i < 3; i++) dy[i] = yb[i] - ya[i];
   double len = norm3(d), Le = norm3(dy);
+  double ext = extension(m, X, a, b, dy, d, len, Le);
   double K = Ks * 0.5 * (m->k[a] + m->k[b]);
   if (use_w) K *= 0.5 * (m->w[a] + m->w[b]);
-  if (E) *E += 0.5 * K * (len - Le) * (len - Le) / (Le * Le);
+  if (E) *E += 0.5 * K * ext * ext / (Le * Le);
   if (F) {
     /* dE/dXb = K (len - Le)/Le^2 * d/len ; dE/dXa = -dE/dXb */
-    double s = K * (len - Le) / (Le * Le) / len;
+    double s = K * ext / (Le * Le) / len;
     addp(F, M, a, d, s);
     addp(F, M, b, d, -s);
   }
@@ -617,15 +634,23 @@ static double hess_edge(const ibo_model *m, const double *X, int64_t a, int64_t 
   getp(v, M, a, va); getp(v, M, b, vb);
   for (int i = 0; i < 3; i++) dv[i] = vb[i] - va[i];
   double len = norm3(d);
+  /* |d| - L0: for a lattice edge (rest length |Yb - Ya|) from displacements as in the force */
+  double ext = len - L0;
+  if (rest_sq) {
+    double ya[3], yb[3], dy[3];
+    getp(m->X_ref, M, a, ya); getp(m->X_ref, M, b, yb);
+    for (int i = 0; i < 3; i++) dy[i] = yb[i] - ya[i];
+    ext = extension(m, X, a, b, dy, d, len, L0);
+  }
   double Ku_p = rest_sq ? Ku / (L0 * L0) : Ku;
   double Kp = Ku_p * kf;
   double dd = d[0] * dv[0] + d[1] * dv[1] + d[2] * dv[2];
   double Hv[3];
-  for (int i = 0; i < 3; i++) Hv[i] = Kp * ((1.0 - L0 / len) * dv[i] + (L0 / (len * len * len)) * dd * d[i]);
+  for (int i = 0; i < 3; i++) Hv[i] = Kp * ((ext / len) * dv[i] + (L0 / (len * len * len)) * dd * d[i]);
   addp(out, M, b, Hv, 1.0);
   addp(out, M, a, Hv, -1.0);
   /* unit force: -c d at b, +c d at a, c = Ku'(|d| - L0)/|d|; dotted with v: -c d.(vb - va) */
-  return -(Ku_p * (len - L0) / len) * dd;
+  return -(Ku_p * ext / len) * dd;
 }
 
 static void elastic_hvp_and_kbar(const ibo_model *m, const double *X, const double *v,

@@ -162,6 +162,10 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
     g_create_error = "ib_create: convect must be 0 or 1";
     return IB_EINVAL;
   }
+  if (p->displacement != 0 && p->displacement != 1) {
+    g_create_error = "ib_create: displacement must be 0 or 1";
+    return IB_EINVAL;
+  }
   const int64_t M = p->n_markers;
   if (M < 0 || M >= (int64_t)INT32_MAX) {
     g_create_error = "ib_create: n_markers out of range";
@@ -256,6 +260,7 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
   mt.kappa = e->kappa;
   mt.M = M;
   mt.K_spring = e->K_spring;
+  mt.disp = p->displacement;
   mt.lat.n = e->n_lattices;
   for (int l = 0; l < e->n_lattices; l++) {
     const ib_lattice &L = e->lattices[l];
@@ -538,7 +543,7 @@ static int graph_capture(ib_ctx *c, double *X, T *u, double amp, double *F_lag_o
   IB_TRY(hipGraphGetNodes(g, nullptr, &nn));
   std::vector<hipGraphNode_t> nodes(nn);
   if (nn) IB_TRY(hipGraphGetNodes(g, nodes.data(), &nn));
-  const void *fk = force_rec_kernel<T>();
+  const void *fk = force_rec_kernel<T>(c->mat.disp != 0);
   for (hipGraphNode_t nd : nodes) {
     hipGraphNodeType ty;
     IB_TRY(hipGraphNodeGetType(nd, &ty));

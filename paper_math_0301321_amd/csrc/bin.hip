@@ -26,7 +26,8 @@ constexpr int kWaveKeys = 64 * kSortItems;
 // Keys of the sort blocks' markers, with the first pass's digit counts of
 // each block (the counts of the later passes depend on the order the earlier
 // passes produce).
-__global__ __launch_bounds__(256) void k_keys_hist(const double *__restrict__ X, int64_t M, double h, int n,
+__global__ __launch_bounds__(256) void k_keys_hist(const double *__restrict__ X, const double *__restrict__ Y,
+                                                   int64_t M, double h, int n,
                                                    int nz, int log2nt, int radix, uint32_t *__restrict__ keys,
                                                    int32_t *__restrict__ vals, uint32_t *__restrict__ hist,
                                                    int nblk) {
@@ -39,7 +40,8 @@ __global__ __launch_bounds__(256) void k_keys_hist(const double *__restrict__ X,
     if (q < M) {
       int c[3];
       for (int d = 0; d < 3; d++) {
-        const double s = X[d * M + q] / h;
+        // the position: X, or Y + D with displacements as the state
+        const double s = (Y ? Y[d * M + q] + X[d * M + q] : X[d * M + q]) / h;
         int64_t cd = isfinite(s) ? (int64_t)floor(s) : 0;
         c[d] = (int)(cd & (int64_t)((d == 2 ? nz : n) - 1));   // periodic wrap (n, nz powers of two)
       }
@@ -368,7 +370,8 @@ hipError_t launch_bin(ib_ctx *c, const double *X) {
     int cur = 0;
     const int bits = c->digit_bits, R = 1 << bits;
     const int nblk = (int)((M + kSortChunk - 1) / kSortChunk);
-    hipLaunchKernelGGL(k_keys_hist, dim3(nblk), dim3(kSortThreads), 0, c->stream, X, M, c->h, c->n, c->nz, c->log2nt, R,
+    hipLaunchKernelGGL(k_keys_hist, dim3(nblk), dim3(kSortThreads), 0, c->stream, X,
+                       c->mat.disp ? c->mat.X_ref : nullptr, M, c->h, c->n, c->nz, c->log2nt, R,
                        ws.keys[0], ws.vals[0], ws.hist, nblk);
     for (int pass = 0; pass < c->sort_passes; pass++) {
       const int shift = pass * bits;

@@ -8,6 +8,9 @@
 // of the drive list.  Lattice rest lengths and bend scales come from the
 // reference shape and weights, computed once when those are set.  In the time
 // step the same pass also writes the marker's sorted record for the spreading.  Force laws: see include/ib.h.
+// With displacements as the state (DISP: X holds D = X - Y, Y = X_ref) an
+// edge vector is (Yo - Yq) + (Do - Dq), a second difference Da - 2Dc + Db and
+// a tether offset D itself, each with the relative precision of D.
 #include "dev_common.h"
 #include "ib_internal.h"
 
@@ -83,14 +86,34 @@ __global__ __launch_bounds__(256) void k_lattice_pre(Material m, double *__restr
   for (int j = 0; j < kLatPre; j++) pre[j * M + q] = v[j];
 }
 
-// Force on marker q (position xq, multiplier kq) from the stretch edge to o
-// (position xo, multiplier ko) with rest length le and ke = Ks w / le^2 (of
-// the edge's lower endpoint).
-__device__ __forceinline__ void stretch_on(const V3 &xq, double kq, const V3 &xo, double ko, double le, double ke,
-                                           V3 &f) {
-  const V3 d{xo.x - xq.x, xo.y - xq.y, xo.z - xq.z};
+// Edge vector from q to o: Xo - Xq, or with displacements (Yo - Yq) + (Do - Dq).
+template <bool DISP>
+__device__ __forceinline__ V3 edge_vec(const V3 &xq, const V3 &xo, const V3 &yq, const V3 &yo) {
+  if (DISP) return V3{(yo.x - yq.x) + (xo.x - xq.x), (yo.y - yq.y) + (xo.y - xq.y), (yo.z - yq.z) + (xo.z - xq.z)};
+  return V3{xo.x - xq.x, xo.y - xq.y, xo.z - xq.z};
+}
+
+// Force on marker q (state xq, reference yq, multiplier kq) from the stretch
+// edge to o (xo, yo, ko) with rest length le and ke = Ks w / le^2 (of the
+// edge's lower endpoint); the reference positions are read only with DISP.
+// Extension |d| - le of a lattice edge; with displacements (d = dy + dl,
+// dy = Yo - Yq, dl = Do - Dq) formed as (2 dy.dl + dl.dl) / (|d| + le), without
+// the cancellation of two lengths that agree to the strain.
+template <bool DISP>
+__device__ __forceinline__ double extension(const V3 &xq, const V3 &xo, const V3 &yq, const V3 &yo, double len,
+                                            double le) {
+  if (!DISP) return len - le;
+  const V3 dy{yo.x - yq.x, yo.y - yq.y, yo.z - yq.z}, dl{xo.x - xq.x, xo.y - xq.y, xo.z - xq.z};
+  const double num = 2.0 * (dy.x * dl.x + dy.y * dl.y + dy.z * dl.z) + (dl.x * dl.x + dl.y * dl.y + dl.z * dl.z);
+  return num / (len + le);
+}
+
+template <bool DISP>
+__device__ __forceinline__ void stretch_on(const V3 &xq, const V3 &yq, double kq, const V3 &xo, const V3 &yo,
+                                           double ko, double le, double ke, V3 &f) {
+  const V3 d = edge_vec<DISP>(xq, xo, yq, yo);
   const double len = nrm(d);
-  const double s = ke * (0.5 * (kq + ko)) * (len - le) / len;
+  const double s = ke * (0.5 * (kq + ko)) * extension<DISP>(xq, xo, yq, yo, len, le) / len;
   f.x += s * d.x;
   f.y += s * d.y;
   f.z += s * d.z;
@@ -99,12 +122,16 @@ __device__ __forceinline__ void stretch_on(const V3 &xq, double kq, const V3 &xo
 // Force on marker q from the bend triple with positions xa, xc (centre c,
 // multiplier kc), xb, cb = Kb w_c / Lc^4 and d2 (3 strided values) the
 // reference second difference Y_a - 2 Y_c + Y_b; role: 0 = end, 1 = centre.
+template <bool DISP>
 __device__ __forceinline__ void bend_on(const Material &m, const V3 &xa, const V3 &xc, const V3 &xb, int64_t c,
                                         double kc, int role, double cb, const double *__restrict__ d2, V3 &f) {
   const int64_t M = m.M;
-  const V3 y2 = ld3(d2, M, c);
   const V3 dx = second_diff(xa, xc, xb);
-  const V3 v{dx.x - y2.x, dx.y - y2.y, dx.z - y2.z};
+  V3 v = dx;                                   // with displacements: Da - 2Dc + Db
+  if (!DISP) {
+    const V3 y2 = ld3(d2, M, c);
+    v = V3{dx.x - y2.x, dx.y - y2.y, dx.z - y2.z};
+  }
   const double K = cb * kc;
   const double s = role ? 2.0 * K : -K;
   f.x += s * v.x;
@@ -112,6 +139,7 @@ __device__ __forceinline__ void bend_on(const Material &m, const V3 &xa, const V
   f.z += s * v.z;
 }
 
+template <bool DISP>
 __device__ void lattice_force(const Material &m, const LatticeDev &L, const double *__restrict__ X,
                               int64_t q, const V3 &xq, V3 &f) {
   const int64_t M = m.M;
@@ -134,10 +162,19 @@ __device__ void lattice_force(const Material &m, const LatticeDev &L, const doub
   if (has_up) { x2p = ld3(X, M, q2p); k2p = m.k[q2p]; }
   const double kq = m.k[q];
   if (L.Ks != 0.0) {
-    if (i1 > 0) stretch_on(xq, kq, x1m, k1m, P[q1m], P[M + q1m], f);
-    if (i1 < n1 - 1) stretch_on(xq, kq, x1p, k1p, P[q], P[M + q], f);
-    if (has_dn) stretch_on(xq, kq, x2m, k2m, P[2 * M + q2m], P[3 * M + q2m], f);
-    if (has_up) stretch_on(xq, kq, x2p, k2p, P[2 * M + q], P[3 * M + q], f);
+    // reference positions of q and the four neighbours (edge vectors with displacements)
+    V3 yq{}, y1m{}, y1p{}, y2m{}, y2p{};
+    if (DISP) {
+      yq = ld3(m.X_ref, M, q);
+      if (i1 > 0) y1m = ld3(m.X_ref, M, q1m);
+      if (i1 < n1 - 1) y1p = ld3(m.X_ref, M, q1p);
+      if (has_dn) y2m = ld3(m.X_ref, M, q2m);
+      if (has_up) y2p = ld3(m.X_ref, M, q2p);
+    }
+    if (i1 > 0) stretch_on<DISP>(xq, yq, kq, x1m, y1m, k1m, P[q1m], P[M + q1m], f);
+    if (i1 < n1 - 1) stretch_on<DISP>(xq, yq, kq, x1p, y1p, k1p, P[q], P[M + q], f);
+    if (has_dn) stretch_on<DISP>(xq, yq, kq, x2m, y2m, k2m, P[2 * M + q2m], P[3 * M + q2m], f);
+    if (has_up) stretch_on<DISP>(xq, yq, kq, x2p, y2p, k2p, P[2 * M + q], P[3 * M + q], f);
   }
   if (L.Kb != 0.0) {
     const double *C1 = P + 4 * M, *C2 = P + 5 * M, *D1 = P + 6 * M, *D2 = P + 9 * M;
@@ -150,9 +187,9 @@ __device__ void lattice_force(const Material &m, const LatticeDev &L, const doub
       V3 xm2{}, xp2{};
       if (bm) xm2 = ld3(X, M, idx(i1 - 2, i2));
       if (bp) xp2 = ld3(X, M, idx(i1 + 2, i2));
-      if (b0) bend_on(m, x1m, xq, x1p, q, kq, 1, C1[q], D1, f);
-      if (bp) bend_on(m, xq, x1p, xp2, q1p, k1p, 0, C1[q1p], D1, f);
-      if (bm) bend_on(m, xm2, x1m, xq, q1m, k1m, 0, C1[q1m], D1, f);
+      if (b0) bend_on<DISP>(m, x1m, xq, x1p, q, kq, 1, C1[q], D1, f);
+      if (bp) bend_on<DISP>(m, xq, x1p, xp2, q1p, k1p, 0, C1[q1p], D1, f);
+      if (bm) bend_on<DISP>(m, xm2, x1m, xq, q1m, k1m, 0, C1[q1m], D1, f);
     }
     // direction 2: centres 1 .. n2-2, or every row when periodic
     {
@@ -162,14 +199,15 @@ __device__ void lattice_force(const Material &m, const LatticeDev &L, const doub
       V3 xm2{}, xp2{};
       if (bm) xm2 = ld3(X, M, idx(i1, w2(i2 - 2)));
       if (bp) xp2 = ld3(X, M, idx(i1, w2(i2 + 2)));
-      if (b0) bend_on(m, x2m, xq, x2p, q, kq, 1, C2[q], D2, f);
-      if (bp) bend_on(m, xq, x2p, xp2, q2p, k2p, 0, C2[q2p], D2, f);
-      if (bm) bend_on(m, xm2, x2m, xq, q2m, k2m, 0, C2[q2m], D2, f);
+      if (b0) bend_on<DISP>(m, x2m, xq, x2p, q, kq, 1, C2[q], D2, f);
+      if (bp) bend_on<DISP>(m, xq, x2p, xp2, q2p, k2p, 0, C2[q2p], D2, f);
+      if (bm) bend_on<DISP>(m, xm2, x2m, xq, q2m, k2m, 0, C2[q2m], D2, f);
     }
   }
 }
 
 // Elastic force on marker q (every term except the drive).
+template <bool DISP>
 __device__ __forceinline__ V3 marker_force(const Material &m, const double *__restrict__ X, int64_t q,
                                            const V3 &xq) {
   const int64_t M = m.M;
@@ -177,15 +215,16 @@ __device__ __forceinline__ V3 marker_force(const Material &m, const double *__re
   for (int l = 0; l < m.lat.n; l++) {
     const LatticeDev &L = m.lat.l[l];
     if (q >= L.first && q < L.first + (int64_t)L.n1 * L.n2) {
-      lattice_force(m, L, X, q, xq, f);
+      lattice_force<DISP>(m, L, X, q, xq, f);
       break;
     }
   }
   if (m.sp_rowptr) {
+    const V3 yq = DISP ? ld3(m.X_ref, M, q) : V3{};
     for (int32_t e = m.sp_rowptr[q]; e < m.sp_rowptr[q + 1]; e++) {
       const int64_t o = m.sp_col[e];
       const V3 xo = ld3(X, M, o);
-      const V3 d{xo.x - xq.x, xo.y - xq.y, xo.z - xq.z};
+      const V3 d = edge_vec<DISP>(xq, xo, yq, DISP ? ld3(m.X_ref, M, o) : V3{});
       const double len = nrm(d);
       const double K = m.K_spring * (0.5 * (m.k[q] + m.k[o]));
       const double s = K * (len - m.sp_rest[e]) / len;
@@ -197,10 +236,16 @@ __device__ __forceinline__ V3 marker_force(const Material &m, const double *__re
   if (m.kappa) {
     const double kw = m.kappa[q] * m.w[q];
     if (kw != 0.0) {
-      const V3 y = ld3(m.X_ref, M, q);
-      f.x += -kw * (xq.x - y.x);
-      f.y += -kw * (xq.y - y.y);
-      f.z += -kw * (xq.z - y.z);
+      if (DISP) {            // the offset from the reference is the displacement
+        f.x += -kw * xq.x;
+        f.y += -kw * xq.y;
+        f.z += -kw * xq.z;
+      } else {
+        const V3 y = ld3(m.X_ref, M, q);
+        f.x += -kw * (xq.x - y.x);
+        f.y += -kw * (xq.y - y.y);
+        f.z += -kw * (xq.z - y.z);
+      }
     }
   }
   return f;
@@ -219,6 +264,7 @@ __device__ __forceinline__ void add_drive(const Material &m, const int32_t *__re
   f.z += s * dir[2 * D + j];
 }
 
+template <bool DISP>
 __global__ __launch_bounds__(256) void k_force(Material m, const double *__restrict__ X,
                                                const int32_t *__restrict__ slot, const double *__restrict__ dir,
                                                int64_t D, double amp, double *__restrict__ F) {
@@ -226,7 +272,7 @@ __global__ __launch_bounds__(256) void k_force(Material m, const double *__restr
   const int64_t M = m.M;
   if (q >= M) return;
   const V3 xq = ld3(X, M, q);
-  V3 f = marker_force(m, X, q, xq);
+  V3 f = marker_force<DISP>(m, X, q, xq);
   add_drive(m, slot, dir, D, amp, q, f);
   F[q] = f.x;
   F[M + q] = f.y;
@@ -237,7 +283,7 @@ __global__ __launch_bounds__(256) void k_force(Material m, const double *__restr
 // offsets and cell key from X as the binning forms them, force in the fluid
 // precision) goes to its sorted position inv[q]; the FP64 force is written
 // only when asked for.
-template <typename T>
+template <typename T, bool DISP>
 __global__ __launch_bounds__(256) void k_force_rec(Material m, const double *__restrict__ X,
                                                    const int32_t *__restrict__ slot, const double *__restrict__ dir,
                                                    int64_t D, double amp, const int32_t *__restrict__ inv, double h,
@@ -247,7 +293,7 @@ __global__ __launch_bounds__(256) void k_force_rec(Material m, const double *__r
   const int64_t M = m.M;
   if (q >= M) return;
   const V3 xq = ld3(X, M, q);
-  V3 f = marker_force(m, X, q, xq);
+  V3 f = marker_force<DISP>(m, X, q, xq);
   add_drive(m, slot, dir, D, amp, q, f);
   if (F) {
     F[q] = f.x;
@@ -255,7 +301,12 @@ __global__ __launch_bounds__(256) void k_force_rec(Material m, const double *__r
     F[2 * M + q] = f.z;
   }
   Rec<T> r{};
-  const double xs[3] = {xq.x, xq.y, xq.z};
+  V3 pq = xq;                                  // the position, where the delta function is evaluated
+  if (DISP) {
+    const V3 yq = ld3(m.X_ref, M, q);
+    pq = V3{yq.x + xq.x, yq.y + xq.y, yq.z + xq.z};
+  }
+  const double xs[3] = {pq.x, pq.y, pq.z};
   int cc[3];
   for (int d = 0; d < 3; d++) {
     const double s = xs[d] / h;
@@ -281,8 +332,12 @@ hipError_t launch_lattice_pre(ib_ctx *c) {
 hipError_t launch_force(ib_ctx *c, const double *X, double amp, double *F) {
   if (c->M == 0) return hipSuccess;
   PhaseScope ps(c, PH_FORCE);
-  hipLaunchKernelGGL(k_force, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream, c->mat, X,
-                     c->ws.drive_slot, c->ws.drive_dir, c->n_drive, amp, F);
+  if (c->mat.disp)
+    hipLaunchKernelGGL(k_force<true>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream, c->mat, X,
+                       c->ws.drive_slot, c->ws.drive_dir, c->n_drive, amp, F);
+  else
+    hipLaunchKernelGGL(k_force<false>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream, c->mat, X,
+                       c->ws.drive_slot, c->ws.drive_dir, c->n_drive, amp, F);
   return hipGetLastError();
 }
 
@@ -290,7 +345,8 @@ template <typename T>
 hipError_t launch_force_rec(ib_ctx *c, const double *X, double amp, double *F) {
   if (c->M == 0) return hipSuccess;
   PhaseScope ps(c, PH_FORCE);
-  hipLaunchKernelGGL(k_force_rec<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream, c->mat, X,
+  hipLaunchKernelGGL((c->mat.disp ? k_force_rec<T, true> : k_force_rec<T, false>),
+                     dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream, c->mat, X,
                      c->ws.drive_slot, c->ws.drive_dir, c->n_drive, amp, c->ws.inv, c->h, c->n, c->nz, c->log2nt, F,
                      (Rec<T> *)c->ws.recs);
   return hipGetLastError();
@@ -301,11 +357,12 @@ template hipError_t launch_force_rec<double>(ib_ctx *, const double *, double, d
 
 // launch_force_rec passes amp as argument kForceRecAmpArg of k_force_rec
 template <typename T>
-const void *force_rec_kernel() {
-  return reinterpret_cast<const void *>(&k_force_rec<T>);
+const void *force_rec_kernel(bool disp) {
+  return disp ? reinterpret_cast<const void *>(&k_force_rec<T, true>)
+              : reinterpret_cast<const void *>(&k_force_rec<T, false>);
 }
-template const void *force_rec_kernel<float>();
-template const void *force_rec_kernel<double>();
+template const void *force_rec_kernel<float>(bool);
+template const void *force_rec_kernel<double>(bool);
 
 }  // namespace ib
 
@@ -320,22 +377,29 @@ namespace ib {
 // Stretch or spring edge (q, o) with energy 1/2 Ku kf (|d| - L0)^2 / D, D = L0^2
 // (lattice) or 1 (spring), d = Xo - Xq.  Adds the edge's part of (H fbar)_q to hv
 // and returns (unit-kf edge force) . fbar over both endpoints.
-__device__ __forceinline__ double edge_adj(const double *__restrict__ X, const double *__restrict__ fb, int64_t M,
-                                           int64_t q, int64_t o, double Ku, double kf, double L0, bool rest_sq,
-                                           V3 &hv) {
+__device__ __forceinline__ double edge_adj(const Material &m, const double *__restrict__ X,
+                                           const double *__restrict__ fb, int64_t M, int64_t q, int64_t o, double Ku,
+                                           double kf, double L0, bool rest_sq, V3 &hv) {
   const V3 xq = ld3(X, M, q), xo = ld3(X, M, o);
   const V3 vq = ld3(fb, M, q), vo = ld3(fb, M, o);
-  const V3 d{xo.x - xq.x, xo.y - xq.y, xo.z - xq.z};
+  V3 yq{}, yo{};
+  if (m.disp) {
+    yq = ld3(m.X_ref, M, q);
+    yo = ld3(m.X_ref, M, o);
+  }
+  const V3 d = m.disp ? edge_vec<true>(xq, xo, yq, yo) : edge_vec<false>(xq, xo, yq, yo);
   const V3 dv{vo.x - vq.x, vo.y - vq.y, vo.z - vq.z};
   const double len = nrm(d);
+  // |d| - L0; a lattice edge (rest_sq: L0 = |Yo - Yq|) from displacements as in the force
+  const double ext = (rest_sq && m.disp) ? extension<true>(xq, xo, yq, yo, len, L0) : len - L0;
   const double Kup = rest_sq ? Ku / (L0 * L0) : Ku;
   const double Kp = Kup * kf;
   const double dd = d.x * dv.x + d.y * dv.y + d.z * dv.z;
-  const double a = 1.0 - L0 / len, b = (L0 / (len * len * len)) * dd;
+  const double a = ext / len, b = (L0 / (len * len * len)) * dd;
   hv.x -= Kp * (a * dv.x + b * d.x);
   hv.y -= Kp * (a * dv.y + b * d.y);
   hv.z -= Kp * (a * dv.z + b * d.z);
-  return -(Kup * (len - L0) / len) * dd;
+  return -(Kup * ext / len) * dd;
 }
 
 // Bend triple (a, c, b): adds the triple's part of (H fbar)_q (role 1: q is the
@@ -358,7 +422,7 @@ __device__ __forceinline__ double bend_adj(const Material &m, const double *__re
   if (!role) return 0.0;
   const V3 xa = ld3(X, M, a), xb = ld3(X, M, b), xc = ld3(X, M, c);
   const V3 dx = second_diff(xa, xc, xb), dy = second_diff(ya, yc, yb);
-  const V3 v{dx.x - dy.x, dx.y - dy.y, dx.z - dy.z};
+  const V3 v = m.disp ? dx : V3{dx.x - dy.x, dx.y - dy.y, dx.z - dy.z};   // displacements: Da - 2Dc + Db
   return -K1 * (v.x * z.x + v.y * z.y + v.z * z.z);
 }
 
@@ -384,7 +448,7 @@ __global__ __launch_bounds__(256) void k_hessvec(Material m, const double *__res
         const V3 dy{yo.x - yq.x, yo.y - yq.y, yo.z - yq.z};
         const double kf = 0.5 * (m.k[q] + m.k[o]);
         const double wbar = 0.5 * (m.w[q] + m.w[o]);
-        kb += 0.5 * edge_adj(X, fb, M, q, o, L.Ks * wbar, kf, nrm(dy), true, hv);
+        kb += 0.5 * edge_adj(m, X, fb, M, q, o, L.Ks * wbar, kf, nrm(dy), true, hv);
       };
       if (i1 > 0) edge(idx(i1 - 1, i2));
       if (i1 < n1 - 1) edge(idx(i1 + 1, i2));
@@ -408,7 +472,7 @@ __global__ __launch_bounds__(256) void k_hessvec(Material m, const double *__res
     for (int32_t e = m.sp_rowptr[q]; e < m.sp_rowptr[q + 1]; e++) {
       const int64_t o = m.sp_col[e];
       const double kf = 0.5 * (m.k[q] + m.k[o]);
-      kb += 0.5 * edge_adj(X, fb, M, q, o, m.K_spring, kf, m.sp_rest[e], false, hv);
+      kb += 0.5 * edge_adj(m, X, fb, M, q, o, m.K_spring, kf, m.sp_rest[e], false, hv);
     }
   }
   if (m.kappa) {

@@ -87,6 +87,8 @@ struct Material {
   int64_t M;
   // reference-shape constants of the lattices, [kLatPre][M] (see k_lattice_pre), or null
   const double *lat_pre;
+  // 1: marker state arrays hold displacements D = X - X_ref (ib_params.displacement)
+  int32_t disp;
 };
 
 struct Workspace {
@@ -207,7 +209,7 @@ hipError_t launch_force_rec(ib_ctx *c, const double *X, double amp, double *F);
 // the kernel launch_force_rec launches, and the position of `amp` among its arguments
 // (for updating a captured launch)
 template <typename T>
-const void *force_rec_kernel();
+const void *force_rec_kernel(bool disp);
 constexpr int kForceRecAmpArg = 5;
 constexpr int kForceRecArgs = 13;
 template <typename T>

@@ -57,6 +57,12 @@ __device__ __forceinline__ double frac_of(double x, double h) {
   return s - floor(s);
 }
 
+// Position component i of the state X: X[i], or Y[i] + X[i] when the state
+// holds displacements from the reference shape Y.
+__device__ __forceinline__ double pos_of(const double *__restrict__ X, const double *__restrict__ Y, int64_t i) {
+  return Y ? Y[i] + X[i] : X[i];
+}
+
 // One marker at position x (its cell is the record's key): interpolate u from
 // the staged halo with FP64 weights, summing in FP64.
 template <typename T>
@@ -98,7 +104,8 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
                                                            const uint32_t *__restrict__ keys, const T *__restrict__ u,
                                                            int n, int nz, int log2nt, int64_t M, double h,
                                                            double dt, const double *__restrict__ Xpos,
-                                                           double *__restrict__ X, double *__restrict__ U) {
+                                                           const double *__restrict__ Y, double *__restrict__ X,
+                                                           double *__restrict__ U) {
   __shared__ U4<T> uh[kHalo3];
   const int tid = threadIdx.x;
   const int W = counts[0];
@@ -165,20 +172,31 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
           q[m] = perm[j];
         }
       }
-      // positions X^n (Xpos = X when moving): the weights and the move
-      double xo[kInterpPer][3];
+      // the state at step n (Xpos = X when moving: positions, or displacements
+      // with Y the reference shape) for the weights and the move
+      double xo[kInterpPer][3], yo[kInterpPer][3];
 #pragma unroll
       for (int m = 0; m < kInterpPer; m++) {
         xo[m][0] = Xpos[q[m]];
         xo[m][1] = Xpos[M + q[m]];
         xo[m][2] = Xpos[2 * M + q[m]];
+        if (Y) {
+          yo[m][0] = Y[q[m]];
+          yo[m][1] = Y[M + q[m]];
+          yo[m][2] = Y[2 * M + q[m]];
+        }
       }
 #pragma unroll
       for (int m = 0; m < kInterpPer; m++) {
         const int j = jr + tid + kInterpThreads * m;
         if (j < j1) {
           double a0, a1, a2;
-          interp_one<T>(uh, key[m], xo[m], h, a0, a1, a2);
+          if (Y) {
+            const double pos[3] = {yo[m][0] + xo[m][0], yo[m][1] + xo[m][1], yo[m][2] + xo[m][2]};
+            interp_one<T>(uh, key[m], pos, h, a0, a1, a2);
+          } else {
+            interp_one<T>(uh, key[m], xo[m], h, a0, a1, a2);
+          }
           if (U) {
             U[q[m]] = a0;
             U[M + q[m]] = a1;
@@ -205,7 +223,7 @@ __global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__
                                                     const int32_t *__restrict__ perm, Rec<T> *__restrict__ recs,
                                                     const T *__restrict__ u, int n, int nz, int log2n, int log2nt,
                                                     int64_t M, double h, double dt, const double *__restrict__ X,
-                                                    double *__restrict__ Xbar) {
+                                                    const double *__restrict__ Y, double *__restrict__ Xbar) {
   const int64_t i = gtid();
   if (i >= M) return;
   const int mask = n - 1, maskz = nz - 1;
@@ -218,7 +236,8 @@ __global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__
   recs[i].F[0] = (T)ub0;
   recs[i].F[1] = (T)ub1;
   recs[i].F[2] = (T)ub2;
-  const double f0 = frac_of(X[q], h), f1 = frac_of(X[M + q], h), f2 = frac_of(X[2 * M + q], h);
+  const double f0 = frac_of(pos_of(X, Y, q), h), f1 = frac_of(pos_of(X, Y, M + q), h),
+               f2 = frac_of(pos_of(X, Y, 2 * M + q), h);
   double wx[4], wy[4], wz[4], gx[4], gy[4], gz[4];
   phi4<double>(f0, wx);
   phi4<double>(f1, wy);
@@ -256,8 +275,8 @@ __global__ __launch_bounds__(256) void k_adj_spread(const uint32_t *__restrict__
                                                     const int32_t *__restrict__ perm, const T *__restrict__ ub,
                                                     const double *__restrict__ F, int n, int nz, int log2n,
                                                     int log2nt, int64_t M, double scale, double h,
-                                                    const double *__restrict__ X, double *__restrict__ Xbar,
-                                                    double *__restrict__ fbar) {
+                                                    const double *__restrict__ X, const double *__restrict__ Y,
+                                                    double *__restrict__ Xbar, double *__restrict__ fbar) {
   const int64_t i = gtid();
   if (i >= M) return;
   const int mask = n - 1, maskz = nz - 1;
@@ -265,7 +284,8 @@ __global__ __launch_bounds__(256) void k_adj_spread(const uint32_t *__restrict__
   const Cell cc = key_cell(keys[i], log2nt);
   const int64_t q = perm[i];
   const double f0 = F[q], f1 = F[M + q], f2 = F[2 * M + q];
-  const double r0 = frac_of(X[q], h), r1 = frac_of(X[M + q], h), r2 = frac_of(X[2 * M + q], h);
+  const double r0 = frac_of(pos_of(X, Y, q), h), r1 = frac_of(pos_of(X, Y, M + q), h),
+               r2 = frac_of(pos_of(X, Y, 2 * M + q), h);
   double wx[4], wy[4], wz[4], gx[4], gy[4], gz[4];
   phi4<double>(r0, wx);
   phi4<double>(r1, wy);
@@ -311,8 +331,8 @@ hipError_t launch_interp(ib_ctx *c, const T *u, const double *X_pos, double *X_i
   const int grid = (int)std::min<int64_t>(c->item_cap, (int64_t)c->ncu * 16);
   hipLaunchKernelGGL(k_interp<T>, dim3(grid), dim3(kInterpThreads), 0, c->stream, c->ws.tile_start,
                      c->ws.tile_item0, c->ws.item_tile, c->chunk, c->ws.nitems, c->ws.vals[c->sorted_buf],
-                     c->ws.keys[c->sorted_buf], u, c->n, c->nz, c->log2nt, c->M, c->h, dt, X_pos, X_inout,
-                     U_out);
+                     c->ws.keys[c->sorted_buf], u, c->n, c->nz, c->log2nt, c->M, c->h, dt, X_pos,
+                     c->mat.disp ? c->mat.X_ref : nullptr, X_inout, U_out);
   return hipGetLastError();
 }
 
@@ -322,7 +342,8 @@ hipError_t launch_adj_interp(ib_ctx *c, const T *u_np1, const double *X_n, doubl
   PhaseScope ps(c, PH_ADJ_INTERP);
   hipLaunchKernelGGL(k_adj_interp<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
                      c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (Rec<T> *)c->ws.recs, u_np1, c->n,
-                     c->nz, c->log2n, c->log2nt, c->M, c->h, c->p.dt, X_n, Xbar);
+                     c->nz, c->log2n, c->log2nt, c->M, c->h, c->p.dt, X_n, c->mat.disp ? c->mat.X_ref : nullptr,
+                     Xbar);
   return hipGetLastError();
 }
 
@@ -334,7 +355,7 @@ hipError_t launch_adj_spread(ib_ctx *c, const T *ubar_n, const double *F, const 
   const double scale = (c->p.dt / c->p.rho) / (c->h * c->h * c->h);
   hipLaunchKernelGGL(k_adj_spread<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
                      c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], ubar_n, F, c->n, c->nz, c->log2n,
-                     c->log2nt, c->M, scale, c->h, X_n, Xbar, fbar);
+                     c->log2nt, c->M, scale, c->h, X_n, c->mat.disp ? c->mat.X_ref : nullptr, Xbar, fbar);
   return hipGetLastError();
 }
 

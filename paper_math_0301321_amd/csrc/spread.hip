@@ -34,14 +34,15 @@ namespace ib {
 // ------------------------------------------------------------- records ----
 template <typename T>
 __global__ __launch_bounds__(256) void k_prep(const int32_t *__restrict__ perm, const uint32_t *__restrict__ keys,
-                                              const double *__restrict__ X, const double *__restrict__ F, int64_t M,
-                                              double h, Rec<T> *__restrict__ recs) {
+                                              const double *__restrict__ X, const double *__restrict__ Y,
+                                              const double *__restrict__ F, int64_t M, double h,
+                                              Rec<T> *__restrict__ recs) {
   const int64_t i = gtid();
   if (i >= M) return;
   const int64_t q = perm[i];
   Rec<T> r{};
   for (int d = 0; d < 3; d++) {
-    const double s = X[d * M + q] / h;
+    const double s = (Y ? Y[d * M + q] + X[d * M + q] : X[d * M + q]) / h;   // position: X or Y + D
     r.f[d] = (T)(s - floor(s));
     r.F[d] = F ? (T)F[d * M + q] : T(0);
   }
@@ -405,8 +406,8 @@ hipError_t launch_prep(ib_ctx *c, const double *X, const double *F) {
   if (c->M == 0) return hipSuccess;
   PhaseScope ps(c, PH_PREP);
   hipLaunchKernelGGL(k_prep<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
-                     c->ws.vals[c->sorted_buf], c->ws.keys[c->sorted_buf], X, F, c->M, c->h,
-                     (Rec<T> *)c->ws.recs);
+                     c->ws.vals[c->sorted_buf], c->ws.keys[c->sorted_buf], X,
+                     c->mat.disp ? c->mat.X_ref : nullptr, F, c->M, c->h, (Rec<T> *)c->ws.recs);
   return hipGetLastError();
 }
 

@@ -35,7 +35,8 @@ class IBError(RuntimeError):
 class ib_params(C.Structure):
     _fields_ = [("n", C.c_int32), ("L", C.c_double), ("rho", C.c_double), ("mu", C.c_double),
                 ("dt", C.c_double), ("fluid_precision", C.c_int32), ("convect", C.c_int32),
-                ("n_markers", C.c_int64), ("stream", C.c_void_p), ("nz", C.c_int32)]
+                ("n_markers", C.c_int64), ("stream", C.c_void_p), ("nz", C.c_int32),
+                ("displacement", C.c_int32)]
 
 
 class ib_lattice(C.Structure):
@@ -124,7 +125,7 @@ def fluid_noalloc(u, F=None, *, L=1.0, rho=1.0, mu=0.01, dt=1e-3, convect=1, str
         stream = torch.cuda.current_stream(u.device).cuda_stream
     p = ib_params(n, float(L), float(rho), float(mu), float(dt),
                   IB_FLUID_FP32 if u.dtype == torch.float32 else IB_FLUID_FP64, int(convect), 0,
-                  C.c_void_p(stream), nz)
+                  C.c_void_p(stream), nz, 0)
     rc = lib.ib_fluid_noalloc(C.byref(p), _ptr(u), _ptr(F))
     if rc != IB_OK:
         raise IBError(rc, lib.ib_last_error(None).decode())
@@ -135,11 +136,12 @@ class Context:
 
     ``wl`` is a :class:`paper_math_0301321_amd.workloads.Workload`.  The
     material arrays are copied to the GPU once and read by every call;
-    ``set_stiffness`` swaps the stiffness array (used by the adjoint).
+    ``set_stiffness`` swaps the stiffness array (used by the adjoint).  With
+    ``displacement=True`` every marker-state tensor holds D = X - X_ref.
     """
 
     def __init__(self, wl, precision: str = "fp32", N: int | None = None, convect: int | None = None,
-                 device: str | torch.device = "cuda", stream=None):
+                 device: str | torch.device = "cuda", stream=None, displacement: bool = False):
         self.lib = load_library()
         self.wl = wl
         self.N = int(wl.N if N is None else N)
@@ -167,9 +169,10 @@ class Context:
         if stream is None:
             stream = torch.cuda.current_stream(self.device).cuda_stream
         self.stream = stream
+        self.displacement = bool(displacement)
         p = ib_params(self.N, float(wl.L), float(wl.rho), float(wl.mu), float(wl.dt),
                       IB_FLUID_FP32 if precision == "fp32" else IB_FLUID_FP64, self.convect, self.M,
-                      C.c_void_p(stream), self.Nz)
+                      C.c_void_p(stream), self.Nz, int(self.displacement))
         e = ib_elastic(_ptr(self.w), _ptr(self.k), _ptr(self.X_ref), _ptr(self.kappa),
                        len(lats), lat_arr,
                        sab.shape[1] if sab.ndim == 2 else 0, sab.ctypes.data_as(C.c_void_p),

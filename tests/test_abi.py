@@ -76,6 +76,7 @@ def _params(ib, **kw):
     (dict(n_markers=-5), "IB_EINVAL"), (dict(n_markers=10), "IB_EINVAL"),   # no material arrays
     (dict(n=16, nz=8), "IB_ENOTSUP"), (dict(n=512, nz=256), "IB_ENOTSUP"),  # half-cube needs n in 32..256
     (dict(n=64, nz=16), "IB_ENOTSUP"), (dict(n=64, nz=128), "IB_ENOTSUP"), (dict(n=64, nz=48), "IB_ENOTSUP"),
+    (dict(displacement=2), "IB_EINVAL"), (dict(displacement=-1), "IB_EINVAL"),
 ])
 def test_create_rejects_bad_parameters(kw, code):
     from paper_math_0301321_amd import ib

@@ -10,8 +10,10 @@ own kbar by 3e-4 (measured, 20 steps).  There FP64 kbar must match the oracle
 to 1e-4.  In the mixed step the interpolation and the adjoint's gathers use
 FP64 weights and sums, so neighbouring markers' velocity differences keep the
 FP32 grid's relative accuracy (with FP32 weights the 1.5M-marker replica's
-mixed kbar was 8.6e-3 off; with FP64 weights 3.5e-4); the bounds are 5e-3 on
-the 128^3 workload and 1e-3 on the 1.5M-marker replica.  Finite differences are taken
+mixed kbar was 8.6e-3 off, with FP64 weights 3.5e-4; the 128^3 workload's
+2.5e-3 became 9.6e-5); the bounds are 5e-4 on the 128^3 workload and 1e-3 on
+the 1.5M-marker replica.  The displacement form (tests/test_gpu_displacement.py)
+removes the positions' conditioning limit altogether.  Finite differences are taken
 along directions over all membrane stiffnesses, where the loss change is far
 above its roundoff (agreement <= 1e-4); per-marker differences are roundoff
 limited to ~3e-4 even with a 100x drive, and are checked to 1e-3.
@@ -168,7 +170,7 @@ def test_rollout_config4_vs_oracle_gradient(mods, oracle_mod):
     idx = wl.meta["loss_idx"]
     announce("config4 oracle gradient")
     Lo, kbo, _, _ = oracle_mod.gradient_k(wl, wl.n_steps, idx)
-    for prec, tol, ltol in (("fp64", 1e-4, 1e-5), ("fp32", 5e-3, 2e-5)):
+    for prec, tol, ltol in (("fp64", 1e-4, 1e-5), ("fp32", 5e-4, 2e-5)):
         L, kb = _gpu_grad(ib, rollout, wl, prec, wl.n_steps, wl.meta["ckpt"], idx)
         print(f"[gpu-case] config4 {prec}: loss rel {abs(L - Lo) / Lo:.3e}, kbar rel L2 {_rel_l2(kb, kbo):.3e}",
               flush=True)

@@ -57,6 +57,28 @@ def test_bend_and_tether_forces_are_linear_in_the_displacement(oracle_mod):
     assert np.abs(F3 - 3.0 * F1).max() <= 1e-13 * np.abs(F3).max()
 
 
+def test_stretch_at_tiny_strain_matches_the_closed_form(oracle_mod):
+    """One lattice edge stretched by a strain of 1e-12 (far below the relative
+    rounding of the positions): in the displacement form the force is the
+    closed form Ks kbar wbar eps / Le along the edge to 1e-10, since the
+    extension is formed from the displacement difference."""
+    Ks, Le, eps = 50.0, 0.01, 1e-12
+    k, w = np.array([1.0, 3.0]), np.array([0.2, 0.6])
+    e = np.array([2.0, -1.0, 2.0]) / 3.0
+    ya = np.array([0.31, 0.52, 0.47])
+    Y = np.stack([ya, ya + Le * e], axis=1)
+    D = np.zeros((3, 2))
+    D[:, 1] = eps * Le * e
+    wl = W.Workload(name="edge", N=16, L=1.0, rho=1.0, mu=0.01, dt=1e-4, n_steps=1, convect=0,
+                    X0=Y + D, w=w, k=k, X_ref=Y, kappa=np.zeros(2), lattices=[W.Lattice(0, 2, 1, False, Ks, 0.0)],
+                    spring_ab=np.zeros((2, 0), np.int32), spring_rest=np.zeros(0), K_spring=0.0,
+                    drive_idx=np.zeros(0, np.int32), drive_dir=np.zeros((3, 0)), drive_A=0.0, drive_freq=0.0)
+    F = oracle_mod.force(oracle_mod.Model(wl, displacement=True), D, 0.0)
+    mag = Ks * 2.0 * 0.4 * eps / Le
+    np.testing.assert_allclose(F[:, 1], -mag * e, rtol=1e-10, atol=0)
+    np.testing.assert_allclose(F[:, 0], mag * e, rtol=1e-10, atol=0)
+
+
 def test_positions_are_reference_plus_displacement(oracle_mod):
     wl = W.tiny_helix()
     md = oracle_mod.Model(wl, displacement=True)
