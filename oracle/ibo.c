@@ -433,7 +433,8 @@ void ibo_advect_adjoint(int N, int Nz, double L, const double *u, const double *
 
 /* ------------------------------------------------------------------------
  * FFT (named, not specified, in Sec. 3.2): an iterative radix-2
- * decimation-in-time transform of length n applied along each axis.
+ * decimation-in-time transform of length n applied along each axis (the
+ * plain DFT for a length that is not a power of two).
  * Twiddles exp(sign 2 pi i j / n) are evaluated directly with cos/sin.
  * ---------------------------------------------------------------------- */
 static void fft1(int n, double *re, double *im, const double *cs, const double *sn, int sign) {
@@ -460,6 +461,25 @@ static void fft1(int n, double *re, double *im, const double *cs, const double *
   }
 }
 
+/* A length that is not a power of two (a box whose z length carries a factor
+ * 3): the DFT from its definition, X[k] = sum_j x[j] exp(sign 2 pi i j k / n),
+ * with the angle's index j k taken mod n. */
+static void dft1(int n, double *re, double *im, const double *cs, const double *sn, int sign, double *tr,
+                 double *ti) {
+  for (int k = 0; k < n; k++) {
+    double ar = 0.0, ai = 0.0;
+    for (int j = 0; j < n; j++) {
+      int64_t e = ((int64_t)j * k) % n;
+      double wr = cs[e], wi = sign * sn[e];
+      ar += re[j] * wr - im[j] * wi;
+      ai += re[j] * wi + im[j] * wr;
+    }
+    tr[k] = ar;
+    ti[k] = ai;
+  }
+  for (int k = 0; k < n; k++) { re[k] = tr[k]; im[k] = ti[k]; }
+}
+
 void ibo_fft3(int N, int Nz, double *re, double *im, int sign) {
   int64_t NN = (int64_t)N * N, G = NN * Nz;
   for (int axis = 0; axis < 3; axis++) {
@@ -471,6 +491,8 @@ void ibo_fft3(int N, int Nz, double *re, double *im, int sign) {
 #pragma omp parallel
     {
       double *br = (double *)malloc(sizeof(double) * n), *bi = (double *)malloc(sizeof(double) * n);
+      double *tr = (double *)malloc(sizeof(double) * n), *ti = (double *)malloc(sizeof(double) * n);
+      const int pow2 = (n & (n - 1)) == 0;
 #pragma omp for schedule(static)
       for (int64_t pencil = 0; pencil < npen; pencil++) {
         /* pencil enumerates the two other axes */
@@ -479,10 +501,11 @@ void ibo_fft3(int N, int Nz, double *re, double *im, int sign) {
         else if (axis == 1) base = b * NN + a;         /* (i=a, k=b) */
         else base = b * N + a;                         /* (i=a, j=b) */
         for (int t = 0; t < n; t++) { br[t] = re[base + t * stride]; bi[t] = im[base + t * stride]; }
-        fft1(n, br, bi, cs, sn, sign);
+        if (pow2) fft1(n, br, bi, cs, sn, sign);
+        else dft1(n, br, bi, cs, sn, sign, tr, ti);
         for (int t = 0; t < n; t++) { re[base + t * stride] = br[t]; im[base + t * stride] = bi[t]; }
       }
-      free(br); free(bi);
+      free(br); free(bi); free(tr); free(ti);
     }
     free(cs); free(sn);
   }
