@@ -67,24 +67,31 @@ double drive_amp(const ib_ctx *c, double t) {
   return c->drive_A * sin(2.0 * kPi * c->drive_freq * t);
 }
 
+// Twiddles, eigenvalues (4/h^2) sin^2(pi m / len) and gradient symbols
+// sin(2 pi m / len) / h (exactly 0 at m = 0, len/2) for one transform length.
 template <typename T>
-hipError_t upload_tables(ib_ctx *c) {
-  const int n = c->n;
-  const double h = c->h;
-  std::vector<T> tw(2 * n), lam(n), sg(n);
-  for (int k = 0; k < n; k++) {
-    const double a = 2.0 * kPi * (double)k / (double)n;
+hipError_t upload_tables_len(int len, double h, void *tw_d, void *lam_d, void *sg_d) {
+  std::vector<T> tw(2 * len), lam(len), sg(len);
+  for (int k = 0; k < len; k++) {
+    const double a = 2.0 * kPi * (double)k / (double)len;
     tw[2 * k] = (T)cos(a);
     tw[2 * k + 1] = (T)(-sin(a));
   }
-  for (int m = 0; m < n; m++) {
-    const double sh = sin(kPi * (double)m / (double)n);
+  for (int m = 0; m < len; m++) {
+    const double sh = sin(kPi * (double)m / (double)len);
     lam[m] = (T)((4.0 / (h * h)) * sh * sh);
-    sg[m] = (m == 0 || 2 * m == n) ? (T)0 : (T)(sin(2.0 * kPi * (double)m / (double)n) / h);
+    sg[m] = (m == 0 || 2 * m == len) ? (T)0 : (T)(sin(2.0 * kPi * (double)m / (double)len) / h);
   }
-  hipError_t e = hipMemcpy(c->ws.tw, tw.data(), sizeof(T) * 2 * n, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(c->ws.lam, lam.data(), sizeof(T) * n, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(c->ws.sgrad, sg.data(), sizeof(T) * n, hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(tw_d, tw.data(), sizeof(T) * 2 * len, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(lam_d, lam.data(), sizeof(T) * len, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(sg_d, sg.data(), sizeof(T) * len, hipMemcpyHostToDevice);
+  return e;
+}
+
+template <typename T>
+hipError_t upload_tables(ib_ctx *c) {
+  hipError_t e = upload_tables_len<T>(c->n, c->h, c->ws.tw, c->ws.lam, c->ws.sgrad);
+  if (e == hipSuccess) e = upload_tables_len<T>(c->nz, c->h, c->ws.twz, c->ws.lamz, c->ws.sgradz);
   return e;
 }
 
@@ -94,7 +101,8 @@ void free_ws(ib_ctx *c) {
   Workspace &w = c->ws;
   void *ptrs[] = {w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.hist, w.tile_start, w.recs, w.Flag, w.fb,
                   w.Fgrid, w.tile_nit, w.tile_item0, w.tile_touch, w.item_tile, w.chunk_item0, w.nitems, w.split_list, w.touch_list, w.scan_tmp, w.partials,
-                  w.r, w.spec, w.nonfinite, w.tw, w.lam, w.sgrad, w.drive_idx, w.drive_dir, w.sp_rowptr, w.sp_col,
+                  w.r, w.spec, w.nonfinite, w.tw, w.lam, w.sgrad, w.twz, w.lamz, w.sgradz, w.drive_idx, w.drive_dir,
+                  w.sp_rowptr, w.sp_col,
                   w.sp_rest, w.inv, w.drive_slot, w.lat_pre, w.touch_bits};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -145,8 +153,8 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
     return IB_ENOTSUP;
   }
   const int nz = p->nz == 0 ? n : p->nz;
-  if (nz != n && !(2 * nz == n && fluid_reg_supported(n, nz))) {
-    g_create_error = "ib_create: nz must be 0, n, or n/2 with n in [32, 256]";
+  if (nz != n && !fluid_reg_supported(n, nz)) {
+    g_create_error = "ib_create: nz must be 0 or n, or n/2 or 3n/4 with n in [32, 256]";
     return IB_ENOTSUP;
   }
   if (!(p->L > 0.0) || !is_fin(p->L) || !(p->rho > 0.0) || !is_fin(p->rho) || !(p->mu >= 0.0) || !is_fin(p->mu) ||
@@ -234,7 +242,6 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
   c->n = n;
   while ((1 << c->log2n) < n) c->log2n++;
   c->nz = nz;
-  while ((1 << c->log2nz) < nz) c->log2nz++;
   c->G = (int64_t)n * n * nz;
   c->M = M;
   c->h = p->L / n;
@@ -243,13 +250,14 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
   const char *chk = getenv("IB_CHECK");
   c->check = chk && chk[0] == '1';
   c->log2nt = c->log2n - 3;
-  c->log2ntz = c->log2nz - 3;
-  c->ntiles = (int64_t)1 << (2 * c->log2nt + c->log2ntz);
+  c->ntz = nz / 8;
+  c->ntiles = ((int64_t)1 << (2 * c->log2nt)) * c->ntz;
   c->n_springs = S;
   c->n_drive = D;
   c->drive_A = e->drive_A;
   c->drive_freq = e->drive_freq;
-  const int key_bits = 2 * c->log2n + c->log2nz;
+  int key_bits = 9;                       // the cell within its tile, then the tile index
+  while (((int64_t)1 << (key_bits - 9)) < c->ntiles) key_bits++;
   c->sort_passes = (key_bits + 7) / 8;
   c->digit_bits = (key_bits + c->sort_passes - 1) / c->sort_passes;
 
@@ -324,6 +332,9 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
   chk_alloc(dalloc_bytes(c, &w.tw, 2 * (int64_t)n * (int64_t)ts));
   chk_alloc(dalloc_bytes(c, &w.lam, (int64_t)n * (int64_t)ts));
   chk_alloc(dalloc_bytes(c, &w.sgrad, (int64_t)n * (int64_t)ts));
+  chk_alloc(dalloc_bytes(c, &w.twz, 2 * (int64_t)nz * (int64_t)ts));
+  chk_alloc(dalloc_bytes(c, &w.lamz, (int64_t)nz * (int64_t)ts));
+  chk_alloc(dalloc_bytes(c, &w.sgradz, (int64_t)nz * (int64_t)ts));
   chk_alloc(dalloc(c, &w.drive_idx, D));
   chk_alloc(dalloc(c, &w.drive_dir, 3 * D));
   if (err != hipSuccess) {

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_keys_hist(const double *__restrict__ X,
         // the position: X, or Y + D with displacements as the state
         const double s = (Y ? Y[d * M + q] + X[d * M + q] : X[d * M + q]) / h;
         int64_t cd = isfinite(s) ? (int64_t)floor(s) : 0;
-        c[d] = (int)(cd & (int64_t)((d == 2 ? nz : n) - 1));   // periodic wrap (n, nz powers of two)
+        c[d] = d == 2 ? wrap_cell(cd, nz) : (int)(cd & (int64_t)(n - 1));   // periodic wrap (n a power of two)
       }
       const uint32_t k = cell_key(c[0], c[1], c[2], log2nt);
       keys[q] = k;
@@ -233,17 +233,17 @@ __global__ __launch_bounds__(256) void k_tile_start(const uint32_t *__restrict__
 // scans of 1024 tiles, a scan of the block totals, and the writes (tile_nit,
 // tile_item0, item_tile, split_list, touch_list, tile_touch).
 __device__ __forceinline__ int3 tile_items(const int32_t *tile_start, int64_t t, int64_t ntiles, int log2nt,
-                                           int log2ntz, int chunk) {
+                                           int ntz, int chunk) {
   if (t >= ntiles) return make_int3(0, 0, 0);
   const int ts = tile_start[t], te = tile_start[t + 1];
   const int it = te > ts ? (te - 1) / chunk - ts / chunk + 1 : 0;
-  const int tmask = (1 << log2nt) - 1, tmaskz = (1 << log2ntz) - 1;
+  const int tmask = (1 << log2nt) - 1;
   const int T1 = (int)(t & tmask), T2 = (int)((t >> log2nt) & tmask), T3 = (int)(t >> (2 * log2nt));
   int touched = 0;
 #pragma unroll
   for (int d = 0; d < 27; d++) {     // all 54 loads independent
     const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
-    const int t2 = (((((T3 + dz) & tmaskz) << log2nt) | ((T2 + dy) & tmask)) << log2nt) | ((T1 + dx) & tmask);
+    const int t2 = (((((T3 + dz + ntz) % ntz) << log2nt) | ((T2 + dy) & tmask)) << log2nt) | ((T1 + dx) & tmask);
     touched |= tile_start[t2 + 1] > tile_start[t2];
   }
   return make_int3(it, it > 1 ? 1 : 0, touched);
@@ -281,14 +281,14 @@ __device__ __forceinline__ int3 scan1024(int3 v, int3 *wsum, int3 *total) {
 
 // Also stores each tile's item count and touched flag for the write pass.
 __global__ __launch_bounds__(1024) void k_item_scan_blocks(const int32_t *__restrict__ tile_start, int64_t ntiles,
-                                                           int log2nt, int log2ntz, int chunk,
+                                                           int log2nt, int ntz, int chunk,
                                                            int3 *__restrict__ block_tot,
                                                            int32_t *__restrict__ tile_nit,
                                                            int32_t *__restrict__ tile_touch,
                                                            uint32_t *__restrict__ touch_bits) {
   __shared__ int3 wsum[16];
   const int64_t t = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-  const int3 v = tile_items(tile_start, t, ntiles, log2nt, log2ntz, chunk);
+  const int3 v = tile_items(tile_start, t, ntiles, log2nt, ntz, chunk);
   if (t < ntiles) {
     tile_nit[t] = v.x;
     tile_touch[t] = v.z;
@@ -395,7 +395,7 @@ hipError_t launch_bin(ib_ctx *c, const double *X) {
   const int nsb = (int)((nt + 1023) / 1024);
   int3 *tmp = (int3 *)ws.scan_tmp;
   hipLaunchKernelGGL(k_item_scan_blocks, dim3(nsb), dim3(1024), 0, c->stream, ws.tile_start, nt, c->log2nt,
-                     c->log2ntz, c->chunk, tmp, ws.tile_nit, ws.tile_touch, ws.touch_bits);
+                     c->ntz, c->chunk, tmp, ws.tile_nit, ws.tile_touch, ws.touch_bits);
   hipLaunchKernelGGL(k_item_scan_top, dim3(1), dim3(1024), 0, c->stream, tmp, nsb, ws.nitems, c->nchunks,
                      ws.chunk_item0);
   hipLaunchKernelGGL(k_item_scan_write, dim3(nsb), dim3(1024), 0, c->stream, ws.tile_nit, nt, ws.tile_touch,

@@ -50,6 +50,27 @@ __host__ __device__ constexpr double cos32(int k) {
 }
 __host__ __device__ constexpr double sin32(int k) { return cos32(k - 8); }
 
+// cos(2 pi k / 24) for k = 0 .. 6 (FP64, correctly rounded); the rest by symmetry.
+__host__ __device__ constexpr double cos24(int k) {
+  k %= 24;
+  if (k < 0) k += 24;
+  if (k > 12) k = 24 - k;
+  const bool neg = k > 6;
+  if (neg) k = 12 - k;
+  double v = 0.0;
+  switch (k) {
+    case 0: v = 1.0; break;
+    case 1: v = 0.9659258262890683; break;
+    case 2: v = 0.8660254037844386; break;
+    case 3: v = 0.7071067811865476; break;
+    case 4: v = 0.5; break;
+    case 5: v = 0.25881904510252074; break;
+    default: v = 0.0; break;
+  }
+  return neg ? -v : v;
+}
+__host__ __device__ constexpr double sin24(int k) { return cos24(k - 6); }
+
 template <int R>
 __host__ __device__ constexpr int brev_c(int i) {
   int r = 0;
@@ -83,9 +104,10 @@ __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
   return cplx<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
-// In-register DFT of length R (2 .. 32) on v[0 .. R), natural order in and out.
+// In-register DFT of length R (1 .. 32, a power of two) on v[0 .. R), natural
+// order in and out.
 template <typename T, int R, bool INV>
-__device__ __forceinline__ void dft_reg(cplx<T> *v) {
+__device__ __forceinline__ void dft_reg2(cplx<T> *v) {
 #pragma unroll
   for (int i = 0; i < R; i++) {
     const int j = brev_c<R>(i);
@@ -118,6 +140,43 @@ __device__ __forceinline__ void dft_reg(cplx<T> *v) {
       }
     }
   }
+}
+
+// In-register DFT of length R = 3 Q (Q a power of two, R | 24): the three
+// decimated sequences v[3m + r] transformed with length Q, then combined,
+// X[k] = sum_r W^{r k} Y_r[k mod Q], W = exp(-+2 pi i / R).
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_reg3(cplx<T> *v) {
+  constexpr int Q = R / 3;
+  static_assert(3 * Q == R && 24 % R == 0, "R = 3, 6, 12 or 24");
+  cplx<T> a[3][Q];
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+#pragma unroll
+    for (int m = 0; m < Q; m++) a[r][m] = v[3 * m + r];
+#pragma unroll
+  for (int r = 0; r < 3; r++) dft_reg2<T, Q, INV>(a[r]);
+#pragma unroll
+  for (int k = 0; k < R; k++) {
+    const int km = k % Q;
+    cplx<T> acc = a[0][km];
+#pragma unroll
+    for (int r = 1; r < 3; r++) {
+      const int e = ((r * k) % R) * (24 / R);     // the angle 2 pi r k / R in 24ths of a turn
+      const T wr = (T)cos24(e), wi = INV ? (T)sin24(e) : (T)(-sin24(e));
+      const cplx<T> b = a[r][km];
+      acc.x += b.x * wr - b.y * wi;
+      acc.y += b.x * wi + b.y * wr;
+    }
+    v[k] = acc;
+  }
+}
+
+// In-register DFT of length R: a power of two up to 32, or 3 times one (R | 24).
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_reg(cplx<T> *v) {
+  if constexpr (R % 3 == 0) dft_reg3<T, R, INV>(v);
+  else dft_reg2<T, R, INV>(v);
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -262,7 +321,6 @@ __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf_rhs(
   constexpr int EPC = 16 / sizeof(T), CPR = N / EPC;
   constexpr int64_t NN = (int64_t)N * N;
   const int64_t G = NN * nz;
-  const int zmask = nz - 1;
   constexpr int RUNS = 3 * YB * CPR / NT;              // r runs per thread
   static_assert(RUNS * NT == 3 * YB * CPR, "runs must divide among the threads");
   constexpr int GMAX = sizeof(T) == 4 ? 8 : 4;
@@ -273,6 +331,7 @@ __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf_rhs(
   const int nyb = N / YB;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int y0 = (b % nyb) * YB, z = b / nyb;
+  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;   // periodic z neighbours
   const int tid = threadIdx.x;
   constexpr uint32_t TB = sizeof(T);
   const __amdgpu_buffer_rsrc_t urs = spec_rsrc(u, (uint32_t)(3 * G * TB));
@@ -307,8 +366,8 @@ __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf_rhs(
       int row, x4;
       const uint32_t at = run_at(g0 + k, row, x4);
       if (CONV) {
-        vzm[k] = bload16<T>(urs, at + (uint32_t)(((z - 1) & zmask) * NN * TB));
-        vzp[k] = bload16<T>(urs, at + (uint32_t)(((z + 1) & zmask) * NN * TB));
+        vzm[k] = bload16<T>(urs, at + (uint32_t)(zm * NN * TB));
+        vzp[k] = bload16<T>(urs, at + (uint32_t)(zp * NN * TB));
       }
       fv[k] = bload16<T>(frs, has[g0 + k] ? at + (uint32_t)(z * NN * TB) : fbytes);
     }
@@ -472,16 +531,16 @@ __global__ __launch_bounds__(256) void k_y(cplx<T> *__restrict__ spec, int64_t n
 }
 
 // ------------------------------------------------- pass z with the solve ----
-// z transforms of length NZ = R1 R2 on a grid of NY x NY x NZ nodes (NZ = NY
-// or NY / 2); the tables are those of length NY, read at stride NY / NZ.
+// z transforms of length NZ = R1 R2 on a grid of NY x NY x NZ nodes (NZ = NY,
+// NY / 2 or 3 NY / 4) with the tables of length NZ (twz, lamz, sgz); the x and
+// y modes read the tables of length NY (lam, sg).
 template <typename T, int R1, int R2, int NY>
 __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ? 2 : 1) void k_z_solve(
-    cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ tw, const T *__restrict__ lam,
-    const T *__restrict__ sg, T nu_dt) {
-  constexpr int NZ = R1 * R2, TS = NY / NZ;
-  static_assert(TS * NZ == NY && (TS == 1 || TS == 2), "nz = n or n / 2");
-  using Ff = Fft4<T, R1, R2, false, true, TS>;
-  using Fi = Fft4<T, R2, R1, true, true, TS>;
+    cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ twz, const T *__restrict__ lamz,
+    const T *__restrict__ sgz, const T *__restrict__ lam, const T *__restrict__ sg, T nu_dt) {
+  constexpr int NZ = R1 * R2;
+  using Ff = Fft4<T, R1, R2, false, true>;
+  using Fi = Fft4<T, R2, R1, true, true>;
   constexpr int P = Ff::P, E = Ff::E, YB = XfCfg<T>::YB, NH = NY / 2 + 1;
   // per-y exchange space, padded to 2 (mod 32) values so that the 16 y's and
   // neighbouring t's of a wave fall in distinct LDS banks
@@ -504,7 +563,7 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ?
       for (int j = 0; j < R1; j++)
         v[c][i * R1 + j] = bload(rs, voff, c * cs + (uint32_t)((P * i + R2 * j) * NY) * CB, T(0));
 #pragma unroll
-  for (int c = 0; c < 3; c++) Ff::run(v[c], t, xch + yy * XSZ, tw);
+  for (int c = 0; c < 3; c++) Ff::run(v[c], t, xch + yy * XSZ, twz);
   // per mode (kx, ky, kz): w = r^/(1 + nu dt lambda), then remove the s-component
   const int ky = y0 + yy;
   const T lxy = lam[kx] + lam[ky];
@@ -515,8 +574,8 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ?
     for (int k2 = 0; k2 < R2; k2++) {
       const int e = i * R2 + k2;
       const int kz = (t + P * i) + R1 * k2;
-      const T rden = T(1) / (T(1) + nu_dt * (lxy + lam[kz * TS]));
-      const T s2 = sg[kz * TS];
+      const T rden = T(1) / (T(1) + nu_dt * (lxy + lamz[kz]));
+      const T s2 = sgz[kz];
       cplx<T> w0{v[0][e].x * rden, v[0][e].y * rden};
       cplx<T> w1{v[1][e].x * rden, v[1][e].y * rden};
       cplx<T> w2{v[2][e].x * rden, v[2][e].y * rden};
@@ -535,7 +594,7 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ?
     }
   }
 #pragma unroll
-  for (int c = 0; c < 3; c++) Fi::run(v[c], t, xch + yy * XSZ, tw);
+  for (int c = 0; c < 3; c++) Fi::run(v[c], t, xch + yy * XSZ, twz);
 #pragma unroll
   for (int c = 0; c < 3; c++)
 #pragma unroll
@@ -749,7 +808,8 @@ hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect
   }
   {
     PhaseScope ps(c, PH_FFT_Z_SOLVE);
-    hipLaunchKernelGGL((k_z_solve<T, Z1, Z2, N>), dim3(NH * (N / YB)), dim3(YB * PZ), 0, c->stream, spec, tw,
+    hipLaunchKernelGGL((k_z_solve<T, Z1, Z2, N>), dim3(NH * (N / YB)), dim3(YB * PZ), 0, c->stream, spec,
+                       (const cplx<T> *)c->ws.twz, (const T *)c->ws.lamz, (const T *)c->ws.sgradz,
                        (const T *)c->ws.lam, (const T *)c->ws.sgrad, (T)(c->p.mu * c->p.dt / c->p.rho));
   }
   if constexpr (yx_merged<T, R1, R2>()) {
@@ -774,26 +834,31 @@ hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect
 }  // namespace
 
 bool fluid_reg_supported(int n, int nz) {
-  return (n == 32 || n == 64 || n == 128 || n == 256) && (nz == n || 2 * nz == n);
+  return (n == 32 || n == 64 || n == 128 || n == 256) && (nz == n || 2 * nz == n || 4 * nz == 3 * n);
 }
 
 template <typename T>
 hipError_t launch_fluid_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect, double f_scale,
                             T *u_out) {
-  const bool half = 2 * c->nz == c->n;
+  // z factors: nz = n (cube), n / 2 (half-cube), 3 n / 4 (a factor 3 along z)
+  const int zk = c->nz == c->n ? 0 : (2 * c->nz == c->n ? 1 : 2);
   switch (c->n) {
     case 32:
-      return half ? run_reg<T, 8, 4, 4, 4>(c, u_in, Fg, fmode, convect, f_scale, u_out)
-                  : run_reg<T, 8, 4, 8, 4>(c, u_in, Fg, fmode, convect, f_scale, u_out);
+      return zk == 0 ? run_reg<T, 8, 4, 8, 4>(c, u_in, Fg, fmode, convect, f_scale, u_out)
+           : zk == 1 ? run_reg<T, 8, 4, 4, 4>(c, u_in, Fg, fmode, convect, f_scale, u_out)
+                     : run_reg<T, 8, 4, 12, 2>(c, u_in, Fg, fmode, convect, f_scale, u_out);
     case 64:
-      return half ? run_reg<T, 8, 8, 8, 4>(c, u_in, Fg, fmode, convect, f_scale, u_out)
-                  : run_reg<T, 8, 8, 8, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out);
+      return zk == 0 ? run_reg<T, 8, 8, 8, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out)
+           : zk == 1 ? run_reg<T, 8, 8, 8, 4>(c, u_in, Fg, fmode, convect, f_scale, u_out)
+                     : run_reg<T, 8, 8, 12, 4>(c, u_in, Fg, fmode, convect, f_scale, u_out);
     case 128:
-      return half ? run_reg<T, 16, 8, 8, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out)
-                  : run_reg<T, 16, 8, 16, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out);
+      return zk == 0 ? run_reg<T, 16, 8, 16, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out)
+           : zk == 1 ? run_reg<T, 16, 8, 8, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out)
+                     : run_reg<T, 16, 8, 24, 4>(c, u_in, Fg, fmode, convect, f_scale, u_out);
     case 256:
-      return half ? run_reg<T, 16, 16, 16, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out)
-                  : run_reg<T, 16, 16, 16, 16>(c, u_in, Fg, fmode, convect, f_scale, u_out);
+      return zk == 0 ? run_reg<T, 16, 16, 16, 16>(c, u_in, Fg, fmode, convect, f_scale, u_out)
+           : zk == 1 ? run_reg<T, 16, 16, 16, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out)
+                     : run_reg<T, 16, 16, 24, 8>(c, u_in, Fg, fmode, convect, f_scale, u_out);
     default: return hipErrorInvalidValue;
   }
 }

@@ -311,13 +311,14 @@ __global__ __launch_bounds__(256) void k_adv_adjoint(const T *__restrict__ u, co
   const int64_t G = (int64_t)nz << (2 * log2n);
   const int64_t p = gtid();
   if (p >= G) return;
-  const int mask = n - 1, maskz = nz - 1;
+  const int mask = n - 1;
   const int x = (int)(p & mask), y = (int)((p >> log2n) & mask), z = (int)(p >> (2 * log2n));
+  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;   // periodic z neighbours
   const int64_t zo = (int64_t)z << (2 * log2n), yo = (int64_t)y << log2n;
   const int64_t pm[3] = {zo + yo + ((x - 1) & mask), zo + ((int64_t)((y - 1) & mask) << log2n) + x,
-                         ((int64_t)((z - 1) & maskz) << (2 * log2n)) + yo + x};
+                         ((int64_t)zm << (2 * log2n)) + yo + x};
   const int64_t pp[3] = {zo + yo + ((x + 1) & mask), zo + ((int64_t)((y + 1) & mask) << log2n) + x,
-                         ((int64_t)((z + 1) & maskz) << (2 * log2n)) + yo + x};
+                         ((int64_t)zp << (2 * log2n)) + yo + x};
 #pragma unroll
   for (int c = 0; c < 3; c++) {
     T acc = T(0);

@@ -313,7 +313,7 @@ __global__ __launch_bounds__(256) void k_force_rec(Material m, const double *__r
     const double fl = floor(s);
     r.f[d] = (T)(s - fl);
     const int64_t ci = isfinite(s) ? (int64_t)fl : 0;
-    cc[d] = (int)(ci & (int64_t)((d == 2 ? nz : n) - 1));
+    cc[d] = d == 2 ? wrap_cell(ci, nz) : (int)(ci & (int64_t)(n - 1));   // as the binning wraps
   }
   r.F[0] = (T)f.x;
   r.F[1] = (T)f.y;

@@ -46,6 +46,13 @@ __host__ __device__ __forceinline__ uint32_t cell_key(int cx, int cy, int cz, in
   const uint32_t tile = ((uint32_t)(cz >> 3) << (2 * log2nt)) | ((uint32_t)(cy >> 3) << log2nt) | (uint32_t)(cx >> 3);
   return (tile << 9) | ((uint32_t)(cz & 7) << 6) | ((uint32_t)(cy & 7) << 3) | (uint32_t)(cx & 7);
 }
+// A cell (or node) index wrapped periodically into [0, len), len any positive
+// length (the z length need not be a power of two).
+__host__ __device__ __forceinline__ int wrap_cell(int64_t c, int len) {
+  const int64_t r = c % len;
+  return (int)(r < 0 ? r + len : r);
+}
+
 // Position of a cell's stencil origin (node cell - 1) in its tile's 11^3 halo.
 __host__ __device__ __forceinline__ int halo_base(uint32_t key) {
   return (int)((key >> 6) & 7) * (kHalo * kHalo) + (int)((key >> 3) & 7) * kHalo + (int)(key & 7);
@@ -120,12 +127,11 @@ struct Workspace {
   void *r;                     // [3][G] right-hand side (radix-2 path only; null for n = 32 .. 256)
   void *spec;                  // [3][n/2+1][nz][n] complex spectrum
   int32_t *nonfinite;          // [1] flag for checked mode
-  // tables (fluid precision)
-  // Along z (nz = n / s, s = 1 or 2) the same tables serve with stride s:
-  // exp(-2 pi i k / nz) = tw[s k], and likewise lam and sgrad.
+  // tables (fluid precision): along x and y of length n, along z of length nz
   void *tw;                    // [n] complex exp(-2 pi i k / n)
   void *lam;                   // [n] (4/h^2) sin^2(pi m / n)
   void *sgrad;                 // [n] sin(2 pi m / n) / h (exact 0 at m = 0, n/2)
+  void *twz, *lamz, *sgradz;   // the same for length nz
   // drive
   int32_t *drive_idx;          // [D]
   double *drive_dir;           // [3][D]
@@ -153,7 +159,7 @@ struct TimerRec {
 struct ib_ctx {
   ib_params p;
   int n = 0, log2n = 0;
-  int nz = 0, log2nz = 0;   // nodes along z: n (cube) or n / 2 (half-cube)
+  int nz = 0;               // nodes along z: n (cube), n / 2 (half-cube) or 3 n / 4
   int64_t G = 0, M = 0;     // G = n * n * nz
   double h = 0.0;
   bool fp32 = false;
@@ -168,7 +174,7 @@ struct ib_ctx {
   int sort_passes = 0, digit_bits = 0;
   int sorted_buf = 0;   // which keys/vals buffer holds the sorted result
   int log2nt = 0;       // log2(n / 8)
-  int log2ntz = 0;      // log2(nz / 8)
+  int ntz = 0;          // nz / 8 (tiles along z)
   int64_t ntiles = 0;
   int ncu = 256;        // compute units of the device
   int item_grid = 0;    // most single-wave blocks of the spreading kernel

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
   __shared__ U4<T> uh[kHalo3];
   const int tid = threadIdx.x;
   const int W = counts[0];
-  const int mask = n - 1, maskz = nz - 1, tmask = (1 << log2nt) - 1;
+  const int mask = n - 1, tmask = (1 << log2nt) - 1;
   const int64_t G = (int64_t)n * n * nz;
   constexpr int kPer = (kHalo3 + kInterpThreads - 1) / kInterpThreads;
   // blocks in runs of 16 per XCD: neighbouring items (tiles) share halo rows in its L2
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
     for (int i = 0; i < kPer; i++) {
       const int e = min(tid + kInterpThreads * i, kHalo3 - 1);
       const int hz = e / (kHalo * kHalo), r = e - hz * (kHalo * kHalo), hy = r / kHalo, hx = r - hy * kHalo;
-      const int64_t p = ((int64_t)((z0 + hz) & maskz) * n + ((y0 + hy) & mask)) * n + ((x0 + hx) & mask);
+      const int64_t p = ((int64_t)wrap_cell(z0 + hz, nz) * n + ((y0 + hy) & mask)) * n + ((x0 + hx) & mask);
       hv[i][0] = u[p];
       hv[i][1] = u[G + p];
       hv[i][2] = u[2 * G + p];
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__
                                                     const double *__restrict__ Y, double *__restrict__ Xbar) {
   const int64_t i = gtid();
   if (i >= M) return;
-  const int mask = n - 1, maskz = nz - 1;
+  const int mask = n - 1;
   const int64_t G = (int64_t)nz << (2 * log2n);
   const Cell cc = key_cell(keys[i], log2nt);
   const int64_t q = perm[i];
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__
   dphi4<double>(f2, gz);
   double g0 = 0, g1 = 0, g2 = 0;
   for (int c3 = 0; c3 < 4; c3++) {
-    const int64_t zo = (int64_t)((cc.z + c3 - 1) & maskz) << (2 * log2n);
+    const int64_t zo = (int64_t)wrap_cell(cc.z + c3 - 1, nz) << (2 * log2n);
     for (int c2 = 0; c2 < 4; c2++) {
       const int64_t yo = zo + ((int64_t)((cc.y + c2 - 1) & mask) << log2n);
       for (int c1 = 0; c1 < 4; c1++) {
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(256) void k_adj_spread(const uint32_t *__restrict__
                                                     double *__restrict__ Xbar, double *__restrict__ fbar) {
   const int64_t i = gtid();
   if (i >= M) return;
-  const int mask = n - 1, maskz = nz - 1;
+  const int mask = n - 1;
   const int64_t G = (int64_t)nz << (2 * log2n);
   const Cell cc = key_cell(keys[i], log2nt);
   const int64_t q = perm[i];
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(256) void k_adj_spread(const uint32_t *__restrict__
   dphi4<double>(r2, gz);
   double a0 = 0, a1 = 0, a2 = 0, g0 = 0, g1 = 0, g2 = 0;
   for (int c3 = 0; c3 < 4; c3++) {
-    const int64_t zo = (int64_t)((cc.z + c3 - 1) & maskz) << (2 * log2n);
+    const int64_t zo = (int64_t)wrap_cell(cc.z + c3 - 1, nz) << (2 * log2n);
     for (int c2 = 0; c2 < 4; c2++) {
       const int64_t yo = zo + ((int64_t)((cc.y + c2 - 1) & mask) << log2n);
       for (int c1 = 0; c1 < 4; c1++) {

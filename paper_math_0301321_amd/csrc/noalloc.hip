@@ -47,8 +47,9 @@ hipError_t scratch_for(int dev, void **out) {
 }
 
 // Twiddles exp(-2 pi i k / n), eigenvalues (4/h^2) sin^2(pi m / n) and gradient
-// symbols sin(2 pi m / n) / h (exactly 0 at m = 0, n/2): the tables ib_create
-// computes on the host, here in FP64 on the device and rounded once.
+// symbols sin(2 pi m / n) / h (exactly 0 at m = 0, n/2) for one transform
+// length n: the tables ib_create computes on the host, here in FP64 on the
+// device and rounded once.
 template <typename T>
 __global__ __launch_bounds__(256) void k_fluid_tables(int n, double h, T *__restrict__ tw, T *__restrict__ lam,
                                                       T *__restrict__ sg) {
@@ -70,7 +71,8 @@ int fluid_noalloc(const ib_params *p, int nz, T *u, const T *F) {
   const size_t ts = sizeof(T);
   const size_t spec_b = align256((size_t)3 * (n / 2 + 1) * n * nz * 2 * ts);
   const size_t tw_b = align256((size_t)2 * n * ts), tab_b = align256((size_t)n * ts);
-  const size_t need = spec_b + tw_b + 2 * tab_b;
+  const size_t twz_b = align256((size_t)2 * nz * ts), tabz_b = align256((size_t)nz * ts);
+  const size_t need = spec_b + tw_b + 2 * tab_b + twz_b + 2 * tabz_b;
   if (need > kNoAllocBytes) {
     set_context_free_error("ib_fluid_noalloc: " + std::to_string(n) + " x " + std::to_string(n) + " x " +
                            std::to_string(nz) + " in this precision needs " + std::to_string(need) +
@@ -101,9 +103,18 @@ int fluid_noalloc(const ib_params *p, int nz, T *u, const T *F) {
   c.ws.tw = b + spec_b;
   c.ws.lam = b + spec_b + tw_b;
   c.ws.sgrad = b + spec_b + tw_b + tab_b;
+  unsigned char *bz = b + spec_b + tw_b + 2 * tab_b;
+  c.ws.twz = bz;
+  c.ws.lamz = bz + twz_b;
+  c.ws.sgradz = bz + twz_b + tabz_b;
   hipLaunchKernelGGL(k_fluid_tables<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, n, c.h,
                      (T *)c.ws.tw, (T *)c.ws.lam, (T *)c.ws.sgrad);
   e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_fluid_tables<T>, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, c.stream, nz, c.h,
+                       (T *)c.ws.twz, (T *)c.ws.lamz, (T *)c.ws.sgradz);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) e = launch_fluid_reg<T>(&c, u, F, F ? 2 : 0, p->convect, p->dt / p->rho, u);
   if (e != hipSuccess) {
     set_context_free_error(std::string("ib_fluid_noalloc: launch failed: ") + hipGetErrorString(e));
@@ -121,7 +132,7 @@ extern "C" int ib_fluid_noalloc(const ib_params *p, void *u, const void *F_grid)
   }
   const int n = p->n, nz = p->nz == 0 ? n : p->nz;
   if (!fluid_reg_supported(n, nz)) {
-    set_context_free_error("ib_fluid_noalloc: n must be 32, 64, 128 or 256 and nz 0, n or n/2");
+    set_context_free_error("ib_fluid_noalloc: n must be 32, 64, 128 or 256 and nz 0, n, n/2 or 3n/4");
     return IB_ENOTSUP;
   }
   if (!(p->L > 0.0) || !isfinite(p->L) || !(p->rho > 0.0) || !isfinite(p->rho) || !(p->mu >= 0.0) ||

@@ -317,11 +317,11 @@ __global__ __launch_bounds__(256) void k_spread_gather(const int32_t *__restrict
                                                        const int32_t *__restrict__ tile_nit,
                                                        const int32_t *__restrict__ tile_item0,
                                                        const T *__restrict__ partials, int n, int nz, int log2nt,
-                                                       int log2ntz, T *__restrict__ Fgrid) {
+                                                       int ntz, T *__restrict__ Fgrid) {
   __shared__ T Vs[4][kSrcPerLane * 64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int ntouch = counts[2];
-  const int tmask = (1 << log2nt) - 1, tmaskz = (1 << log2ntz) - 1;
+  const int tmask = (1 << log2nt) - 1;
   const int64_t G = (int64_t)n * n * nz;
   const int px = lane & 7, py = lane >> 3;
   // source slots of this lane's column: x, y positions in the 11^3 source cube
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(256) void k_spread_gather(const int32_t *__restrict
     int nb_base = -1;                     // first halo value of neighbour `lane`, -1 without markers
     if (lane < 27) {
       const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
-      const int t2 = (((((T3 + dz) & tmaskz) << log2nt) | ((T2 + dy) & tmask)) << log2nt) | ((T1 + dx) & tmask);
+      const int t2 = (((((T3 + dz + ntz) % ntz) << log2nt) | ((T2 + dy) & tmask)) << log2nt) | ((T1 + dx) & tmask);
       if (tile_nit[t2] > 0) nb_base = tile_item0[t2] * kPartStride;
     }
     T *dst = Fgrid + (((int64_t)(8 * T3) * n + 8 * T2 + py) * n + 8 * T1 + px);
@@ -428,7 +428,7 @@ hipError_t launch_spread(ib_ctx *c, T *Fgrid, bool dense, double scale) {
   PhaseScope ps(c, PH_GATHER);
   hipLaunchKernelGGL(k_spread_gather<T>, dim3((unsigned)std::min<int64_t>((c->ntiles + 3) / 4, 5 * c->ncu)),
                      dim3(256), 0, c->stream, c->ws.touch_list, c->ws.nitems, c->ws.tile_nit, c->ws.tile_item0,
-                     (const T *)c->ws.partials, c->n, c->nz, c->log2nt, c->log2ntz, Fgrid);
+                     (const T *)c->ws.partials, c->n, c->nz, c->log2nt, c->ntz, Fgrid);
   if (dense)
     hipLaunchKernelGGL(k_spread_zero<T>, dim3((unsigned)c->ntiles), dim3(256), 0, c->stream, c->ws.tile_touch, c->n,
                        c->nz, c->log2nt, Fgrid);

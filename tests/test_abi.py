@@ -75,7 +75,8 @@ def _params(ib, **kw):
     (dict(fluid_precision=7), "IB_EINVAL"), (dict(convect=2), "IB_EINVAL"),
     (dict(n_markers=-5), "IB_EINVAL"), (dict(n_markers=10), "IB_EINVAL"),   # no material arrays
     (dict(n=16, nz=8), "IB_ENOTSUP"), (dict(n=512, nz=256), "IB_ENOTSUP"),  # half-cube needs n in 32..256
-    (dict(n=64, nz=16), "IB_ENOTSUP"), (dict(n=64, nz=128), "IB_ENOTSUP"), (dict(n=64, nz=48), "IB_ENOTSUP"),
+    (dict(n=64, nz=16), "IB_ENOTSUP"), (dict(n=64, nz=128), "IB_ENOTSUP"), (dict(n=64, nz=40), "IB_ENOTSUP"),
+    (dict(n=16, nz=12), "IB_ENOTSUP"), (dict(n=512, nz=384), "IB_ENOTSUP"),   # 3n/4 needs n in 32..256
     (dict(displacement=2), "IB_EINVAL"), (dict(displacement=-1), "IB_EINVAL"),
 ])
 def test_create_rejects_bad_parameters(kw, code):

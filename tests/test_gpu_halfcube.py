@@ -52,7 +52,7 @@ def _markers(N, M, seed):
 
 def test_create_rejects_other_shapes(ibm):
     X = np.zeros((3, 0))
-    for n, nz in ((16, 8), (512, 256), (64, 16), (64, 128), (64, 48)):
+    for n, nz in ((16, 8), (512, 256), (64, 16), (64, 128), (64, 40), (16, 12)):
         wl = _free_wl(n, X)
         wl.Nz = nz
         with pytest.raises(ibm.IBError) as ei:
