@@ -191,7 +191,10 @@ __device__ __forceinline__ void wave_sync() {
 // xch: R1 (R2 + 1) LDS values private to the pencil.  BLOCK: the pencil's
 // threads span several waves (block barrier) instead of one (wave barrier).
 // tw holds exp(-2 pi i k / (TS N)); the transform reads it at stride TS.
-template <typename T, int R1, int R2, bool INV, bool BLOCK, int TS = 1>
+// FRESH_TW: the twiddles are read again in every call rather than kept in
+// registers from an earlier call (for kernels whose register budget is
+// taken by pencils held across calls).
+template <typename T, int R1, int R2, bool INV, bool BLOCK, int TS = 1, bool FRESH_TW = false>
 struct Fft4 {
   static constexpr int N = R1 * R2;
   static constexpr int P = R1 < R2 ? R1 : R2;
@@ -204,6 +207,7 @@ struct Fft4 {
   __device__ static __forceinline__ void run(cplx<T> *v, int t, cplx<T> *xch, const cplx<T> *__restrict__ tw) {
 #pragma unroll
     for (int i = 0; i < R2 / P; i++) dft_reg<T, R1, INV>(v + i * R1);
+    if constexpr (FRESH_TW) asm volatile("" : "+s"(tw));   // an opaque copy: loads through it are not reused
 #pragma unroll
     for (int i = 0; i < R2 / P; i++) {
       const int s = t + P * i;
@@ -699,7 +703,7 @@ template <typename T, int R1, int R2>
 __global__ __launch_bounds__(1024) void k_yxi(const cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ tw,
                                               T scale, T *__restrict__ u, int nz) {
   using C = YxiCfg<T, R1, R2>;
-  using F4 = Fft4<T, R1, R2, true, false>;
+  using F4 = Fft4<T, R1, R2, true, false, 1, true>;
   constexpr int N = C::N, NH = C::NH, P = C::P, E = F4::E, TS = C::TS;
   static_assert(R2 / P == 1 && R1 / P == 1, "square four-step factors");
   __shared__ __attribute__((aligned(16))) unsigned char smem[C::BYTES];
