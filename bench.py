@@ -35,7 +35,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 # phases timed by exactly one kernel launch (the roofline kernel is chosen among them)
 SINGLE_KERNEL = {"force": "k_force_rec", "spread": "k_spread", "split": "k_split_reduce",
                  "gather": "k_spread_gather", "rhs_fft_x": "k_xf_rhs", "fft_y": "k_y",
-                 "fft_z_solve": "k_z_solve", "fft_y_inv": "k_y", "fft_x_inv": "k_xi", "interp": "k_interp"}
+                 "fft_z_solve": "k_z_solve", "fft_y_inv": "k_y", "fft_x_inv": "k_xi",
+                 "fft_yx_inv": "k_yxi", "interp": "k_interp"}
 
 
 def worklist_sizes(wl, ncu=256):
@@ -48,7 +49,7 @@ def worklist_sizes(wl, ncu=256):
     n, nt, ntz = wl.N, wl.N // 8, wl.nz // 8
     c = np.floor(wl.X0 / wl.h).astype(np.int64)
     c[:2] &= n - 1
-    c[2] &= wl.nz - 1
+    c[2] %= wl.nz
     t = c // 8
     tile = (t[2] * nt + t[1]) * nt + t[0]
     K = np.bincount(tile, minlength=nt * nt * ntz)
@@ -92,13 +93,15 @@ def phase_bytes(phase, N, M, b, wls, Nz=None):
         "fft_z_solve": 2 * spec,
         "fft_y_inv": 2 * spec,
         "fft_x_inv": spec + grid,
+        "fft_yx_inv": spec + grid,
         "interp": M * (4 + 4 + 48) + touched * 512 * 3 * b,    # cell key, perm, X in/out; u of touched tiles
     }.get(phase)
 
 
 KERNEL_SOURCE = {"k_force_rec": "force.hip", "k_spread": "spread.hip", "k_split_reduce": "spread.hip",
                  "k_spread_gather": "spread.hip", "k_xf_rhs": "fft_reg.hip",
-                 "k_y": "fft_reg.hip", "k_z_solve": "fft_reg.hip", "k_xi": "fft_reg.hip", "k_interp": "interp.hip"}
+                 "k_y": "fft_reg.hip", "k_z_solve": "fft_reg.hip", "k_xi": "fft_reg.hip", "k_yxi": "fft_reg.hip",
+                 "k_interp": "interp.hip"}
 
 
 def traffic_for(kernel, workload):

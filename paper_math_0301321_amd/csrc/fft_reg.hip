@@ -742,19 +742,22 @@ __global__ __launch_bounds__(1024) void k_yxi(const cplx<T> *__restrict__ spec, 
   // row pairs (2r, 2r + 1), r = s, and the rows written out
 #pragma unroll
   for (int h = 0; h < 2; h++) {
+    int th = threadIdx.x;
+    asm volatile("" : "+v"(th));   // addresses formed anew in each half
+    const int sh = th / P, tt = th % P;   // s and t
     __syncthreads();   // the previous half's exchange space is free
 #pragma unroll
     for (int k2 = 0; k2 < R2 / 2; k2++) {
-      const int yl = t + R1 * k2;                  // row within the half
-      tr[yl * TS + s] = va[k2 + h * R2 / 2];
-      tr[yl * TS + s + C::SLOTS] = vb[k2 + h * R2 / 2];
+      const int yl = tt + R1 * k2;                  // row within the half
+      tr[yl * TS + sh] = va[k2 + h * R2 / 2];
+      tr[yl * TS + sh + C::SLOTS] = vb[k2 + h * R2 / 2];
     }
     __syncthreads();
-    const int r0 = 2 * s;
+    const int r0 = 2 * sh;
     cplx<T> v[E];
 #pragma unroll
     for (int j = 0; j < R1; j++) {
-      const int k = t + R2 * j;
+      const int k = tt + R2 * j;
       const bool hi = k > N / 2;
       const int kk = hi ? N - k : k;
       cplx<T> a = kk == N / 2 ? nyq[h * C::HALF + r0] : tr[r0 * TS + kk];
@@ -766,11 +769,11 @@ __global__ __launch_bounds__(1024) void k_yxi(const cplx<T> *__restrict__ spec, 
       v[j] = cplx<T>{a.x - b.y, a.y + b.x};
     }
     __syncthreads();   // the transpose is consumed: its space becomes exchange space
-    F4::run(v, t, xch, tw);
+    F4::run(v, tt, xch, tw);
     T *ra = u + c * G + ((int64_t)z * N + h * C::HALF + r0) * N;
 #pragma unroll
     for (int k2 = 0; k2 < R2; k2++) {
-      const int x = t + R1 * k2;
+      const int x = tt + R1 * k2;
       ra[x] = v[k2].x * scale;
       ra[N + x] = v[k2].y * scale;
     }
@@ -792,6 +795,8 @@ hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect
   if (c->n != N || nz != NZ) return hipErrorInvalidValue;
   cplx<T> *spec = (cplx<T> *)c->ws.spec;
   const cplx<T> *tw = (const cplx<T> *)c->ws.tw;
+  const int64_t npen = (int64_t)3 * NH * NZ;
+  const unsigned ny = (unsigned)((npen + 256 / P - 1) / (256 / P));
   {
     PhaseScope ps(c, PH_RHS_FFT_X);
     const int fm = Fg ? fmode : 0;
@@ -804,8 +809,6 @@ hipError_t run_reg(ib_ctx *c, const T *u_in, const T *Fg, int fmode, int convect
       hipLaunchKernelGGL((k_xf_rhs<T, R1, R2, YR, false>), dim3(NZ * (N / YR)), dim3(3 * YR / 2 * P), 0, c->stream,
                          u_in, Fg, c->ws.touch_bits, fm, dtih, (T)f_scale, tw, spec, nz);
   }
-  const int64_t npen = (int64_t)3 * NH * NZ;
-  const unsigned ny = (unsigned)((npen + 256 / P - 1) / (256 / P));
   {
     PhaseScope ps(c, PH_FFT_Y);
     hipLaunchKernelGGL((k_y<T, R1, R2, false>), dim3(ny), dim3(256), 0, c->stream, spec, npen, tw);

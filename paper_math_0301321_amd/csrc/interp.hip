@@ -95,7 +95,7 @@ __device__ __forceinline__ void interp_one(const U4<T> *uh, uint32_t key, const 
 // Per round a thread takes up to kInterpPer markers: all their cell-key and
 // marker-id loads, and the halo loads, are issued together, then the position
 // loads, so that an item costs a few memory round trips.
-template <typename T>
+template <typename T, bool DISP>
 __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__restrict__ tile_start,
                                                            const int32_t *__restrict__ tile_item0,
                                                            const int32_t *__restrict__ item_tile, int chunk,
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
         xo[m][0] = Xpos[q[m]];
         xo[m][1] = Xpos[M + q[m]];
         xo[m][2] = Xpos[2 * M + q[m]];
-        if (Y) {
+        if (DISP) {
           yo[m][0] = Y[q[m]];
           yo[m][1] = Y[M + q[m]];
           yo[m][2] = Y[2 * M + q[m]];
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
         const int j = jr + tid + kInterpThreads * m;
         if (j < j1) {
           double a0, a1, a2;
-          if (Y) {
+          if (DISP) {
             const double pos[3] = {yo[m][0] + xo[m][0], yo[m][1] + xo[m][1], yo[m][2] + xo[m][2]};
             interp_one<T>(uh, key[m], pos, h, a0, a1, a2);
           } else {
@@ -329,10 +329,12 @@ hipError_t launch_interp(ib_ctx *c, const T *u, const double *X_pos, double *X_i
   // behind them (measured: 68 us at 256^3 + 1.5M markers against 82 with one
   // resident round)
   const int grid = (int)std::min<int64_t>(c->item_cap, (int64_t)c->ncu * 16);
-  hipLaunchKernelGGL(k_interp<T>, dim3(grid), dim3(kInterpThreads), 0, c->stream, c->ws.tile_start,
-                     c->ws.tile_item0, c->ws.item_tile, c->chunk, c->ws.nitems, c->ws.vals[c->sorted_buf],
-                     c->ws.keys[c->sorted_buf], u, c->n, c->nz, c->log2nt, c->M, c->h, dt, X_pos,
-                     c->mat.disp ? c->mat.X_ref : nullptr, X_inout, U_out);
+  // the displacement form (positions Y + X) as its own kernel, so that the
+  // position form holds no registers for Y
+  hipLaunchKernelGGL((c->mat.disp ? k_interp<T, true> : k_interp<T, false>), dim3(grid), dim3(kInterpThreads), 0,
+                     c->stream, c->ws.tile_start, c->ws.tile_item0, c->ws.item_tile, c->chunk, c->ws.nitems,
+                     c->ws.vals[c->sorted_buf], c->ws.keys[c->sorted_buf], u, c->n, c->nz, c->log2nt, c->M, c->h, dt,
+                     X_pos, c->mat.disp ? c->mat.X_ref : nullptr, X_inout, U_out);
   return hipGetLastError();
 }
 
