@@ -248,12 +248,14 @@ def extras(wl, n=10):
     return out
 
 
-def step_rate(wl, prec, steps, warmup, graph):
+def step_rate(wl, prec, steps, warmup, graph, reuse=True):
     """Steps/s of `steps` steps after `warmup` (events around the steps), eager
-    launches or the step replayed as a HIP graph."""
+    launches or the step replayed as a HIP graph; reuse=False rebuilds the
+    marker partition at every step."""
     import torch
     from paper_math_0301321_amd import ib
     ctx = ib.Context(wl, prec)
+    ctx.bin_reuse(reuse)
     if graph:
         ctx.graph_enable(True)
     X = torch.as_tensor(wl.X0, dtype=torch.float64, device="cuda").contiguous()
@@ -317,6 +319,8 @@ def rollout_times(n=256):
 
 
 def cpu_baseline(wl, sample_steps: int):
+    """The oracle timed on `sample_steps` steps of the workload from rest; also
+    returns its final state (X, u) for the error of the GPU paths."""
     import numpy as np
     import oracle
     model = oracle.Model(wl)
@@ -326,10 +330,71 @@ def cpu_baseline(wl, sample_steps: int):
     for n in range(sample_steps):
         X, u = oracle.step(model, wl, X, u, n * wl.dt)
     dt = time.perf_counter() - t0
-    return {"value": sample_steps / dt, "unit": "steps/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{sample_steps} full FP64 oracle step(s) of {wl.name} ({wl.N}x{wl.N}x{wl.nz} grid, "
-                      f"{wl.M} markers), "
-                      f"{dt:.1f} s wall"}
+    rec = {"value": sample_steps / dt, "unit": "steps/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"{sample_steps} full FP64 oracle step(s) of {wl.name} ({wl.N}x{wl.N}x{wl.nz} grid, "
+                     f"{wl.M} markers), "
+                     f"{dt:.1f} s wall"}
+    return rec, X, u
+
+
+def oracle_errors(wl, steps, Xo, uo):
+    """Max-norm relative error against the oracle of u and of the marker
+    displacement X - X0 after `steps` GPU steps from rest, per precision."""
+    import numpy as np
+    import torch
+    out = {"steps": steps}
+    dXo = Xo - wl.X0
+    for prec in ("fp32", "fp64"):
+        r = run_gpu(wl, prec, steps, 0)
+        ug = r["u"].double().cpu().numpy()
+        dXg = r["X"].cpu().numpy() - wl.X0
+        out["mixed" if prec == "fp32" else "fp64"] = {
+            "u": float(np.abs(ug - uo).max() / np.abs(uo).max()),
+            "dX": float(np.abs(dXg - dXo).max() / np.abs(dXo).max())}
+        del r
+        torch.cuda.synchronize()
+    return out
+
+
+def oracle_single_thread_rates():
+    """The oracle on one host thread: steps/s of the 32^3 shell (2,562 markers)
+    and the 128^3 helix (500k markers) from rest."""
+    import numpy as np
+    import oracle
+    from paper_math_0301321_amd import workloads as W
+    nt0 = oracle.num_threads()
+    oracle.set_num_threads(1)
+    out = {}
+    try:
+        for name, wl, steps in (("shell32", W.config1(), 20), ("helix128", W.config2(), 2)):
+            model = oracle.Model(wl)
+            X, u = wl.X0.copy(), np.zeros(wl.grid_shape)
+            t0 = time.perf_counter()
+            for n in range(steps):
+                X, u = oracle.step(model, wl, X, u, n * wl.dt)
+            out[name] = round(steps / (time.perf_counter() - t0), 3)
+    finally:
+        oracle.set_num_threads(nt0)
+    return out
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """GB/s of a plain device-to-device copy (bytes read + written), the
+    achievable HBM rate beside the vendor peak."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    return gbs
 
 
 def main():
@@ -391,8 +456,10 @@ def main():
     avg_ms = tot / calls
     nbytes = phase_bytes(dom, wl.N, wl.M, 4, wls, wl.nz)
     ach = nbytes / (avg_ms * 1e-3) / 1e9
+    copy_gbs = copy_bandwidth()
     roof = {"bound": "hbm", "kernel": SINGLE_KERNEL[dom], "phase": dom, "achieved": round(ach, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(ach / copy_gbs, 4),
             "traffic": traffic_for(SINGLE_KERNEL[dom], wl.name),
             "bytes_per_launch": nbytes, "avg_ms": round(avg_ms, 5), "launches": calls}
     brk_steps = max(5, args.steps // 5)
@@ -417,6 +484,9 @@ def main():
     if not args.no_extras and args.workload == "helix":
         extra.update(extras(wl))
         extra[f"{wl.name}_mixed_graph_steps_per_s"] = round(step_rate(wl, "fp32", args.steps, args.warmup, True), 2)
+        # the same steps with the partition rebuilt at every step (no reuse)
+        extra[f"{wl.name}_mixed_rebuild_partition_steps_per_s"] = round(
+            step_rate(wl, "fp32", args.steps, args.warmup, False, reuse=False), 2)
         print(f"[bench] graph: {extra[f'{wl.name}_mixed_graph_steps_per_s']} steps/s", file=sys.stderr, flush=True)
         extra.update(config_rates())
         print(f"[bench] config rates done", file=sys.stderr, flush=True)
@@ -426,7 +496,14 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(wl, args.cpu_sample_steps)
+        cpu, Xo, uo = cpu_baseline(wl, args.cpu_sample_steps)
+        extra["oracle_error"] = oracle_errors(wl, args.cpu_sample_steps, Xo, uo)
+        print(f"[bench] error against the oracle: {extra['oracle_error']}", file=sys.stderr, flush=True)
+        del Xo, uo
+        if not args.no_extras:
+            extra["oracle_1thread_steps_per_s"] = oracle_single_thread_rates()
+            print(f"[bench] oracle on one thread: {extra['oracle_1thread_steps_per_s']}", file=sys.stderr,
+                  flush=True)
 
     if args.workload == "helix":
         metric = "IB steps/s at 256^3 grid + 1.5M markers; mixed vs FP64 at stated error"

@@ -150,6 +150,18 @@ int ib_graph_enable(ib_ctx *c, int on);
 /* Graphs captured and launched on this context so far. */
 int ib_graph_stats(const ib_ctx *c, int64_t *captures, int64_t *launches);
 
+/* Update of the marker partition (Sec. 3.3 partitions the material points
+ * among the processors; here binning orders them by 8^3-cell tile and cell).
+ * With on = 1 (the default) every binning compares each marker's cell with
+ * the one it had at the last binning: with no change the sorted order, tile
+ * ranges and work list stay; with up to 4096 markers in new cells those are
+ * moved into place in the last sorted order (the work list is rebuilt only
+ * if one changed tile); with more, or on the first binning, the markers are
+ * sorted in full.  The choice is made on the device, so no call waits for
+ * the host.  on = 0 sorts in full at every binning.  The results are bitwise
+ * the same either way.  on other than 0 or 1: IB_EINVAL. */
+int ib_bin_reuse(ib_ctx *c, int on);
+
 /* Sub-step 1: F_lag = f(X, t) dq, [3][M] double (overwritten). */
 int ib_force(ib_ctx *c, const double *X, double t, double *F_lag);
 

@@ -114,6 +114,11 @@ def num_threads() -> int:
     return lib().ibo_num_threads()
 
 
+def set_num_threads(nt: int) -> None:
+    """Threads of the oracle's parallel loops from here on (results do not depend on it)."""
+    lib().ibo_set_num_threads(C.c_int(int(nt)))
+
+
 def phi(r):
     r = np.asarray(r, dtype=np.float64)
     f = lib().ibo_phi

@@ -33,6 +33,14 @@ int ibo_num_threads(void) {
 #endif
 }
 
+void ibo_set_num_threads(int nt) {
+#ifdef _OPENMP
+  if (nt > 0) omp_set_num_threads(nt);
+#else
+  (void)nt;
+#endif
+}
+
 static inline int64_t wrap(int64_t i, int64_t n) {
   int64_t r = i % n;
   return r < 0 ? r + n : r;

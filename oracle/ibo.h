@@ -108,6 +108,8 @@ void ibo_adjoint_step_u(const ibo_model *m, int N, int Nz, double L, double rho,
                         double *Xbar, double *ubar, double *kbar);
 
 int ibo_num_threads(void);
+/* Threads of the parallel loops from here on (nt > 0); results do not depend on it. */
+void ibo_set_num_threads(int nt);
 
 #ifdef __cplusplus
 }

@@ -99,7 +99,7 @@ bool is_fin(double v) { return isfinite(v) != 0; }
 
 void free_ws(ib_ctx *c) {
   Workspace &w = c->ws;
-  void *ptrs[] = {w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.hist, w.tile_start, w.recs, w.Flag, w.fb,
+  void *ptrs[] = {w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.keys_id, w.bin_state, w.bin_mov, w.hist, w.tile_start, w.recs, w.Flag, w.fb,
                   w.Fgrid, w.tile_nit, w.tile_item0, w.tile_touch, w.item_tile, w.chunk_item0, w.nitems, w.split_list, w.touch_list, w.scan_tmp, w.partials,
                   w.r, w.spec, w.nonfinite, w.tw, w.lam, w.sgrad, w.twz, w.lamz, w.sgradz, w.drive_idx, w.drive_dir,
                   w.sp_rowptr, w.sp_col,
@@ -260,6 +260,7 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
   while (((int64_t)1 << (key_bits - 9)) < c->ntiles) key_bits++;
   c->sort_passes = (key_bits + 7) / 8;
   c->digit_bits = (key_bits + c->sort_passes - 1) / c->sort_passes;
+  c->sorted_buf = (c->sort_passes - 1) & 1;   // the last radix pass writes keys/vals[(passes - 1) & 1]
 
   Material &mt = c->mat;
   mt.w = e->w;
@@ -286,6 +287,9 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
   chk_alloc(dalloc(c, &w.keys[1], M));
   chk_alloc(dalloc(c, &w.vals[0], M));
   chk_alloc(dalloc(c, &w.vals[1], M));
+  chk_alloc(dalloc(c, &w.keys_id, M));
+  chk_alloc(dalloc(c, &w.bin_state, BS_WORDS));
+  chk_alloc(dalloc(c, &w.bin_mov, 5 * kMoverCap));
   chk_alloc(dalloc(c, &w.hist, sort_hist_words(M, c->digit_bits)));
   chk_alloc(dalloc(c, &w.tile_start, c->ntiles + 1));
   chk_alloc(dalloc(c, &w.inv, M));
@@ -342,6 +346,12 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
     free_ws(c);
     delete c;
     return err == hipErrorOutOfMemory ? IB_ENOMEM : IB_EDEVICE;
+  }
+  {
+    // no partition yet: the first binning sorts in full
+    uint32_t st0[BS_WORDS] = {};
+    st0[BS_FULL] = 1u;
+    chk_alloc(hipMemcpy(w.bin_state, st0, sizeof(st0), hipMemcpyHostToDevice));
   }
   if (D > 0) {
     chk_alloc(hipMemcpy(w.drive_idx, e->drive_idx, sizeof(int32_t) * D, hipMemcpyHostToDevice));
@@ -619,6 +629,14 @@ extern "C" int ib_step(ib_ctx *c, double *X, void *u, double t, double *F_lag_ou
   c->err.clear();
   return c->fp32 ? step_impl<float>(c, X, (float *)u, t, F_lag_out)
                  : step_impl<double>(c, X, (double *)u, t, F_lag_out);
+}
+
+extern "C" int ib_bin_reuse(ib_ctx *c, int on) {
+  if (!c) return IB_EINVAL;
+  if (on != 0 && on != 1) return fail(c, IB_EINVAL, "ib_bin_reuse: on must be 0 or 1");
+  if (c->bin_reuse != (on != 0)) graph_release(c);   // a captured step holds the choice
+  c->bin_reuse = on != 0;
+  return IB_OK;
 }
 
 extern "C" int ib_graph_enable(ib_ctx *c, int on) {

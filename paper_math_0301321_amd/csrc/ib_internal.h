@@ -98,10 +98,18 @@ struct Material {
   int32_t disp;
 };
 
+// Device-side state of the binning: full sort this call, movers listed,
+// some mover changed tile, range [lo, hi] of sorted positions that change.
+enum BinState { BS_FULL = 0, BS_NMOV = 1, BS_TILES = 2, BS_LO = 3, BS_HI = 4, BS_WORDS = 8 };
+constexpr int kMoverCap = 4096;   // most movers the incremental update takes (one block sorts them)
+
 struct Workspace {
   // binning
   uint32_t *keys[2];
   int32_t *vals[2];
+  uint32_t *keys_id;           // [M] cell key of each marker at the last binning
+  uint32_t *bin_state;         // [BS_WORDS] the binning's device-side state (BinState)
+  int32_t *bin_mov;            // [5 kMoverCap] the movers' list (ids; sorted keys, ids, new and old positions)
   uint32_t *hist;
   int nblk_sort;
   int32_t *tile_start;         // [ntiles + 1] first sorted position of each tile
@@ -173,6 +181,7 @@ struct ib_ctx {
   int64_t ws_bytes = 0;
   int sort_passes = 0, digit_bits = 0;
   int sorted_buf = 0;   // which keys/vals buffer holds the sorted result
+  bool bin_reuse = true;   // keep the last partition when no marker changed cell
   int log2nt = 0;       // log2(n / 8)
   int ntz = 0;          // nz / 8 (tiles along z)
   int64_t ntiles = 0;

@@ -56,7 +56,7 @@ class ib_elastic(C.Structure):
 EXPORTS = ["ib_create", "ib_destroy", "ib_set_material", "ib_set_stream", "ib_step", "ib_force",
            "ib_spread", "ib_interp", "ib_fluid", "ib_bin", "ib_adjoint_step", "ib_adjoint_step_u", "ib_probe", "ib_last_error",
            "ib_workspace_bytes", "ib_timers_enable", "ib_timers_select", "ib_timers_read", "ib_timer_name",
-           "ib_graph_enable", "ib_graph_stats", "ib_fluid_noalloc"]
+           "ib_graph_enable", "ib_graph_stats", "ib_fluid_noalloc", "ib_bin_reuse"]
 IB_N_TIMERS = 32
 
 _lib = None
@@ -95,6 +95,7 @@ def load_library():
     lib.ib_timers_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
     lib.ib_fluid_noalloc.argtypes = [C.POINTER(ib_params), vp, vp]
     lib.ib_graph_enable.argtypes = [vp, C.c_int]
+    lib.ib_bin_reuse.argtypes = [vp, C.c_int]
     lib.ib_graph_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.ib_timer_name.argtypes = [C.c_int]
     lib.ib_timer_name.restype = C.c_char_p
@@ -266,6 +267,11 @@ class Context:
     def graph_enable(self, on: bool = True):
         """Replay the step as a HIP graph (captured per (X, u, F_out) pointers)."""
         self._check(self.lib.ib_graph_enable(self._h, 1 if on else 0))
+
+    def bin_reuse(self, on: bool = True):
+        """Keep the last marker partition when no marker changed cell (default on);
+        off rebuilds it at every binning.  Results are bitwise the same."""
+        self._check(self.lib.ib_bin_reuse(self._h, 1 if on else 0))
 
     def graph_stats(self) -> tuple:
         """(graphs captured, graph launches) on this context."""

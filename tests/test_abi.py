@@ -119,6 +119,7 @@ def test_null_context_calls_fail_cleanly():
     lib = _lib()
     assert lib.ib_step(None, None, None, 0.0, None) == ib.IB_EINVAL
     assert lib.ib_adjoint_step(None, None, None, 0.0, None, None, None) == ib.IB_EINVAL
+    assert lib.ib_bin_reuse(None, 1) == ib.IB_EINVAL
     assert lib.ib_workspace_bytes(None) == 0
 
 

@@ -394,3 +394,22 @@ def test_force_vanishes_at_reference_shape(oracle_mod):
         assert np.abs(oracle_mod.force(model, wl.X_ref, 1.3e-4)).max() > 0      # the drive
         X = wl.X_ref + 1e-6 * np.random.default_rng(0).standard_normal(wl.X_ref.shape)
         assert np.abs(oracle_mod.force(model, X, 0.0)).max() > 0                # the elastic terms
+
+
+# --------------------------------------------------------------------------
+# thread count (the partition of Sec. 3.3 among processors must not change
+# the result)
+# --------------------------------------------------------------------------
+def test_steps_do_not_depend_on_the_thread_count(oracle_mod):
+    wl = W.tiny_helix()
+    u0 = 0.5 * W.smooth_field(wl.N, seed=3, Nz=wl.nz)
+    nt0 = oracle_mod.num_threads()
+    runs = []
+    try:
+        for nt in (1, 3, max(nt0, 2)):
+            oracle_mod.set_num_threads(nt)
+            runs.append(oracle_mod.run(wl, 3, u=u0, t0_step=2))
+    finally:
+        oracle_mod.set_num_threads(nt0)
+    for X, u in runs[1:]:
+        assert np.array_equal(X, runs[0][0]) and np.array_equal(u, runs[0][1])
