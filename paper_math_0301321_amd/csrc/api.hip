@@ -289,7 +289,7 @@ extern "C" int ib_create(const ib_params *p, const ib_elastic *e, ib_ctx **out) 
   chk_alloc(dalloc(c, &w.vals[1], M));
   chk_alloc(dalloc(c, &w.keys_id, M));
   chk_alloc(dalloc(c, &w.bin_state, BS_WORDS));
-  chk_alloc(dalloc(c, &w.bin_mov, 5 * kMoverCap));
+  chk_alloc(dalloc(c, &w.bin_mov, MV_ARRAYS * kMoverCap));
   chk_alloc(dalloc(c, &w.hist, sort_hist_words(M, c->digit_bits)));
   chk_alloc(dalloc(c, &w.tile_start, c->ntiles + 1));
   chk_alloc(dalloc(c, &w.inv, M));

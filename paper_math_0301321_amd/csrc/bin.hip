@@ -56,19 +56,22 @@ __device__ __forceinline__ bool update_off(const uint32_t *st) {
 }
 
 // Cell keys by marker id, compared with the stored ones: movers are listed
-// (block-wide counts, one global atomic per block; their order in the list is
-// irrelevant, the list is sorted later), a mover that changed tile sets
-// BS_TILES, more than kMoverCap movers or rebuild set BS_FULL.  With BS_FULL
-// already set (the first binning) nothing is listed.
+// with their new key and old sorted position (block-wide counts, one global
+// atomic per block; their order in the list is irrelevant, the list is
+// sorted later), a mover that changed tile sets BS_TILES, more than
+// kMoverCap movers or rebuild set BS_FULL.  With BS_FULL already set (the
+// first binning) nothing is listed.
 __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ X, const double *__restrict__ Y, int64_t M,
                                               double h, int n, int nz, int log2nt, uint32_t *__restrict__ keys_id,
-                                              int rebuild, uint32_t *__restrict__ st, int32_t *__restrict__ mov_q) {
+                                              const int32_t *__restrict__ inv, int rebuild,
+                                              uint32_t *__restrict__ st, int32_t *__restrict__ mov) {
   __shared__ uint32_t nloc, base;
   if (threadIdx.x == 0) nloc = 0;
   __syncthreads();
   const bool listing = !rebuild && full_off(st);
   const int64_t b0 = (int64_t)blockIdx.x * kSortChunk;
   int slot[kSortItems];
+  uint32_t knew[kSortItems];
   bool tile_moved = false;
 #pragma unroll
   for (int it = 0; it < kSortItems; it++) {
@@ -84,6 +87,7 @@ __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ X, cons
       }
       const uint32_t k = cell_key(c[0], c[1], c[2], log2nt), ko = keys_id[q];
       keys_id[q] = k;
+      knew[it] = k;
       if (k != ko) {
         tile_moved |= (k >> 9) != (ko >> 9);
         if (listing) slot[it] = (int)atomicAdd(&nloc, 1u);
@@ -101,8 +105,14 @@ __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ X, cons
   for (int it = 0; it < kSortItems; it++) {
     if (slot[it] >= 0) {
       const uint32_t j = base + (uint32_t)slot[it];
-      if (j < (uint32_t)kMoverCap) mov_q[j] = (int32_t)(b0 + (int64_t)it * kSortThreads + threadIdx.x);
-      else st[BS_FULL] = 1u;
+      const int64_t q = b0 + (int64_t)it * kSortThreads + threadIdx.x;
+      if (j < (uint32_t)kMoverCap) {
+        mov[MV_Q * kMoverCap + j] = (int32_t)q;
+        mov[MV_KEY * kMoverCap + j] = (int32_t)knew[it];
+        mov[MV_POS * kMoverCap + j] = inv[q];
+      } else {
+        st[BS_FULL] = 1u;
+      }
     }
   }
 }
@@ -267,13 +277,31 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
   }
 }
 
-// tile_start[t] = first sorted position whose key is >= t * 512, t in [0, ntiles].
+// tile_start[t] = first sorted position whose key is >= t * 512, t in [0, ntiles]:
+// after a full sort by search in the sorted keys; after an update, from the
+// last value, plus the movers now in tiles below t, less those that were.
 __global__ __launch_bounds__(256) void k_tile_start(const uint32_t *__restrict__ keys, int64_t M, int64_t ntiles,
                                                     int32_t *__restrict__ tile_start,
-                                                    const uint32_t *__restrict__ bin_state) {
+                                                    const uint32_t *__restrict__ bin_state,
+                                                    const int32_t *__restrict__ mov) {
   if (worklist_off(bin_state)) return;
   const int64_t t = gtid();
   if (t > ntiles) return;
+  if (bs_word(bin_state, BS_FULL) == 0u) {
+    const uint32_t m = bs_word(bin_state, BS_NMOV), tile = (uint32_t)t;
+    auto below = [&](const int32_t *k) {   // entries of the ascending keys k[0 .. m) in tiles below t
+      uint32_t a = 0, b = m;
+      while (a < b) {
+        const uint32_t mid = (a + b) >> 1;
+        if (((uint32_t)k[mid] >> 9) < tile) a = mid + 1;
+        else b = mid;
+      }
+      return a;
+    };
+    const uint32_t in_now = below(mov + MS_KEY * kMoverCap), in_was = below(mov + MS_OLDKEY * kMoverCap);
+    if (in_now != in_was) tile_start[t] += (int32_t)in_now - (int32_t)in_was;
+    return;
+  }
   const uint64_t target = (uint64_t)t << 9;
   int64_t lo = 0, hi = M;
   while (lo < hi) {
@@ -430,9 +458,6 @@ __global__ __launch_bounds__(1024) void k_item_scan_write(const int32_t *__restr
 }
 
 // ------------------------------------------------- incremental update ----
-// Mover list layout (kMoverCap entries each): q (listed by k_keys), then the
-// movers sorted by (new key, id): key, id, new position; then their old
-// positions, ascending.
 __device__ __forceinline__ bool pair_less(uint32_t ka, uint32_t va, uint32_t kb, uint32_t vb) {
   return ka < kb || (ka == kb && va < vb);
 }
@@ -442,9 +467,7 @@ __device__ __forceinline__ bool pair_less(uint32_t ka, uint32_t va, uint32_t kb,
 // plus the stayers before it: the old entries before it, found within its
 // tile's old range, less the movers among them), and record the range
 // [lo, hi] of sorted positions that change.
-__global__ __launch_bounds__(1024) void k_bin_fix(const uint32_t *__restrict__ keys_id,
-                                                  const uint32_t *__restrict__ K, const int32_t *__restrict__ V,
-                                                  const int32_t *__restrict__ inv,
+__global__ __launch_bounds__(1024) void k_bin_fix(const uint32_t *__restrict__ K, const int32_t *__restrict__ V,
                                                   const int32_t *__restrict__ tile_start, uint32_t *__restrict__ st,
                                                   int32_t *__restrict__ mov) {
   if (update_off(st)) return;
@@ -456,9 +479,8 @@ __global__ __launch_bounds__(1024) void k_bin_fix(const uint32_t *__restrict__ k
   while (np2 < m) np2 <<= 1;
   for (int j = tid; j < np2; j += 1024) {
     if (j < m) {
-      const int32_t q = mov[j];
-      L[j] = ((uint64_t)keys_id[q] << 32) | (uint32_t)q;
-      Po[j] = (uint32_t)inv[q];
+      L[j] = ((uint64_t)(uint32_t)mov[MV_KEY * kMoverCap + j] << 32) | (uint32_t)mov[MV_Q * kMoverCap + j];
+      Po[j] = (uint32_t)mov[MV_POS * kMoverCap + j];
     } else {
       L[j] = ~0ull;
       Po[j] = ~0u;
@@ -490,8 +512,8 @@ __global__ __launch_bounds__(1024) void k_bin_fix(const uint32_t *__restrict__ k
       }
       __syncthreads();
     }
-  int32_t *mkey = mov + kMoverCap, *mval = mov + 2 * kMoverCap, *mnew = mov + 3 * kMoverCap,
-          *mold = mov + 4 * kMoverCap;
+  int32_t *mkey = mov + MS_KEY * kMoverCap, *mval = mov + MS_VAL * kMoverCap, *mnew = mov + MS_NEW * kMoverCap,
+          *mold = mov + MS_OLD * kMoverCap, *moldk = mov + MS_OLDKEY * kMoverCap;
   uint32_t lo = ~0u, hi = 0u;
   for (int j = tid; j < m; j += 1024) {
     const uint32_t kq = (uint32_t)(L[j] >> 32), q = (uint32_t)L[j];
@@ -515,6 +537,7 @@ __global__ __launch_bounds__(1024) void k_bin_fix(const uint32_t *__restrict__ k
     mval[j] = (int32_t)q;
     mnew[j] = (int32_t)pn;
     mold[j] = (int32_t)Po[j];
+    moldk[j] = (int32_t)K[Po[j]];
     lo = min(lo, min(pn, Po[j]));
     hi = max(hi, max(pn, Po[j]));
   }
@@ -539,8 +562,8 @@ __global__ __launch_bounds__(256) void k_bin_merge(const uint32_t *__restrict__ 
   if (update_off(st)) return;
   const uint32_t m = bs_word(st, BS_NMOV), lo = bs_word(st, BS_LO), hi = bs_word(st, BS_HI);
   const uint32_t g = blockIdx.x * 256u + threadIdx.x, stride = gridDim.x * 256u;
-  const int32_t *mkey = mov + kMoverCap, *mval = mov + 2 * kMoverCap, *mnew = mov + 3 * kMoverCap,
-                *mold = mov + 4 * kMoverCap;
+  const int32_t *mkey = mov + MS_KEY * kMoverCap, *mval = mov + MS_VAL * kMoverCap,
+                *mnew = mov + MS_NEW * kMoverCap, *mold = mov + MS_OLD * kMoverCap;
   for (uint32_t j = g; j < m; j += stride) {   // the movers
     const uint32_t pn = (uint32_t)mnew[j];
     K2[pn] = (uint32_t)mkey[j];
@@ -606,7 +629,7 @@ hipError_t launch_bin(ib_ctx *c, const double *X) {
     const int nblk = (int)((M + kSortChunk - 1) / kSortChunk);
     hipLaunchKernelGGL(k_keys, dim3(nblk), dim3(kSortThreads), 0, c->stream, X,
                        c->mat.disp ? c->mat.X_ref : nullptr, M, c->h, c->n, c->nz, c->log2nt, ws.keys_id,
-                       c->bin_reuse ? 0 : 1, st, ws.bin_mov);
+                       (const int32_t *)ws.inv, c->bin_reuse ? 0 : 1, st, ws.bin_mov);
     // full sort (BS_FULL): pass p reads the keys by marker id (p = 0) or pass
     // p - 1's output, and writes keys/vals[p & 1]; the last pass lands in sb
     for (int pass = 0; pass < c->sort_passes; pass++) {
@@ -623,9 +646,8 @@ hipError_t launch_bin(ib_ctx *c, const double *X) {
     }
     // incremental update (movers, no BS_FULL), through the other buffer
     const unsigned pgrid = (unsigned)std::min<int64_t>((M + 255) / 256, 2048);   // grid-stride over [lo, hi]
-    hipLaunchKernelGGL(k_bin_fix, dim3(1), dim3(1024), 0, c->stream, (const uint32_t *)ws.keys_id,
-                       (const uint32_t *)ws.keys[sb], (const int32_t *)ws.vals[sb], (const int32_t *)ws.inv,
-                       (const int32_t *)ws.tile_start, st, ws.bin_mov);
+    hipLaunchKernelGGL(k_bin_fix, dim3(1), dim3(1024), 0, c->stream, (const uint32_t *)ws.keys[sb],
+                       (const int32_t *)ws.vals[sb], (const int32_t *)ws.tile_start, st, ws.bin_mov);
     hipLaunchKernelGGL(k_bin_merge, dim3(pgrid), dim3(256), 0, c->stream, (const uint32_t *)ws.keys[sb],
                        (const int32_t *)ws.vals[sb], ws.keys[sb ^ 1], ws.vals[sb ^ 1], ws.inv, cst,
                        (const int32_t *)ws.bin_mov);
@@ -635,7 +657,7 @@ hipError_t launch_bin(ib_ctx *c, const double *X) {
   // tile ranges and work list (BS_FULL, or a mover changed tile)
   const int64_t nt = c->ntiles;
   hipLaunchKernelGGL(k_tile_start, dim3((unsigned)((nt + 1 + 255) / 256)), dim3(256), 0, c->stream,
-                     ws.keys[sb], M, nt, ws.tile_start, cst);
+                     ws.keys[sb], M, nt, ws.tile_start, cst, (const int32_t *)ws.bin_mov);
   const int nsb = (int)((nt + 1023) / 1024);
   int3 *tmp = (int3 *)ws.scan_tmp;
   hipLaunchKernelGGL(k_item_scan_blocks, dim3(nsb), dim3(1024), 0, c->stream, ws.tile_start, nt, c->log2nt,

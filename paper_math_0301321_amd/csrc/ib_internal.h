@@ -102,6 +102,10 @@ struct Material {
 // some mover changed tile, range [lo, hi] of sorted positions that change.
 enum BinState { BS_FULL = 0, BS_NMOV = 1, BS_TILES = 2, BS_LO = 3, BS_HI = 4, BS_WORDS = 8 };
 constexpr int kMoverCap = 4096;   // most movers the incremental update takes (one block sorts them)
+// The movers' list, kMoverCap entries per array: as listed (id, new key, old
+// sorted position), then sorted by (new key, id) (key, id, new position) and
+// the old positions and old keys, ascending.
+enum MoverList { MV_Q = 0, MV_KEY, MV_POS, MS_KEY, MS_VAL, MS_NEW, MS_OLD, MS_OLDKEY, MV_ARRAYS };
 
 struct Workspace {
   // binning
@@ -109,7 +113,7 @@ struct Workspace {
   int32_t *vals[2];
   uint32_t *keys_id;           // [M] cell key of each marker at the last binning
   uint32_t *bin_state;         // [BS_WORDS] the binning's device-side state (BinState)
-  int32_t *bin_mov;            // [5 kMoverCap] the movers' list (ids; sorted keys, ids, new and old positions)
+  int32_t *bin_mov;            // [MV_ARRAYS][kMoverCap] the movers' list (MoverList)
   uint32_t *hist;
   int nblk_sort;
   int32_t *tile_start;         // [ntiles + 1] first sorted position of each tile
