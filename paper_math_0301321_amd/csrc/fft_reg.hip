@@ -99,6 +99,10 @@ struct V16<double> {
 template <typename T>
 using Vec16 = typename V16<T>::type;
 
+// 1 / x: the hardware reciprocal in FP32 (within 1 ulp), a division in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 template <typename T>
 __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
   return cplx<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
@@ -578,14 +582,14 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ?
     for (int k2 = 0; k2 < R2; k2++) {
       const int e = i * R2 + k2;
       const int kz = (t + P * i) + R1 * k2;
-      const T rden = T(1) / (T(1) + nu_dt * (lxy + lamz[kz]));
+      const T rden = recip(T(1) + nu_dt * (lxy + lamz[kz]));
       const T s2 = sgz[kz];
       cplx<T> w0{v[0][e].x * rden, v[0][e].y * rden};
       cplx<T> w1{v[1][e].x * rden, v[1][e].y * rden};
       cplx<T> w2{v[2][e].x * rden, v[2][e].y * rden};
       const T ss = s0 * s0 + s1 * s1 + s2 * s2;
       if (ss > T(0)) {
-        const T rss = T(1) / ss;
+        const T rss = recip(ss);
         const T dr = (s0 * w0.x + s1 * w1.x + s2 * w2.x) * rss;
         const T di = (s0 * w0.y + s1 * w1.y + s2 * w2.y) * rss;
         w0.x -= s0 * dr; w0.y -= s0 * di;
