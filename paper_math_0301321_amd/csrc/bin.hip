@@ -41,9 +41,11 @@ constexpr int kSortChunk = kSortThreads * kSortItems;
 // layout hist[digit * nblk + block].
 constexpr int kWaveKeys = 64 * kSortItems;
 
-__device__ __forceinline__ uint32_t bs_word(const uint32_t *st, int i) {
-  return __atomic_load_n(st + i, __ATOMIC_RELAXED);
-}
+// A plain load: the words are written by earlier kernels on the stream (or,
+// for BS_FULL, BS_NMOV and BS_TILES, only raised within k_keys, which reads
+// BS_FULL once at the start), so a uniform scalar load suffices and lets a
+// kernel of the path not taken exit early.
+__device__ __forceinline__ uint32_t bs_word(const uint32_t *st, int i) { return st[i]; }
 // the full sort is off this call
 __device__ __forceinline__ bool full_off(const uint32_t *st) { return bs_word(st, BS_FULL) == 0u; }
 // the tile ranges and work list stand
