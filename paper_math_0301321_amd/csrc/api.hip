@@ -731,13 +731,17 @@ static int adjoint_impl(ib_ctx *c, const double *X_n, const T *u_n, const T *u_n
   IB_TRY(launch_adj_interp<T>(c, u_np1, X_n, Xbar));
   // transpose of interpolation: ubar_tot = ubar + S(Ubar) h^3
   IB_TRY(launch_spread<T>(c, (T *)c->ws.Fgrid, false, 1.0));
-  // the NS operator is symmetric: ubar^n = Lop ubar_tot
-  IB_TRY(launch_fluid<T>(c, ubar, (const T *)c->ws.Fgrid, 1, 0, 1.0, ubar));
+  // the NS operator is symmetric: rbar = Lop ubar_tot.  With advection rbar
+  // goes to the force grid (its first pass has read the force by the time its
+  // last pass writes), and the advection's transpose forms ubar from it below;
+  // without, rbar is ubar^n
+  T *rbar = c->p.convect ? (T *)c->ws.Fgrid : ubar;
+  IB_TRY(launch_fluid<T>(c, ubar, (const T *)c->ws.Fgrid, 1, 0, 1.0, rbar));
   // transpose of spreading (fbar) and its phi' term, then the force Jacobian
-  IB_TRY(launch_adj_spread<T>(c, ubar, c->ws.Flag, X_n, Xbar, c->ws.fb));
+  IB_TRY(launch_adj_spread<T>(c, rbar, c->ws.Flag, X_n, Xbar, c->ws.fb));
   IB_TRY(launch_hessvec(c, X_n, c->ws.fb, Xbar, kbar));
   // with advection, r = u - dt A(u) + ...: ubar^n = rbar - dt (dA/du)^T rbar at u^n
-  if (c->p.convect) IB_TRY(launch_adv_adjoint<T>(c, u_n, ubar, (T *)c->ws.Fgrid));
+  if (c->p.convect) IB_TRY(launch_adv_adjoint<T>(c, u_n, (const T *)rbar, ubar));
   return checked(c, ubar, c->fp32, Xbar);
 }
 

@@ -304,61 +304,109 @@ template hipError_t launch_fluid_solve<double>(ib_ctx *, const double *, double 
 //   out_c(y) = sum_c' r_c'(y) D_c u_c'(y)
 //            + sum_k [b_k(y) - b_k(y + e_k) - f_k(y) + f_k(y - e_k)],
 // b_k(x) = u_k(x) r_c(x) / h where u_k(x) > 0, f_k(x) the same where
-// u_k(x) < 0.  One thread per grid point; the result, times dt, goes to tmp.
+// u_k(x) < 0.  The step's adjoint is then ubar = r - dt out.
+//
+// One thread per run of E = 16 / sizeof(T) consecutive x values of one row:
+// the three components of u and r at the run, its y and z neighbour rows
+// (16-byte loads) and its two x neighbours, all loads issued before use.
+// r is read and ubar written (out of place), so no point's result waits for
+// its neighbours' reads.
+template <typename T>
+struct AdvVec;
+template <>
+struct AdvVec<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct AdvVec<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_adv_adjoint(const T *__restrict__ u, const T *__restrict__ r, int n,
-                                                     int nz, int log2n, T inv_h, T dt, T *__restrict__ tmp) {
+                                                     int nz, int log2n, T inv_h, T dt, T *__restrict__ ubar) {
+  using V = typename AdvVec<T>::type;
+  constexpr int E = 16 / sizeof(T);
   const int64_t G = (int64_t)nz << (2 * log2n);
-  const int64_t p = gtid();
-  if (p >= G) return;
+  const int64_t e = gtid();                                    // run index
+  if (e * E >= G) return;
   const int mask = n - 1;
-  const int x = (int)(p & mask), y = (int)((p >> log2n) & mask), z = (int)(p >> (2 * log2n));
+  const int64_t p0 = e * E;                                     // first point of the run
+  const int x0 = (int)(p0 & mask), y = (int)((p0 >> log2n) & mask), z = (int)(p0 >> (2 * log2n));
   const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;   // periodic z neighbours
-  const int64_t zo = (int64_t)z << (2 * log2n), yo = (int64_t)y << log2n;
-  const int64_t pm[3] = {zo + yo + ((x - 1) & mask), zo + ((int64_t)((y - 1) & mask) << log2n) + x,
-                         ((int64_t)zm << (2 * log2n)) + yo + x};
-  const int64_t pp[3] = {zo + yo + ((x + 1) & mask), zo + ((int64_t)((y + 1) & mask) << log2n) + x,
-                         ((int64_t)zp << (2 * log2n)) + yo + x};
+  const int64_t zo = (int64_t)z << (2 * log2n), row = zo + ((int64_t)y << log2n);
+  const int64_t rym = zo + ((int64_t)((y - 1) & mask) << log2n), ryp = zo + ((int64_t)((y + 1) & mask) << log2n);
+  const int64_t rzm = ((int64_t)zm << (2 * log2n)) + ((int64_t)y << log2n);
+  const int64_t rzp = ((int64_t)zp << (2 * log2n)) + ((int64_t)y << log2n);
+  const int xl = (x0 - 1) & mask, xr = (x0 + E) & mask;
+  // [comp][0: centre, 1: y-1, 2: y+1, 3: z-1, 4: z+1] runs, and the x neighbours
+  V U[3][5], R[3][5];
+  T ul[3], ur[3], rl[3], rr[3];
 #pragma unroll
-  for (int c = 0; c < 3; c++) {
-    T acc = T(0);
-    const T uc = u[c * G + p];
-#pragma unroll
-    for (int cp = 0; cp < 3; cp++) {
-      const T *v = u + cp * G;
-      const T D = uc > T(0) ? (v[p] - v[pm[c]]) * inv_h : (uc < T(0) ? (v[pp[c]] - v[p]) * inv_h : T(0));
-      acc += r[cp * G + p] * D;
-    }
-    const T *rc = r + c * G;
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-      const T at = u[k * G + p], up = u[k * G + pp[k]], dn = u[k * G + pm[k]];
-      if (at > T(0)) acc += at * rc[p] * inv_h;
-      if (up > T(0)) acc -= up * rc[pp[k]] * inv_h;
-      if (at < T(0)) acc -= at * rc[p] * inv_h;
-      if (dn < T(0)) acc += dn * rc[pm[k]] * inv_h;
-    }
-    tmp[c * G + p] = dt * acc;
+  for (int k = 0; k < 3; k++) {
+    const T *uk = u + k * G, *rk = r + k * G;
+    U[k][0] = *(const V *)(uk + row + x0);
+    U[k][1] = *(const V *)(uk + rym + x0);
+    U[k][2] = *(const V *)(uk + ryp + x0);
+    U[k][3] = *(const V *)(uk + rzm + x0);
+    U[k][4] = *(const V *)(uk + rzp + x0);
+    R[k][0] = *(const V *)(rk + row + x0);
+    R[k][1] = *(const V *)(rk + rym + x0);
+    R[k][2] = *(const V *)(rk + ryp + x0);
+    R[k][3] = *(const V *)(rk + rzm + x0);
+    R[k][4] = *(const V *)(rk + rzp + x0);
+    ul[k] = uk[row + xl];
+    ur[k] = uk[row + xr];
+    rl[k] = rk[row + xl];
+    rr[k] = rk[row + xr];
   }
+  V out[3];
+#pragma unroll
+  for (int i = 0; i < E; i++) {
+    // neighbours of point i along direction d: minus (m) and plus (p)
+    auto um = [&](int k, int d) { return d == 0 ? (i == 0 ? ul[k] : U[k][0][i - 1]) : U[k][2 * d - 1][i]; };
+    auto up = [&](int k, int d) { return d == 0 ? (i == E - 1 ? ur[k] : U[k][0][i + 1]) : U[k][2 * d][i]; };
+    auto rm = [&](int k, int d) { return d == 0 ? (i == 0 ? rl[k] : R[k][0][i - 1]) : R[k][2 * d - 1][i]; };
+    auto rp = [&](int k, int d) { return d == 0 ? (i == E - 1 ? rr[k] : R[k][0][i + 1]) : R[k][2 * d][i]; };
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      T acc = T(0);
+      const T uc = U[c][0][i];
+#pragma unroll
+      for (int cp = 0; cp < 3; cp++) {
+        const T v = U[cp][0][i];
+        const T D = uc > T(0) ? (v - um(cp, c)) * inv_h : (uc < T(0) ? (up(cp, c) - v) * inv_h : T(0));
+        acc += R[cp][0][i] * D;
+      }
+      const T rcp = R[c][0][i];
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        const T at = U[k][0][i], uup = up(k, k), udn = um(k, k);
+        if (at > T(0)) acc += at * rcp * inv_h;
+        if (uup > T(0)) acc -= uup * rp(c, k) * inv_h;
+        if (at < T(0)) acc -= at * rcp * inv_h;
+        if (udn < T(0)) acc += udn * rm(c, k) * inv_h;
+      }
+      out[c][i] = rcp - dt * acc;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; c++) *(V *)(ubar + c * G + row + x0) = out[c];
 }
 
+// ubar = rbar - dt (dA/du)^T rbar at u^n; rbar and ubar are distinct arrays.
 template <typename T>
-__global__ __launch_bounds__(256) void k_sub_inplace(T *__restrict__ a, const T *__restrict__ b, int64_t count) {
-  const int64_t i = gtid();
-  if (i < count) a[i] -= b[i];
-}
-
-template <typename T>
-hipError_t launch_adv_adjoint(ib_ctx *c, const T *u_n, T *ubar, T *tmp) {
+hipError_t launch_adv_adjoint(ib_ctx *c, const T *u_n, const T *rbar, T *ubar) {
   PhaseScope ps(c, PH_ADJ_ADVECT);
-  const unsigned g1 = (unsigned)((c->G + 255) / 256), g3 = (unsigned)((3 * c->G + 255) / 256);
-  hipLaunchKernelGGL(k_adv_adjoint<T>, dim3(g1), dim3(256), 0, c->stream, u_n, (const T *)ubar, c->n, c->nz, c->log2n,
-                     (T)(1.0 / c->h), (T)c->p.dt, tmp);
-  hipLaunchKernelGGL(k_sub_inplace<T>, dim3(g3), dim3(256), 0, c->stream, ubar, (const T *)tmp, 3 * c->G);
+  constexpr int E = 16 / sizeof(T);
+  if (c->n % E != 0) return hipErrorInvalidValue;
+  const unsigned g = (unsigned)((c->G / E + 255) / 256);
+  hipLaunchKernelGGL(k_adv_adjoint<T>, dim3(g), dim3(256), 0, c->stream, u_n, rbar, c->n, c->nz, c->log2n,
+                     (T)(1.0 / c->h), (T)c->p.dt, ubar);
   return hipGetLastError();
 }
 
-template hipError_t launch_adv_adjoint<float>(ib_ctx *, const float *, float *, float *);
-template hipError_t launch_adv_adjoint<double>(ib_ctx *, const double *, double *, double *);
+template hipError_t launch_adv_adjoint<float>(ib_ctx *, const float *, const float *, float *);
+template hipError_t launch_adv_adjoint<double>(ib_ctx *, const double *, const double *, double *);
 
 }  // namespace ib

@@ -265,7 +265,7 @@ hipError_t launch_probe(ib_ctx *c, const double *X, const double *X0, const int3
                         int64_t count, double *disp, double *env);
 // adjoint step with advection: ubar -= dt (dA/du)^T ubar at u^n (tmp: [3][G] scratch)
 template <typename T>
-hipError_t launch_adv_adjoint(ib_ctx *c, const T *u_n, T *ubar, T *tmp);
+hipError_t launch_adv_adjoint(ib_ctx *c, const T *u_n, const T *rbar, T *ubar);   // ubar = rbar - dt A'^T rbar
 
 // text returned by ib_last_error(NULL)
 void set_context_free_error(const std::string &msg);
