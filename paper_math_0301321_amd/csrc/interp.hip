@@ -245,18 +245,26 @@ __global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__
   dphi4<double>(f0, gx);
   dphi4<double>(f1, gy);
   dphi4<double>(f2, gz);
+  // the stencil sums are separable: per x row the sums of u.Ubar against the
+  // x weight and its derivative, then the rows against the y and z factors
   double g0 = 0, g1 = 0, g2 = 0;
+#pragma unroll
   for (int c3 = 0; c3 < 4; c3++) {
     const int64_t zo = (int64_t)wrap_cell(cc.z + c3 - 1, nz) << (2 * log2n);
+#pragma unroll
     for (int c2 = 0; c2 < 4; c2++) {
       const int64_t yo = zo + ((int64_t)((cc.y + c2 - 1) & mask) << log2n);
+      double sw = 0, sg = 0;
+#pragma unroll
       for (int c1 = 0; c1 < 4; c1++) {
         const int64_t p = yo + ((cc.x + c1 - 1) & mask);
         const double uU = (double)u[p] * ub0 + (double)u[G + p] * ub1 + (double)u[2 * G + p] * ub2;
-        g0 += uU * (gx[c1] * wy[c2] * wz[c3]);
-        g1 += uU * (wx[c1] * gy[c2] * wz[c3]);
-        g2 += uU * (wx[c1] * wy[c2] * gz[c3]);
+        sw += wx[c1] * uU;
+        sg += gx[c1] * uU;
       }
+      g0 += (wy[c2] * wz[c3]) * sg;
+      g1 += (gy[c2] * wz[c3]) * sw;
+      g2 += (wy[c2] * gz[c3]) * sw;
     }
   }
   Xbar[q] = xb0 + g0 / h;
@@ -293,23 +301,34 @@ __global__ __launch_bounds__(256) void k_adj_spread(const uint32_t *__restrict__
   dphi4<double>(r0, gx);
   dphi4<double>(r1, gy);
   dphi4<double>(r2, gz);
+  // separable sums: per x row against the x weight and its derivative, then
+  // the rows against the y and z factors
   double a0 = 0, a1 = 0, a2 = 0, g0 = 0, g1 = 0, g2 = 0;
+#pragma unroll
   for (int c3 = 0; c3 < 4; c3++) {
     const int64_t zo = (int64_t)wrap_cell(cc.z + c3 - 1, nz) << (2 * log2n);
+#pragma unroll
     for (int c2 = 0; c2 < 4; c2++) {
       const int64_t yo = zo + ((int64_t)((cc.y + c2 - 1) & mask) << log2n);
+      double s0 = 0, s1 = 0, s2 = 0, sf = 0, sg = 0;
+#pragma unroll
       for (int c1 = 0; c1 < 4; c1++) {
         const int64_t p = yo + ((cc.x + c1 - 1) & mask);
         const double b0 = ub[p], b1 = ub[G + p], b2 = ub[2 * G + p];
-        const double wt = (wx[c1] * wy[c2]) * wz[c3];
-        a0 += b0 * wt;
-        a1 += b1 * wt;
-        a2 += b2 * wt;
         const double Ff = b0 * f0 + b1 * f1 + b2 * f2;
-        g0 += Ff * (gx[c1] * wy[c2] * wz[c3]);
-        g1 += Ff * (wx[c1] * gy[c2] * wz[c3]);
-        g2 += Ff * (wx[c1] * wy[c2] * gz[c3]);
+        s0 += wx[c1] * b0;
+        s1 += wx[c1] * b1;
+        s2 += wx[c1] * b2;
+        sf += wx[c1] * Ff;
+        sg += gx[c1] * Ff;
       }
+      const double wyz = wy[c2] * wz[c3];
+      a0 += wyz * s0;
+      a1 += wyz * s1;
+      a2 += wyz * s2;
+      g0 += wyz * sg;
+      g1 += (gy[c2] * wz[c3]) * sf;
+      g2 += (wy[c2] * gz[c3]) * sf;
     }
   }
   fbar[q] = scale * a0;
