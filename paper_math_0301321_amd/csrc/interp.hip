@@ -213,63 +213,128 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const int32_t *__rest
   }
 }
 
+// ------------------------------------------------- adjoint gathers ----
+// Both adjoint gathers take the work items like k_interp: a block stages the
+// grid field on the item's tile halo in LDS (three components per node),
+// then each thread takes one of the item's sorted markers at a time and sums
+// its 4^3 stencil from LDS.  The sums are separable: per x row against the x
+// weight and its derivative, then the rows against the y and z factors.  A
+// tile that fits one block round is taken whole by its first item's block.
+template <typename T, typename Body>
+__device__ __forceinline__ void adj_items(U4<T> *uh, const int32_t *__restrict__ tile_start,
+                                          const int32_t *__restrict__ tile_item0,
+                                          const int32_t *__restrict__ item_tile, int chunk, int W,
+                                          const T *__restrict__ g, int n, int nz, int log2nt, Body body) {
+  const int tid = threadIdx.x;
+  const int mask = n - 1, tmask = (1 << log2nt) - 1;
+  const int64_t G = (int64_t)n * n * nz;
+  constexpr int kPer = (kHalo3 + kInterpThreads - 1) / kInterpThreads;
+  for (int item = xcd_runs<16>(blockIdx.x, gridDim.x); item < W; item += gridDim.x) {
+    const int tile = item_tile[item];
+    int j0, j1;
+    item_range(item, tile_start, tile_item0, item_tile, chunk, &j0, &j1);
+    {
+      const int ts = tile_start[tile], te = tile_start[tile + 1];
+      if (te - ts <= kInterpThreads * kInterpPer) {
+        if (item != tile_item0[tile]) continue;
+        j0 = ts;
+        j1 = te;
+      }
+    }
+    const int x0 = 8 * (tile & tmask) - 1, y0 = 8 * ((tile >> log2nt) & tmask) - 1, z0 = 8 * (tile >> (2 * log2nt)) - 1;
+    T hv[kPer][3];
+#pragma unroll
+    for (int i = 0; i < kPer; i++) {   // every load issued (indices clamped) before the stores
+      const int e = min(tid + kInterpThreads * i, kHalo3 - 1);
+      const int hz = e / (kHalo * kHalo), r = e - hz * (kHalo * kHalo), hy = r / kHalo, hx = r - hy * kHalo;
+      const int64_t p = ((int64_t)wrap_cell(z0 + hz, nz) * n + ((y0 + hy) & mask)) * n + ((x0 + hx) & mask);
+      hv[i][0] = g[p];
+      hv[i][1] = g[G + p];
+      hv[i][2] = g[2 * G + p];
+    }
+    __syncthreads();   // the previous item's reads of the halo are done
+#pragma unroll
+    for (int i = 0; i < kPer; i++) {
+      const int e = tid + kInterpThreads * i;
+      if (e < kHalo3) {
+        U4<T> v;
+        v.x = hv[i][0];
+        v.y = hv[i][1];
+        v.z = hv[i][2];
+        v.pad = T(0);
+        uh[e] = v;
+      }
+    }
+    __syncthreads();
+    for (int j = j0 + tid; j < j1; j += kInterpThreads) body(j);
+  }
+}
+
+// Weights and their derivatives of one marker (FP64, from its FP64 position).
+struct StencilW {
+  double wx[4], wy[4], wz[4], gx[4], gy[4], gz[4];
+};
+__device__ __forceinline__ StencilW stencil_w(const double *__restrict__ X, const double *__restrict__ Y, int64_t M,
+                                              int64_t q, double h) {
+  StencilW s;
+  const double f0 = frac_of(pos_of(X, Y, q), h), f1 = frac_of(pos_of(X, Y, M + q), h),
+               f2 = frac_of(pos_of(X, Y, 2 * M + q), h);
+  phi4<double>(f0, s.wx);
+  phi4<double>(f1, s.wy);
+  phi4<double>(f2, s.wz);
+  dphi4<double>(f0, s.gx);
+  dphi4<double>(f1, s.gy);
+  dphi4<double>(f2, s.gz);
+  return s;
+}
+
 // Adjoint of the interpolation and move.  With Ubar = dt Xbar (Xbar at n+1):
 //   Xbar_q += sum_x (u^{n+1}(x) . Ubar_q) dPhi_q/dX_q      (phi' term)
 // and Ubar is staged (sorted order, fluid precision) for the transpose of
 // interpolation, a spread without the 1/h^3 factor.
 // The gather is in FP64 (weights from the FP64 position X^n, as in k_interp).
 template <typename T>
-__global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__ keys,
-                                                    const int32_t *__restrict__ perm, Rec<T> *__restrict__ recs,
-                                                    const T *__restrict__ u, int n, int nz, int log2n, int log2nt,
-                                                    int64_t M, double h, double dt, const double *__restrict__ X,
-                                                    const double *__restrict__ Y, double *__restrict__ Xbar) {
-  const int64_t i = gtid();
-  if (i >= M) return;
-  const int mask = n - 1;
-  const int64_t G = (int64_t)nz << (2 * log2n);
-  const Cell cc = key_cell(keys[i], log2nt);
-  const int64_t q = perm[i];
-  const double xb0 = Xbar[q], xb1 = Xbar[M + q], xb2 = Xbar[2 * M + q];
-  const double ub0 = dt * xb0, ub1 = dt * xb1, ub2 = dt * xb2;
-  // stage Ubar as the record's force: the transpose of interpolation is a spread
-  recs[i].F[0] = (T)ub0;
-  recs[i].F[1] = (T)ub1;
-  recs[i].F[2] = (T)ub2;
-  const double f0 = frac_of(pos_of(X, Y, q), h), f1 = frac_of(pos_of(X, Y, M + q), h),
-               f2 = frac_of(pos_of(X, Y, 2 * M + q), h);
-  double wx[4], wy[4], wz[4], gx[4], gy[4], gz[4];
-  phi4<double>(f0, wx);
-  phi4<double>(f1, wy);
-  phi4<double>(f2, wz);
-  dphi4<double>(f0, gx);
-  dphi4<double>(f1, gy);
-  dphi4<double>(f2, gz);
-  // the stencil sums are separable: per x row the sums of u.Ubar against the
-  // x weight and its derivative, then the rows against the y and z factors
-  double g0 = 0, g1 = 0, g2 = 0;
+__global__ __launch_bounds__(kInterpThreads) void k_adj_interp(
+    const int32_t *__restrict__ tile_start, const int32_t *__restrict__ tile_item0,
+    const int32_t *__restrict__ item_tile, int chunk, const int32_t *__restrict__ counts,
+    const uint32_t *__restrict__ keys, const int32_t *__restrict__ perm, Rec<T> *__restrict__ recs,
+    const T *__restrict__ u, int n, int nz, int log2nt, int64_t M, double h, double dt,
+    const double *__restrict__ X, const double *__restrict__ Y, double *__restrict__ Xbar) {
+  __shared__ U4<T> uh[kHalo3];
+  adj_items<T>(uh, tile_start, tile_item0, item_tile, chunk, counts[0], u, n, nz, log2nt, [&](int j) {
+    const uint32_t key = keys[j];
+    const int64_t q = perm[j];
+    const double xb0 = Xbar[q], xb1 = Xbar[M + q], xb2 = Xbar[2 * M + q];
+    const double ub0 = dt * xb0, ub1 = dt * xb1, ub2 = dt * xb2;
+    // stage Ubar as the record's force: the transpose of interpolation is a spread
+    recs[j].F[0] = (T)ub0;
+    recs[j].F[1] = (T)ub1;
+    recs[j].F[2] = (T)ub2;
+    const StencilW w = stencil_w(X, Y, M, q, h);
+    const int base = halo_base(key);
+    double g0 = 0, g1 = 0, g2 = 0;
 #pragma unroll
-  for (int c3 = 0; c3 < 4; c3++) {
-    const int64_t zo = (int64_t)wrap_cell(cc.z + c3 - 1, nz) << (2 * log2n);
+    for (int c3 = 0; c3 < 4; c3++) {
 #pragma unroll
-    for (int c2 = 0; c2 < 4; c2++) {
-      const int64_t yo = zo + ((int64_t)((cc.y + c2 - 1) & mask) << log2n);
-      double sw = 0, sg = 0;
+      for (int c2 = 0; c2 < 4; c2++) {
+        const int row = base + c3 * (kHalo * kHalo) + c2 * kHalo;
+        double sw = 0, sg = 0;
 #pragma unroll
-      for (int c1 = 0; c1 < 4; c1++) {
-        const int64_t p = yo + ((cc.x + c1 - 1) & mask);
-        const double uU = (double)u[p] * ub0 + (double)u[G + p] * ub1 + (double)u[2 * G + p] * ub2;
-        sw += wx[c1] * uU;
-        sg += gx[c1] * uU;
+        for (int c1 = 0; c1 < 4; c1++) {
+          const U4<T> v = uh[row + c1];
+          const double uU = (double)v.x * ub0 + (double)v.y * ub1 + (double)v.z * ub2;
+          sw += w.wx[c1] * uU;
+          sg += w.gx[c1] * uU;
+        }
+        g0 += (w.wy[c2] * w.wz[c3]) * sg;
+        g1 += (w.gy[c2] * w.wz[c3]) * sw;
+        g2 += (w.wy[c2] * w.gz[c3]) * sw;
       }
-      g0 += (wy[c2] * wz[c3]) * sg;
-      g1 += (gy[c2] * wz[c3]) * sw;
-      g2 += (wy[c2] * gz[c3]) * sw;
     }
-  }
-  Xbar[q] = xb0 + g0 / h;
-  Xbar[M + q] = xb1 + g1 / h;
-  Xbar[2 * M + q] = xb2 + g2 / h;
+    Xbar[q] = xb0 + g0 / h;
+    Xbar[M + q] = xb1 + g1 / h;
+    Xbar[2 * M + q] = xb2 + g2 / h;
+  });
 }
 
 // Adjoint of the spreading, with Fbar = scale_F * ubar^n (scale_F = dt/rho):
@@ -279,64 +344,54 @@ __global__ __launch_bounds__(256) void k_adj_interp(const uint32_t *__restrict__
 // fbar feeds the elastic Hessian, whose stretch and bend parts difference it
 // across neighbouring markers.
 template <typename T>
-__global__ __launch_bounds__(256) void k_adj_spread(const uint32_t *__restrict__ keys,
-                                                    const int32_t *__restrict__ perm, const T *__restrict__ ub,
-                                                    const double *__restrict__ F, int n, int nz, int log2n,
-                                                    int log2nt, int64_t M, double scale, double h,
-                                                    const double *__restrict__ X, const double *__restrict__ Y,
-                                                    double *__restrict__ Xbar, double *__restrict__ fbar) {
-  const int64_t i = gtid();
-  if (i >= M) return;
-  const int mask = n - 1;
-  const int64_t G = (int64_t)nz << (2 * log2n);
-  const Cell cc = key_cell(keys[i], log2nt);
-  const int64_t q = perm[i];
-  const double f0 = F[q], f1 = F[M + q], f2 = F[2 * M + q];
-  const double r0 = frac_of(pos_of(X, Y, q), h), r1 = frac_of(pos_of(X, Y, M + q), h),
-               r2 = frac_of(pos_of(X, Y, 2 * M + q), h);
-  double wx[4], wy[4], wz[4], gx[4], gy[4], gz[4];
-  phi4<double>(r0, wx);
-  phi4<double>(r1, wy);
-  phi4<double>(r2, wz);
-  dphi4<double>(r0, gx);
-  dphi4<double>(r1, gy);
-  dphi4<double>(r2, gz);
-  // separable sums: per x row against the x weight and its derivative, then
-  // the rows against the y and z factors
-  double a0 = 0, a1 = 0, a2 = 0, g0 = 0, g1 = 0, g2 = 0;
+__global__ __launch_bounds__(kInterpThreads) void k_adj_spread(
+    const int32_t *__restrict__ tile_start, const int32_t *__restrict__ tile_item0,
+    const int32_t *__restrict__ item_tile, int chunk, const int32_t *__restrict__ counts,
+    const uint32_t *__restrict__ keys, const int32_t *__restrict__ perm, const T *__restrict__ ub,
+    const double *__restrict__ F, int n, int nz, int log2nt, int64_t M, double scale, double h,
+    const double *__restrict__ X, const double *__restrict__ Y, double *__restrict__ Xbar,
+    double *__restrict__ fbar) {
+  __shared__ U4<T> uh[kHalo3];
+  adj_items<T>(uh, tile_start, tile_item0, item_tile, chunk, counts[0], ub, n, nz, log2nt, [&](int j) {
+    const uint32_t key = keys[j];
+    const int64_t q = perm[j];
+    const double f0 = F[q], f1 = F[M + q], f2 = F[2 * M + q];
+    const StencilW w = stencil_w(X, Y, M, q, h);
+    const int base = halo_base(key);
+    double a0 = 0, a1 = 0, a2 = 0, g0 = 0, g1 = 0, g2 = 0;
 #pragma unroll
-  for (int c3 = 0; c3 < 4; c3++) {
-    const int64_t zo = (int64_t)wrap_cell(cc.z + c3 - 1, nz) << (2 * log2n);
+    for (int c3 = 0; c3 < 4; c3++) {
 #pragma unroll
-    for (int c2 = 0; c2 < 4; c2++) {
-      const int64_t yo = zo + ((int64_t)((cc.y + c2 - 1) & mask) << log2n);
-      double s0 = 0, s1 = 0, s2 = 0, sf = 0, sg = 0;
+      for (int c2 = 0; c2 < 4; c2++) {
+        const int row = base + c3 * (kHalo * kHalo) + c2 * kHalo;
+        double s0 = 0, s1 = 0, s2 = 0, sf = 0, sg = 0;
 #pragma unroll
-      for (int c1 = 0; c1 < 4; c1++) {
-        const int64_t p = yo + ((cc.x + c1 - 1) & mask);
-        const double b0 = ub[p], b1 = ub[G + p], b2 = ub[2 * G + p];
-        const double Ff = b0 * f0 + b1 * f1 + b2 * f2;
-        s0 += wx[c1] * b0;
-        s1 += wx[c1] * b1;
-        s2 += wx[c1] * b2;
-        sf += wx[c1] * Ff;
-        sg += gx[c1] * Ff;
+        for (int c1 = 0; c1 < 4; c1++) {
+          const U4<T> v = uh[row + c1];
+          const double b0 = v.x, b1 = v.y, b2 = v.z;
+          const double Ff = b0 * f0 + b1 * f1 + b2 * f2;
+          s0 += w.wx[c1] * b0;
+          s1 += w.wx[c1] * b1;
+          s2 += w.wx[c1] * b2;
+          sf += w.wx[c1] * Ff;
+          sg += w.gx[c1] * Ff;
+        }
+        const double wyz = w.wy[c2] * w.wz[c3];
+        a0 += wyz * s0;
+        a1 += wyz * s1;
+        a2 += wyz * s2;
+        g0 += wyz * sg;
+        g1 += (w.gy[c2] * w.wz[c3]) * sf;
+        g2 += (w.wy[c2] * w.gz[c3]) * sf;
       }
-      const double wyz = wy[c2] * wz[c3];
-      a0 += wyz * s0;
-      a1 += wyz * s1;
-      a2 += wyz * s2;
-      g0 += wyz * sg;
-      g1 += (gy[c2] * wz[c3]) * sf;
-      g2 += (wy[c2] * gz[c3]) * sf;
     }
-  }
-  fbar[q] = scale * a0;
-  fbar[M + q] = scale * a1;
-  fbar[2 * M + q] = scale * a2;
-  Xbar[q] += scale * g0 / h;
-  Xbar[M + q] += scale * g1 / h;
-  Xbar[2 * M + q] += scale * g2 / h;
+    fbar[q] = scale * a0;
+    fbar[M + q] = scale * a1;
+    fbar[2 * M + q] = scale * a2;
+    Xbar[q] += scale * g0 / h;
+    Xbar[M + q] += scale * g1 / h;
+    Xbar[2 * M + q] += scale * g2 / h;
+  });
 }
 
 template <typename T>
@@ -361,10 +416,11 @@ template <typename T>
 hipError_t launch_adj_interp(ib_ctx *c, const T *u_np1, const double *X_n, double *Xbar) {
   if (c->M == 0) return hipSuccess;
   PhaseScope ps(c, PH_ADJ_INTERP);
-  hipLaunchKernelGGL(k_adj_interp<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
-                     c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], (Rec<T> *)c->ws.recs, u_np1, c->n,
-                     c->nz, c->log2n, c->log2nt, c->M, c->h, c->p.dt, X_n, c->mat.disp ? c->mat.X_ref : nullptr,
-                     Xbar);
+  const int grid = (int)std::min<int64_t>(c->item_cap, (int64_t)c->ncu * 16);   // as k_interp
+  hipLaunchKernelGGL(k_adj_interp<T>, dim3(grid), dim3(kInterpThreads), 0, c->stream, c->ws.tile_start,
+                     c->ws.tile_item0, c->ws.item_tile, c->chunk, c->ws.nitems, c->ws.keys[c->sorted_buf],
+                     c->ws.vals[c->sorted_buf], (Rec<T> *)c->ws.recs, u_np1, c->n, c->nz, c->log2nt, c->M, c->h,
+                     c->p.dt, X_n, c->mat.disp ? c->mat.X_ref : nullptr, Xbar);
   return hipGetLastError();
 }
 
@@ -374,9 +430,11 @@ hipError_t launch_adj_spread(ib_ctx *c, const T *ubar_n, const double *F, const 
   if (c->M == 0) return hipSuccess;
   PhaseScope ps(c, PH_ADJ_SPREAD);
   const double scale = (c->p.dt / c->p.rho) / (c->h * c->h * c->h);
-  hipLaunchKernelGGL(k_adj_spread<T>, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream,
-                     c->ws.keys[c->sorted_buf], c->ws.vals[c->sorted_buf], ubar_n, F, c->n, c->nz, c->log2n,
-                     c->log2nt, c->M, scale, c->h, X_n, c->mat.disp ? c->mat.X_ref : nullptr, Xbar, fbar);
+  const int grid = (int)std::min<int64_t>(c->item_cap, (int64_t)c->ncu * 16);   // as k_interp
+  hipLaunchKernelGGL(k_adj_spread<T>, dim3(grid), dim3(kInterpThreads), 0, c->stream, c->ws.tile_start,
+                     c->ws.tile_item0, c->ws.item_tile, c->chunk, c->ws.nitems, c->ws.keys[c->sorted_buf],
+                     c->ws.vals[c->sorted_buf], ubar_n, F, c->n, c->nz, c->log2nt, c->M, scale, c->h, X_n,
+                     c->mat.disp ? c->mat.X_ref : nullptr, Xbar, fbar);
   return hipGetLastError();
 }
 
