@@ -402,30 +402,113 @@ __device__ __forceinline__ double edge_adj(const Material &m, const double *__re
   return -(Kup * ext / len) * dd;
 }
 
-// Bend triple (a, c, b): adds the triple's part of (H fbar)_q (role 1: q is the
-// centre) and returns, for the centre, (unit-k_c triple force) . fbar.
-__device__ __forceinline__ double bend_adj(const Material &m, const double *__restrict__ X,
-                                           const double *__restrict__ fb, int64_t a, int64_t c, int64_t b,
-                                           int role, double Kb, V3 &hv) {
+// The lattice part of (H fbar)_q and of kbar_q, as the forward kernel forms
+// the force: the neighbours' states, cotangents and multipliers read once
+// (offsets -2 .. 2 along each direction), the rest lengths, stiffness
+// scales and reference second differences from the lattice constants.
+template <bool DISP>
+__device__ void lattice_hessvec(const Material &m, const LatticeDev &L, const double *__restrict__ X,
+                                const double *__restrict__ fb, int64_t q, V3 &hv, double &kb) {
   const int64_t M = m.M;
-  const V3 ya = ld3(m.X_ref, M, a), yb = ld3(m.X_ref, M, b), yc = ld3(m.X_ref, M, c);
-  const V3 e1{yc.x - ya.x, yc.y - ya.y, yc.z - ya.z}, e2{yb.x - yc.x, yb.y - yc.y, yb.z - yc.z};
-  const double Lc = 0.5 * (nrm(e1) + nrm(e2));
-  const double K1 = Kb * m.w[c] / (Lc * Lc * Lc * Lc);
-  const double K = K1 * m.k[c];
-  const V3 va = ld3(fb, M, a), vb = ld3(fb, M, b), vc = ld3(fb, M, c);
-  const V3 z{va.x - 2.0 * vc.x + vb.x, va.y - 2.0 * vc.y + vb.y, va.z - 2.0 * vc.z + vb.z};
-  const double s = role ? -2.0 * K : K;
-  hv.x += s * z.x;
-  hv.y += s * z.y;
-  hv.z += s * z.z;
-  if (!role) return 0.0;
-  const V3 xa = ld3(X, M, a), xb = ld3(X, M, b), xc = ld3(X, M, c);
-  const V3 dx = second_diff(xa, xc, xb), dy = second_diff(ya, yc, yb);
-  const V3 v = m.disp ? dx : V3{dx.x - dy.x, dx.y - dy.y, dx.z - dy.z};   // displacements: Da - 2Dc + Db
-  return -K1 * (v.x * z.x + v.y * z.y + v.z * z.z);
+  const double *P = m.lat_pre;
+  const int64_t rel = q - L.first;
+  const int64_t n1 = L.n1, n2 = L.n2;
+  const int64_t i1 = rel % n1, i2 = rel / n1;
+  const bool per = L.periodic2 != 0;
+  auto idx = [&](int64_t a1, int64_t a2) { return L.first + a2 * n1 + a1; };
+  auto w2 = [&](int64_t a2) { return per ? (a2 + n2) % n2 : a2; };
+  const bool has_dn = per || i2 > 0, has_up = per || i2 < n2 - 1;
+  if (L.Ks == 0.0 && L.Kb == 0.0) return;
+  const int64_t q1m = idx(i1 - 1, i2), q1p = idx(i1 + 1, i2), q2m = idx(i1, w2(i2 - 1)), q2p = idx(i1, w2(i2 + 1));
+  const V3 xq = ld3(X, M, q), vq = ld3(fb, M, q);
+  const double kq = m.k[q];
+  V3 x1m{}, x1p{}, x2m{}, x2p{}, v1m{}, v1p{}, v2m{}, v2p{};
+  double k1m = 0.0, k1p = 0.0, k2m = 0.0, k2p = 0.0;
+  if (i1 > 0) { x1m = ld3(X, M, q1m); v1m = ld3(fb, M, q1m); k1m = m.k[q1m]; }
+  if (i1 < n1 - 1) { x1p = ld3(X, M, q1p); v1p = ld3(fb, M, q1p); k1p = m.k[q1p]; }
+  if (has_dn) { x2m = ld3(X, M, q2m); v2m = ld3(fb, M, q2m); k2m = m.k[q2m]; }
+  if (has_up) { x2p = ld3(X, M, q2p); v2p = ld3(fb, M, q2p); k2p = m.k[q2p]; }
+  if (L.Ks != 0.0) {
+    V3 yq{}, y1m{}, y1p{}, y2m{}, y2p{};
+    if (DISP) {
+      yq = ld3(m.X_ref, M, q);
+      if (i1 > 0) y1m = ld3(m.X_ref, M, q1m);
+      if (i1 < n1 - 1) y1p = ld3(m.X_ref, M, q1p);
+      if (has_dn) y2m = ld3(m.X_ref, M, q2m);
+      if (has_up) y2p = ld3(m.X_ref, M, q2p);
+    }
+    // edge (q, o): energy 1/2 ke kf (|d| - le)^2, ke = Ks w / le^2, kf the mean multiplier
+    auto edge = [&](const V3 &xo, const V3 &yo, const V3 &vo, double ko, double le, double ke) {
+      const V3 d = edge_vec<DISP>(xq, xo, yq, yo);
+      const V3 dv{vo.x - vq.x, vo.y - vq.y, vo.z - vq.z};
+      const double len = nrm(d);
+      const double ext = extension<DISP>(xq, xo, yq, yo, len, le);
+      const double Kp = ke * (0.5 * (kq + ko));
+      const double dd = d.x * dv.x + d.y * dv.y + d.z * dv.z;
+      const double a = ext / len, b = (le / (len * len * len)) * dd;
+      hv.x -= Kp * (a * dv.x + b * d.x);
+      hv.y -= Kp * (a * dv.y + b * d.y);
+      hv.z -= Kp * (a * dv.z + b * d.z);
+      kb += 0.5 * (-(ke * ext / len) * dd);
+    };
+    if (i1 > 0) edge(x1m, y1m, v1m, k1m, P[q1m], P[M + q1m]);
+    if (i1 < n1 - 1) edge(x1p, y1p, v1p, k1p, P[q], P[M + q]);
+    if (has_dn) edge(x2m, y2m, v2m, k2m, P[2 * M + q2m], P[3 * M + q2m]);
+    if (has_up) edge(x2p, y2p, v2p, k2p, P[2 * M + q], P[3 * M + q]);
+  }
+  if (L.Kb != 0.0) {
+    const double *C1 = P + 4 * M, *C2 = P + 5 * M, *D1 = P + 6 * M, *D2 = P + 9 * M;
+    // triple (a, c, b): z = fbar_a - 2 fbar_c + fbar_b; K = cb k_c with cb = Kb w_c / Lc^4;
+    // q at an end adds K z, q the centre adds -2 K z and kbar_q gets -cb (v . z),
+    // v the second difference of the state less the reference one
+    auto zdiff = [](const V3 &a, const V3 &c, const V3 &b) {
+      return V3{a.x - 2.0 * c.x + b.x, a.y - 2.0 * c.y + b.y, a.z - 2.0 * c.z + b.z};
+    };
+    auto end = [&](const V3 &z, double cb, double kc) {
+      const double K = cb * kc;
+      hv.x += K * z.x;
+      hv.y += K * z.y;
+      hv.z += K * z.z;
+    };
+    auto centre = [&](const V3 &z, double cb, const V3 &xa, const V3 &xb, const double *d2) {
+      const double K = cb * kq;
+      hv.x += -2.0 * K * z.x;
+      hv.y += -2.0 * K * z.y;
+      hv.z += -2.0 * K * z.z;
+      const V3 dx = second_diff(xa, xq, xb);
+      V3 v = dx;                                   // with displacements: Da - 2Dq + Db
+      if (!DISP) {
+        const V3 y2 = ld3(d2, M, q);
+        v = V3{dx.x - y2.x, dx.y - y2.y, dx.z - y2.z};
+      }
+      kb += -cb * (v.x * z.x + v.y * z.y + v.z * z.z);
+    };
+    // direction 1: centres 1 .. n1-2
+    {
+      const bool b0 = i1 >= 1 && i1 <= n1 - 2, bp = i1 + 1 <= n1 - 2, bm = i1 - 1 >= 1;
+      V3 vm2{}, vp2{};
+      if (bm) vm2 = ld3(fb, M, idx(i1 - 2, i2));
+      if (bp) vp2 = ld3(fb, M, idx(i1 + 2, i2));
+      if (b0) centre(zdiff(v1m, vq, v1p), C1[q], x1m, x1p, D1);
+      if (bp) end(zdiff(vq, v1p, vp2), C1[q1p], k1p);
+      if (bm) end(zdiff(vm2, v1m, vq), C1[q1m], k1m);
+    }
+    // direction 2: centres 1 .. n2-2, or every row when periodic
+    {
+      auto centre_ok = [&](int64_t c2) { return per || (c2 >= 1 && c2 <= n2 - 2); };
+      const bool b0 = centre_ok(i2), bp = (per || i2 + 1 < n2) && centre_ok(i2 + 1),
+                 bm = (per || i2 - 1 >= 0) && centre_ok(i2 - 1);
+      V3 vm2{}, vp2{};
+      if (bm) vm2 = ld3(fb, M, idx(i1, w2(i2 - 2)));
+      if (bp) vp2 = ld3(fb, M, idx(i1, w2(i2 + 2)));
+      if (b0) centre(zdiff(v2m, vq, v2p), C2[q], x2m, x2p, D2);
+      if (bp) end(zdiff(vq, v2p, vp2), C2[q2p], k2p);
+      if (bm) end(zdiff(vm2, v2m, vq), C2[q2m], k2m);
+    }
+  }
 }
 
+template <bool DISP>
 __global__ __launch_bounds__(256) void k_hessvec(Material m, const double *__restrict__ X,
                                                  const double *__restrict__ fb, double *__restrict__ Xbar,
                                                  double *__restrict__ kbar) {
@@ -436,37 +519,10 @@ __global__ __launch_bounds__(256) void k_hessvec(Material m, const double *__res
   double kb = 0.0;
   for (int l = 0; l < m.lat.n; l++) {
     const LatticeDev &L = m.lat.l[l];
-    if (q < L.first || q >= L.first + (int64_t)L.n1 * L.n2) continue;
-    const int64_t rel = q - L.first, n1 = L.n1, n2 = L.n2;
-    const int64_t i1 = rel % n1, i2 = rel / n1;
-    const bool per = L.periodic2 != 0;
-    auto idx = [&](int64_t a1, int64_t a2) { return L.first + a2 * n1 + a1; };
-    auto w2 = [&](int64_t a2) { return per ? (a2 + n2) % n2 : a2; };
-    if (L.Ks != 0.0) {
-      auto edge = [&](int64_t o) {
-        const V3 yq = ld3(m.X_ref, M, q), yo = ld3(m.X_ref, M, o);
-        const V3 dy{yo.x - yq.x, yo.y - yq.y, yo.z - yq.z};
-        const double kf = 0.5 * (m.k[q] + m.k[o]);
-        const double wbar = 0.5 * (m.w[q] + m.w[o]);
-        kb += 0.5 * edge_adj(m, X, fb, M, q, o, L.Ks * wbar, kf, nrm(dy), true, hv);
-      };
-      if (i1 > 0) edge(idx(i1 - 1, i2));
-      if (i1 < n1 - 1) edge(idx(i1 + 1, i2));
-      if (per || i2 > 0) edge(idx(i1, w2(i2 - 1)));
-      if (per || i2 < n2 - 1) edge(idx(i1, w2(i2 + 1)));
+    if (q >= L.first && q < L.first + (int64_t)L.n1 * L.n2) {
+      lattice_hessvec<DISP>(m, L, X, fb, q, hv, kb);
+      break;
     }
-    if (L.Kb != 0.0) {
-      if (i1 >= 1 && i1 <= n1 - 2) kb += bend_adj(m, X, fb, idx(i1 - 1, i2), q, idx(i1 + 1, i2), 1, L.Kb, hv);
-      if (i1 + 1 <= n1 - 2) bend_adj(m, X, fb, q, idx(i1 + 1, i2), idx(i1 + 2, i2), 0, L.Kb, hv);
-      if (i1 - 1 >= 1) bend_adj(m, X, fb, idx(i1 - 2, i2), idx(i1 - 1, i2), q, 0, L.Kb, hv);
-      auto centre_ok = [&](int64_t c2) { return per || (c2 >= 1 && c2 <= n2 - 2); };
-      if (centre_ok(i2)) kb += bend_adj(m, X, fb, idx(i1, w2(i2 - 1)), q, idx(i1, w2(i2 + 1)), 1, L.Kb, hv);
-      if ((per || i2 + 1 < n2) && centre_ok(i2 + 1))
-        bend_adj(m, X, fb, q, idx(i1, w2(i2 + 1)), idx(i1, w2(i2 + 2)), 0, L.Kb, hv);
-      if ((per || i2 - 1 >= 0) && centre_ok(i2 - 1))
-        bend_adj(m, X, fb, idx(i1, w2(i2 - 2)), idx(i1, w2(i2 - 1)), q, 0, L.Kb, hv);
-    }
-    break;
   }
   if (m.sp_rowptr) {
     for (int32_t e = m.sp_rowptr[q]; e < m.sp_rowptr[q + 1]; e++) {
@@ -493,8 +549,8 @@ __global__ __launch_bounds__(256) void k_hessvec(Material m, const double *__res
 hipError_t launch_hessvec(ib_ctx *c, const double *X, const double *v, double *Xbar, double *kbar) {
   if (c->M == 0) return hipSuccess;
   PhaseScope ps(c, PH_HESSVEC);
-  hipLaunchKernelGGL(k_hessvec, dim3((unsigned)((c->M + 255) / 256)), dim3(256), 0, c->stream, c->mat, X, v, Xbar,
-                     kbar);
+  hipLaunchKernelGGL((c->mat.disp ? k_hessvec<true> : k_hessvec<false>), dim3((unsigned)((c->M + 255) / 256)),
+                     dim3(256), 0, c->stream, c->mat, X, v, Xbar, kbar);
   return hipGetLastError();
 }
 
