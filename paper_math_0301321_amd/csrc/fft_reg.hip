@@ -194,16 +194,21 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Copy a table of n values into LDS, the block's nthreads threads in turn
+// (the caller synchronises before the first read).  Table reads inside the
+// transforms and the solve then wait on LDS, not on the vector cache.
+template <typename V>
+__device__ __forceinline__ void stage_table(V *dst, const V *__restrict__ src, int n, int nthreads) {
+  for (int i = (int)threadIdx.x; i < n; i += nthreads) dst[i] = src[i];
+}
+
 // Four-step transform of one pencil of length N = R1 R2 by P = min(R1, R2) threads.
 //   in : v[i R1 + j]  = x[(t + P i) + R2 j],   i < R2/P, j < R1
 //   out: v[i R2 + k2] = X[(t + P i) + R1 k2],  i < R1/P, k2 < R2
 // xch: R1 (R2 + 1) LDS values private to the pencil.  BLOCK: the pencil's
 // threads span several waves (block barrier) instead of one (wave barrier).
 // tw holds exp(-2 pi i k / (TS N)); the transform reads it at stride TS.
-// FRESH_TW: the twiddles are read again in every call rather than kept in
-// registers from an earlier call (for kernels whose register budget is
-// taken by pencils held across calls).
-template <typename T, int R1, int R2, bool INV, bool BLOCK, int TS = 1, bool FRESH_TW = false>
+template <typename T, int R1, int R2, bool INV, bool BLOCK, int TS = 1>
 struct Fft4 {
   static constexpr int N = R1 * R2;
   static constexpr int P = R1 < R2 ? R1 : R2;
@@ -216,7 +221,6 @@ struct Fft4 {
   __device__ static __forceinline__ void run(cplx<T> *v, int t, cplx<T> *xch, const cplx<T> *__restrict__ tw) {
 #pragma unroll
     for (int i = 0; i < R2 / P; i++) dft_reg<T, R1, INV>(v + i * R1);
-    if constexpr (FRESH_TW) asm volatile("" : "+s"(tw));   // an opaque copy: loads through it are not reused
 #pragma unroll
     for (int i = 0; i < R2 / P; i++) {
       const int s = t + P * i;
@@ -341,6 +345,8 @@ __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf_rhs(
   static_assert(RUNS % GR == 0, "whole groups");
   __shared__ __attribute__((aligned(16))) unsigned char smem[SM::BYTES];
   T *us = (T *)smem;                                   // [3][HR][US] u, row y0 - 1 + lr
+  __shared__ cplx<T> tw_s[N];
+  stage_table(tw_s, tw, N, NT);   // read after the staging barrier
   const int nyb = N / YB;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int y0 = (b % nyb) * YB, z = b / nyb;
@@ -484,7 +490,7 @@ __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xf_rhs(
     }
   __syncthreads();   // the staged rows are dead; the buffer becomes pencil exchange space
   cplx<T> *xch = (cplx<T> *)smem + p * R1 * (R2 + 1);
-  F4::run(v, t, xch, tw);
+  F4::run(v, t, xch, tw_s);
   // spectra of the two real rows: A = (Z[k] + conj Z[-k]) / 2, B = (Z[k] - conj Z[-k]) / 2i
   wave_sync();
 #pragma unroll
@@ -527,6 +533,9 @@ __global__ __launch_bounds__(256) void k_y(cplx<T> *__restrict__ spec, int64_t n
   using F4 = Fft4<T, R1, R2, INV, false>;
   constexpr int N = R1 * R2, P = F4::P, E = F4::E, PPB = 256 / P;
   __shared__ cplx<T> xch[PPB * R1 * (R2 + 1)];
+  __shared__ cplx<T> tw_s[N];
+  stage_table(tw_s, tw, N, 256);
+  __syncthreads();
   const int lp = threadIdx.x / P, t = threadIdx.x % P;
   const int64_t pen = (int64_t)blockIdx.x * PPB + lp;
   if (pen >= npencils) return;       // whole pencils only: the exchange is wave-local
@@ -536,7 +545,7 @@ __global__ __launch_bounds__(256) void k_y(cplx<T> *__restrict__ spec, int64_t n
   for (int i = 0; i < R2 / P; i++)
 #pragma unroll
     for (int j = 0; j < R1; j++) v[i * R1 + j] = g[(t + P * i) + R2 * j];
-  F4::run(v, t, xch + lp * R1 * (R2 + 1), tw);
+  F4::run(v, t, xch + lp * R1 * (R2 + 1), tw_s);
 #pragma unroll
   for (int i = 0; i < R1 / P; i++)
 #pragma unroll
@@ -545,8 +554,8 @@ __global__ __launch_bounds__(256) void k_y(cplx<T> *__restrict__ spec, int64_t n
 
 // ------------------------------------------------- pass z with the solve ----
 // z transforms of length NZ = R1 R2 on a grid of NY x NY x NZ nodes (NZ = NY,
-// NY / 2 or 3 NY / 4) with the tables of length NZ (twz, lamz, sgz); the x and
-// y modes read the tables of length NY (lam, sg).
+// NY / 2 or 3 NY / 4) with the tables of length NZ (twz, lamz, sgz), which the
+// block stages in LDS; the x and y modes read the tables of length NY (lam, sg).
 template <typename T, int R1, int R2, int NY>
 __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ? 2 : 1) void k_z_solve(
     cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ twz, const T *__restrict__ lamz,
@@ -560,6 +569,12 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ?
   constexpr int XS0 = (R1 * (R2 + 1) > R2 * (R1 + 1)) ? R1 * (R2 + 1) : R2 * (R1 + 1);
   constexpr int XSZ = XS0 + ((2 - XS0 % 32) + 32) % 32;
   __shared__ cplx<T> xch[YB * XSZ];
+  __shared__ cplx<T> twz_s[NZ];
+  __shared__ T lamz_s[NZ], sgz_s[NZ];
+  stage_table(twz_s, twz, NZ, YB * P);
+  stage_table(lamz_s, lamz, NZ, YB * P);
+  stage_table(sgz_s, sgz, NZ, YB * P);
+  __syncthreads();
   const int nyb = NY / YB;
   const int kx = blockIdx.x / nyb, y0 = (blockIdx.x % nyb) * YB;
   const int yy = threadIdx.x % YB, t = threadIdx.x / YB;
@@ -576,7 +591,7 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ?
       for (int j = 0; j < R1; j++)
         v[c][i * R1 + j] = bload(rs, voff, c * cs + (uint32_t)((P * i + R2 * j) * NY) * CB, T(0));
 #pragma unroll
-  for (int c = 0; c < 3; c++) Ff::run(v[c], t, xch + yy * XSZ, twz);
+  for (int c = 0; c < 3; c++) Ff::run(v[c], t, xch + yy * XSZ, twz_s);
   // per mode (kx, ky, kz): w = r^/(1 + nu dt lambda), then remove the s-component
   const int ky = y0 + yy;
   const T lxy = lam[kx] + lam[ky];
@@ -587,8 +602,8 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ?
     for (int k2 = 0; k2 < R2; k2++) {
       const int e = i * R2 + k2;
       const int kz = (t + P * i) + R1 * k2;
-      const T rden = recip(T(1) + nu_dt * (lxy + lamz[kz]));
-      const T s2 = sgz[kz];
+      const T rden = recip(T(1) + nu_dt * (lxy + lamz_s[kz]));
+      const T s2 = sgz_s[kz];
       cplx<T> w0{v[0][e].x * rden, v[0][e].y * rden};
       cplx<T> w1{v[1][e].x * rden, v[1][e].y * rden};
       cplx<T> w2{v[2][e].x * rden, v[2][e].y * rden};
@@ -607,7 +622,7 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ?
     }
   }
 #pragma unroll
-  for (int c = 0; c < 3; c++) Fi::run(v[c], t, xch + yy * XSZ, twz);
+  for (int c = 0; c < 3; c++) Fi::run(v[c], t, xch + yy * XSZ, twz_s);
 #pragma unroll
   for (int c = 0; c < 3; c++)
 #pragma unroll
@@ -631,6 +646,8 @@ __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xi(
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int y0 = (b % nyb) * YB, z = b / nyb;
   const int tid = threadIdx.x;
+  __shared__ cplx<T> tw_s[N];
+  stage_table(tw_s, tw, N, NT);   // read after the staging barrier
   {
     // 16-byte loads of the (c, kx) runs along y, all issued before the LDS stores
     using V = Vec16<T>;
@@ -675,7 +692,7 @@ __global__ __launch_bounds__(3 * YB / 2 * (R1 < R2 ? R1 : R2)) void k_xi(
       v[i * R1 + j] = cplx<T>{a.x - bb.y, a.y + bb.x};
     }
   __syncthreads();   // staging is dead; the buffer becomes pencil exchange space
-  F4::run(v, t, (cplx<T> *)smem + p * R1 * (R2 + 1), tw);
+  F4::run(v, t, (cplx<T> *)smem + p * R1 * (R2 + 1), tw_s);
   T *ra = u + c * G + ((int64_t)z * N + y0 + 2 * rp) * N;
 #pragma unroll
   for (int i = 0; i < R1 / P; i++)
@@ -712,10 +729,13 @@ template <typename T, int R1, int R2>
 __global__ __launch_bounds__(1024) void k_yxi(const cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ tw,
                                               T scale, T *__restrict__ u, int nz) {
   using C = YxiCfg<T, R1, R2>;
-  using F4 = Fft4<T, R1, R2, true, false, 1, true>;
+  using F4 = Fft4<T, R1, R2, true, false>;
   constexpr int N = C::N, NH = C::NH, P = C::P, E = F4::E, TS = C::TS;
   static_assert(R2 / P == 1 && R1 / P == 1, "square four-step factors");
   __shared__ __attribute__((aligned(16))) unsigned char smem[C::BYTES];
+  __shared__ cplx<T> tw_s[N];
+  stage_table(tw_s, tw, N, 1024);
+  __syncthreads();
   const int64_t G = (int64_t)N * N * nz;
   const int c = blockIdx.x / nz, z = blockIdx.x % nz;
   const int s = threadIdx.x / P, t = threadIdx.x % P;
@@ -730,7 +750,7 @@ __global__ __launch_bounds__(1024) void k_yxi(const cplx<T> *__restrict__ spec, 
     const cplx<T> *gn = pencil(N / 2);
 #pragma unroll
     for (int j = 0; j < R1; j++) vn[j] = gn[t + R2 * j];
-    F4::run(vn, t, xch, tw);
+    F4::run(vn, t, xch, tw_s);
 #pragma unroll
     for (int k2 = 0; k2 < R2; k2++) nyq[t + R1 * k2] = vn[k2];
   }
@@ -740,13 +760,13 @@ __global__ __launch_bounds__(1024) void k_yxi(const cplx<T> *__restrict__ spec, 
 #pragma unroll
     for (int j = 0; j < R1; j++) va[j] = ga[t + R2 * j];
   }
-  F4::run(va, t, xch, tw);                          // y = t + R1 k2 in slot k2
+  F4::run(va, t, xch, tw_s);                          // y = t + R1 k2 in slot k2
   {
     const cplx<T> *gb = pencil(s + C::SLOTS);
 #pragma unroll
     for (int j = 0; j < R1; j++) vb[j] = gb[t + R2 * j];
   }
-  F4::run(vb, t, xch, tw);
+  F4::run(vb, t, xch, tw_s);
   // 2. per half of the rows: transpose to [y][kx], inverse x transforms of
   // row pairs (2r, 2r + 1), r = s, and the rows written out
 #pragma unroll
@@ -778,7 +798,7 @@ __global__ __launch_bounds__(1024) void k_yxi(const cplx<T> *__restrict__ spec, 
       v[j] = cplx<T>{a.x - b.y, a.y + b.x};
     }
     __syncthreads();   // the transpose is consumed: its space becomes exchange space
-    F4::run(v, tt, xch, tw);
+    F4::run(v, tt, xch, tw_s);
     T *ra = u + c * G + ((int64_t)z * N + h * C::HALF + r0) * N;
 #pragma unroll
     for (int k2 = 0; k2 < R2; k2++) {
