@@ -621,14 +621,16 @@ __global__ __launch_bounds__(XfCfg<T>::YB *(R1 < R2 ? R1 : R2), sizeof(T) == 4 ?
       v[2][e] = w2;
     }
   }
+  // each component stored as soon as it is transformed back, so that its
+  // stores drain while the next component's transform runs
 #pragma unroll
-  for (int c = 0; c < 3; c++) Fi::run(v[c], t, xch + yy * XSZ, twz_s);
-#pragma unroll
-  for (int c = 0; c < 3; c++)
+  for (int c = 0; c < 3; c++) {
+    Fi::run(v[c], t, xch + yy * XSZ, twz_s);
 #pragma unroll
     for (int i = 0; i < R2 / P; i++)
 #pragma unroll
       for (int j = 0; j < R1; j++) bstore(rs, voff, c * cs + (uint32_t)((P * i + R2 * j) * NY) * CB, v[c][i * R1 + j]);
+  }
 }
 
 // ------------------------------------------------------ pass x, inverse ----

@@ -280,27 +280,20 @@ __host__ __device__ constexpr int src_pos(int s) { return s < 2 ? s + 9 : (s < 1
 
 constexpr int kSrcPerLane = (kHalo3 + 63) / 64;   // 21
 
-// For each of the 11^3 sources of a tile: the neighbour index d27 = (dz + 1) 9
-// + (dy + 1) 3 + (dx + 1) and the position in that neighbour's halo.
-struct SrcTab {
-  uint16_t e[kSrcPerLane * 64];
-  uint8_t d[kSrcPerLane * 64];
-};
-constexpr SrcTab make_src_tab() {
-  SrcTab t{};
-  for (int s = 0; s < kSrcPerLane * 64; s++) {
-    if (s >= kHalo3) {
-      t.e[s] = 0;
-      t.d[s] = 13;
-      continue;
-    }
-    const int sz = s / (kHalo * kHalo), sy = (s / kHalo) % kHalo, sx = s % kHalo;
-    t.d[s] = (uint8_t)((src_off(sz) + 1) * 9 + (src_off(sy) + 1) * 3 + (src_off(sx) + 1));
-    t.e[s] = (uint16_t)((src_pos(sz) * kHalo + src_pos(sy)) * kHalo + src_pos(sx));
+// Source s of a tile's 11^3 sources (z, y, x = s / 121, (s / 11) % 11,
+// s % 11): the neighbour d27 = (dz + 1) 9 + (dy + 1) 3 + (dx + 1) whose halo
+// holds it and its position e there; the padding sources past 11^3 read
+// position 0 of the tile itself and are never summed.  Formed arithmetically:
+// a table lookup per source made the gather wait on 21 dependent loads per tile.
+__device__ __forceinline__ void src_of(int s, int &d27, int &e) {
+  const int sz = s / (kHalo * kHalo), r = s - sz * (kHalo * kHalo), sy = r / kHalo, sx = r - sy * kHalo;
+  d27 = (src_off(sz) + 1) * 9 + (src_off(sy) + 1) * 3 + (src_off(sx) + 1);
+  e = (src_pos(sz) * kHalo + src_pos(sy)) * kHalo + src_pos(sx);
+  if (s >= kHalo3) {
+    d27 = 13;
+    e = 0;
   }
-  return t;
 }
-__constant__ SrcTab kSrc = make_src_tab();
 
 // Waves take the touched tiles of the binning's list (four per block, round
 // robin).  For each component, every lane loads its share of the 11^3
@@ -344,8 +337,10 @@ __global__ __launch_bounds__(256) void k_spread_gather(const int32_t *__restrict
 #pragma unroll
     for (int i = 0; i < kSrcPerLane; i++) {
       const int sidx = lane + 64 * i;
-      const int b = __shfl(nb_base, kSrc.d[sidx], 64);
-      soff[i] = b >= 0 ? b + kSrc.e[sidx] : -1;
+      int d27, e;
+      src_of(sidx, d27, e);
+      const int b = __shfl(nb_base, d27, 64);
+      soff[i] = b >= 0 ? b + e : -1;
     }
     for (int c = 0; c < 3; c++) {
       T v[kSrcPerLane];
