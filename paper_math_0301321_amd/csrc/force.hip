@@ -515,6 +515,11 @@ __global__ __launch_bounds__(256) void k_hessvec(Material m, const double *__res
   const int64_t q = gtid();
   const int64_t M = m.M;
   if (q >= M) return;
+  // the values indexed by q alone, loaded together before the terms that use
+  // them (the tether sits behind branches; the outputs are read-modify-write)
+  const double kw = m.kappa ? m.kappa[q] * m.w[q] : 0.0;
+  const V3 fq = ld3(fb, M, q);
+  const double xb0 = Xbar[q], xb1 = Xbar[M + q], xb2 = Xbar[2 * M + q], kb0 = kbar[q];
   V3 hv{0.0, 0.0, 0.0};
   double kb = 0.0;
   for (int l = 0; l < m.lat.n; l++) {
@@ -531,19 +536,15 @@ __global__ __launch_bounds__(256) void k_hessvec(Material m, const double *__res
       kb += 0.5 * edge_adj(m, X, fb, M, q, o, m.K_spring, kf, m.sp_rest[e], false, hv);
     }
   }
-  if (m.kappa) {
-    const double kw = m.kappa[q] * m.w[q];
-    if (kw != 0.0) {
-      const V3 v = ld3(fb, M, q);
-      hv.x += kw * v.x;
-      hv.y += kw * v.y;
-      hv.z += kw * v.z;
-    }
+  if (kw != 0.0) {
+    hv.x += kw * fq.x;
+    hv.y += kw * fq.y;
+    hv.z += kw * fq.z;
   }
-  Xbar[q] -= hv.x;
-  Xbar[M + q] -= hv.y;
-  Xbar[2 * M + q] -= hv.z;
-  kbar[q] += kb;
+  Xbar[q] = xb0 - hv.x;
+  Xbar[M + q] = xb1 - hv.y;
+  Xbar[2 * M + q] = xb2 - hv.z;
+  kbar[q] = kb0 + kb;
 }
 
 hipError_t launch_hessvec(ib_ctx *c, const double *X, const double *v, double *Xbar, double *kbar) {

@@ -57,12 +57,6 @@ __device__ __forceinline__ double frac_of(double x, double h) {
   return s - floor(s);
 }
 
-// Position component i of the state X: X[i], or Y[i] + X[i] when the state
-// holds displacements from the reference shape Y.
-__device__ __forceinline__ double pos_of(const double *__restrict__ X, const double *__restrict__ Y, int64_t i) {
-  return Y ? Y[i] + X[i] : X[i];
-}
-
 // One marker at position x (its cell is the record's key): interpolate u from
 // the staged halo with FP64 weights, summing in FP64.
 template <typename T>
@@ -277,8 +271,14 @@ struct StencilW {
 __device__ __forceinline__ StencilW stencil_w(const double *__restrict__ X, const double *__restrict__ Y, int64_t M,
                                               int64_t q, double h) {
   StencilW s;
-  const double f0 = frac_of(pos_of(X, Y, q), h), f1 = frac_of(pos_of(X, Y, M + q), h),
-               f2 = frac_of(pos_of(X, Y, 2 * M + q), h);
+  double x0 = X[q], x1 = X[M + q], x2 = X[2 * M + q];
+  if (Y) {   // the position Y + D with displacements as the state: both loaded before either is used
+    const double y0 = Y[q], y1 = Y[M + q], y2 = Y[2 * M + q];
+    x0 = y0 + x0;
+    x1 = y1 + x1;
+    x2 = y2 + x2;
+  }
+  const double f0 = frac_of(x0, h), f1 = frac_of(x1, h), f2 = frac_of(x2, h);
   phi4<double>(f0, s.wx);
   phi4<double>(f1, s.wy);
   phi4<double>(f2, s.wz);
@@ -356,6 +356,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_adj_spread(
     const uint32_t key = keys[j];
     const int64_t q = perm[j];
     const double f0 = F[q], f1 = F[M + q], f2 = F[2 * M + q];
+    const double xb0 = Xbar[q], xb1 = Xbar[M + q], xb2 = Xbar[2 * M + q];   // read with the others
     const StencilW w = stencil_w(X, Y, M, q, h);
     const int base = halo_base(key);
     double a0 = 0, a1 = 0, a2 = 0, g0 = 0, g1 = 0, g2 = 0;
@@ -388,9 +389,9 @@ __global__ __launch_bounds__(kInterpThreads) void k_adj_spread(
     fbar[q] = scale * a0;
     fbar[M + q] = scale * a1;
     fbar[2 * M + q] = scale * a2;
-    Xbar[q] += scale * g0 / h;
-    Xbar[M + q] += scale * g1 / h;
-    Xbar[2 * M + q] += scale * g2 / h;
+    Xbar[q] = xb0 + scale * g0 / h;
+    Xbar[M + q] = xb1 + scale * g1 / h;
+    Xbar[2 * M + q] = xb2 + scale * g2 / h;
   });
 }
 
